@@ -1,0 +1,181 @@
+"""Brute-force oracle for tiny graphs -- TEST INFRASTRUCTURE ONLY.
+
+Everything here follows a definition directly, with no pruning:
+  * k-cliques: every k-subset, pairwise adjacent (Pangolin section 2.2).
+  * k-motifs: every k-subset whose induced subgraph is connected, grouped by
+    isomorphism class (sections 2.1-2.2, vertex-induced embeddings).
+  * FSM: for each labelled pattern with at most 3 edges, every injective,
+    label-preserving map of its vertices into the graph that sends pattern
+    edges to graph edges; the minimum-image (domain) support is the smallest
+    number of distinct images over the pattern's vertices (section 2.2).
+Use on graphs of about a dozen vertices.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+
+def dense_adj(g) -> np.ndarray:
+    A = np.zeros((g.n, g.n), dtype=bool)
+    for v in range(g.n):
+        A[v, g.adj(v)] = True
+    return A
+
+
+def clique_count(g, k: int) -> int:
+    A = dense_adj(g)
+    total = 0
+    for s in itertools.combinations(range(g.n), k):
+        if all(A[a, b] for a, b in itertools.combinations(s, 2)):
+            total += 1
+    return total
+
+
+def _connected(A, s) -> bool:
+    s = list(s)
+    seen = {s[0]}
+    stack = [s[0]]
+    while stack:
+        x = stack.pop()
+        for y in s:
+            if y not in seen and A[x, y]:
+                seen.add(y)
+                stack.append(y)
+    return len(seen) == len(s)
+
+
+def motif_class(A, s) -> int:
+    """Isomorphism class of a connected induced subgraph on 3 or 4 vertices,
+    from its edge count and largest degree:
+      3 vertices: 0 wedge, 1 triangle
+      4 vertices: 0 path, 1 star, 2 cycle, 3 paw (tailed triangle),
+                  4 diamond, 5 clique."""
+    deg = [sum(1 for y in s if y != x and A[x, y]) for x in s]
+    e = sum(deg) // 2
+    if len(s) == 3:
+        return 1 if e == 3 else 0
+    if e == 3:
+        return 1 if max(deg) == 3 else 0
+    if e == 4:
+        return 3 if max(deg) == 3 else 2
+    return 4 if e == 5 else 5
+
+
+def motif_counts(g, k: int) -> np.ndarray:
+    A = dense_adj(g)
+    out = np.zeros(2 if k == 3 else 6, dtype=np.uint64)
+    for s in itertools.combinations(range(g.n), k):
+        if _connected(A, s):
+            out[motif_class(A, s)] += 1
+    return out
+
+
+def connected_subsets(g, k: int) -> int:
+    A = dense_adj(g)
+    return sum(1 for s in itertools.combinations(range(g.n), k) if _connected(A, s))
+
+
+# --------------------------------------------------------------------- FSM
+
+# shape id -> (number of vertices, edges between pattern vertex positions)
+SHAPES = {
+    0: (2, [(0, 1)]),                    # single edge, labels (a, b)
+    1: (3, [(0, 1), (0, 2)]),            # wedge, labels (centre, leaf, leaf)
+    2: (3, [(0, 1), (0, 2), (1, 2)]),    # triangle
+    3: (4, [(0, 1), (1, 2), (2, 3)]),    # path, labels along the path
+    4: (4, [(0, 1), (0, 2), (0, 3)]),    # star, labels (centre, leaves)
+}
+SHAPE_EDGES = {0: 1, 1: 2, 2: 3, 3: 3, 4: 3}
+
+
+def pattern_table(max_edges: int, L: int):
+    """The dense pattern numbering, generated block by block in order:
+    edges (a<=b), wedges (centre c, leaves a<=b), triangles (a<=b<=c),
+    paths (a,b,c,d) <= (d,c,b,a), stars (centre c, leaves a<=b<=c);
+    each block in lexicographic order.  Returns a list of (shape, labels)
+    whose position is the index."""
+    table = []
+    r = range(L)
+    if max_edges >= 1:
+        table += [(0, (a, b)) for a in r for b in r if a <= b]
+    if max_edges >= 2:
+        table += [(1, (c, a, b)) for c in r for a in r for b in r if a <= b]
+    if max_edges >= 3:
+        table += [(2, (a, b, c)) for a in r for b in r for c in r if a <= b <= c]
+        table += [(3, t) for t in itertools.product(r, repeat=4) if t <= t[::-1]]
+        table += [(4, (c, a, b, d)) for c in r for a in r for b in r for d in r if a <= b <= d]
+    return table
+
+
+def canonical_labels(shape: int, labels) -> tuple:
+    """Representative label tuple of a labelled shape under its symmetries."""
+    lab = tuple(labels)
+    if shape == 0:
+        return tuple(sorted(lab))
+    if shape == 1:
+        return (lab[0],) + tuple(sorted(lab[1:]))
+    if shape == 2:
+        return tuple(sorted(lab))
+    if shape == 3:
+        return min(lab, lab[::-1])
+    return (lab[0],) + tuple(sorted(lab[1:]))
+
+
+def pattern_index(shape: int, labels, L: int, max_edges: int = 3) -> int:
+    table = pattern_table(max_edges, L)
+    return table.index((shape, canonical_labels(shape, labels)))
+
+
+def mni_support(g, shape: int, labels) -> int:
+    """Minimum-image support of one labelled pattern, by enumerating every
+    injective label-preserving edge-preserving map."""
+    A = dense_adj(g)
+    nv, pedges = SHAPES[shape]
+    dom = [set() for _ in range(nv)]
+    cands = [[v for v in range(g.n) if g.labels[v] == labels[i]] for i in range(nv)]
+    for phi in itertools.product(*cands):
+        if len(set(phi)) < nv:
+            continue
+        if all(A[phi[a], phi[b]] for a, b in pedges):
+            for i in range(nv):
+                dom[i].add(phi[i])
+    return min(len(d) for d in dom)
+
+
+def fsm_supports_all(g, max_edges: int) -> np.ndarray:
+    """Unfiltered supports at the dense index."""
+    table = pattern_table(max_edges, g.n_labels)
+    out = np.zeros(len(table), dtype=np.uint64)
+    present = set(int(x) for x in g.labels)
+    for i, (shape, lab) in enumerate(table):
+        if all(x in present for x in lab):
+            out[i] = mni_support(g, shape, lab)
+    return out
+
+
+def fsm(g, max_edges: int, min_support: int) -> np.ndarray:
+    sup = fsm_supports_all(g, max_edges)
+    sup[sup < np.uint64(max(min_support, 0))] = 0
+    return sup
+
+
+def edge_subsets(g, j: int) -> int:
+    """Number of connected j-edge subsets (edge-induced embeddings)."""
+    E = [tuple(e) for e in g.edges()]
+    total = 0
+    for s in itertools.combinations(E, j):
+        verts = {x for e in s for x in e}
+        # connectivity of the edge set
+        comp = {next(iter(verts))}
+        changed = True
+        while changed:
+            changed = False
+            for a, b in s:
+                if (a in comp) != (b in comp):
+                    comp |= {a, b}
+                    changed = True
+        if comp == verts:
+            total += 1
+    return total

@@ -1,0 +1,133 @@
+"""Pins of the motif oracle (ESU enumeration and the closed form) against
+brute force over vertex subsets and against closed forms of graph families.
+Vertex-induced counting, Pangolin sections 2.1-2.2; 3-MC patterns: wedge,
+triangle; 4-MC patterns in the order path, star, cycle, paw, diamond,
+4-clique."""
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute, closed_form
+from paper_1911_06969_amd import synth
+
+
+def all_three(g, k):
+    b = brute.motif_counts(g, k)
+    e = oracle.motif_esu(g, k, nthreads=1)
+    c = closed_form.motif3(g, nthreads=1) if k == 3 else closed_form.motif4(g, nthreads=1)
+    return b, e, c
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_brute_esu_closed_agree(seed):
+    rng = np.random.default_rng(100 + seed)
+    g = synth.gnp_small(int(rng.integers(5, 13)), float(rng.uniform(0.15, 0.85)), seed)
+    for k in (3, 4):
+        b, e, c = all_three(g, k)
+        assert np.array_equal(b, e), (k, b, e)
+        assert np.array_equal(b, c), (k, b, c)
+
+
+def test_every_graph_on_five_vertices():
+    for g in synth.all_graphs(5):
+        for k in (3, 4):
+            b, e, c = all_three(g, k)
+            assert np.array_equal(b, e) and np.array_equal(b, c)
+
+
+def test_connected_subset_total():
+    g = synth.gnp_small(12, 0.3, 7)
+    for k in (3, 4):
+        assert int(oracle.motif_esu(g, k).sum()) == brute.connected_subsets(g, k)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 6, 11])
+def test_star(m):
+    g = synth.star(m)
+    assert list(oracle.motif_esu(g, 3)) == [comb(m, 2), 0]
+    assert list(closed_form.motif4(g)) == [0, comb(m, 3), 0, 0, 0, 0]
+    assert list(oracle.motif_esu(g, 4)) == [0, comb(m, 3), 0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("n", [5, 6, 9, 17])
+def test_cycle(n):
+    g = synth.cycle(n)
+    assert list(oracle.motif_esu(g, 3)) == [n, 0]
+    assert list(oracle.motif_esu(g, 4)) == [n, 0, 0, 0, 0, 0]
+    assert list(closed_form.motif4(g)) == [n, 0, 0, 0, 0, 0]
+
+
+def test_cycle4():
+    g = synth.cycle(4)
+    assert list(oracle.motif_esu(g, 4)) == [0, 0, 1, 0, 0, 0]
+
+
+@pytest.mark.parametrize("n", [3, 4, 7, 12])
+def test_path(n):
+    g = synth.path(n)
+    assert list(oracle.motif_esu(g, 3)) == [n - 2, 0]
+    assert list(closed_form.motif4(g)) == [max(n - 3, 0), 0, 0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("n", [4, 5, 8])
+def test_complete(n):
+    g = synth.complete(n)
+    assert list(oracle.motif_esu(g, 3)) == [0, comb(n, 3)]
+    assert list(oracle.motif_esu(g, 4)) == [0, 0, 0, 0, 0, comb(n, 4)]
+    assert list(closed_form.motif4(g)) == [0, 0, 0, 0, 0, comb(n, 4)]
+
+
+@pytest.mark.parametrize("a,b", [(2, 2), (2, 5), (3, 4), (6, 6)])
+def test_complete_bipartite(a, b):
+    g = synth.complete_multipartite([a, b])
+    expect = [0, a * comb(b, 3) + b * comb(a, 3), comb(a, 2) * comb(b, 2), 0, 0, 0]
+    assert list(oracle.motif_esu(g, 4)) == expect
+    assert list(closed_form.motif4(g)) == expect
+
+
+def test_single_patterns():
+    """Each 4-vertex pattern alone counts once in its own slot."""
+    shapes = {
+        0: [(0, 1), (1, 2), (2, 3)],
+        1: [(0, 1), (0, 2), (0, 3)],
+        2: [(0, 1), (1, 2), (2, 3), (3, 0)],
+        3: [(0, 1), (1, 2), (2, 0), (2, 3)],
+        4: [(0, 1), (1, 2), (2, 0), (2, 3), (3, 0)],
+        5: [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)],
+    }
+    for p, e in shapes.items():
+        g = synth.from_edges(4, e)
+        expect = [0] * 6
+        expect[p] = 1
+        assert list(oracle.motif_esu(g, 4)) == expect
+        assert list(closed_form.motif4(g)) == expect
+
+
+def test_esu_closed_form_rmat():
+    g = synth.rmat(9, 8, seed=21)
+    for k in (3, 4):
+        e = oracle.motif_esu(g, k)
+        c = closed_form.motif3(g) if k == 3 else closed_form.motif4(g)
+        assert np.array_equal(e, c)
+
+
+def test_relabel_invariance():
+    g = synth.rmat(8, 8, seed=22)
+    h = synth.relabel(g, np.random.default_rng(5).permutation(g.n))
+    assert np.array_equal(oracle.motif_esu(g, 4), oracle.motif_esu(h, 4))
+
+
+def test_roots_partition_total():
+    g = synth.rmat(9, 6, seed=23)
+    whole = oracle.motif_esu(g, 4)
+    a = oracle.motif_esu_roots(g, 4, np.arange(0, g.n, 2))
+    b = oracle.motif_esu_roots(g, 4, np.arange(1, g.n, 2))
+    assert np.array_equal(whole, a + b)
+
+
+def test_reduce_example_triangles_and_wedge():
+    """Three embeddings reduce to {triangle: 2, wedge: 1} (section 3.1)."""
+    g = synth.disjoint_union(synth.complete(3), synth.complete(3), synth.path(3))
+    assert list(oracle.motif_esu(g, 3)) == [1, 2]
