@@ -1,0 +1,237 @@
+/*
+ * pangolin_hip.h -- C ABI of an MI355X (gfx950) graph pattern mining library.
+ *
+ * The library implements the extend-reduce-filter mining model of Pangolin
+ * (Chen, Dathathri, Gill, Pingali, VLDB 2020): embeddings grow level by
+ * level over a CSR graph (section 3.1, Algorithms 1-2), each level is kept
+ * as a structure of arrays and built by a count pass, an exclusive prefix
+ * sum and a write pass (sections 5.1 and 5.3), and the last level is fused
+ * with pattern classification and reduction (section 5.2).  Counts are exact
+ * unsigned 64-bit integers.
+ *
+ * Conventions for every call:
+ *  - The return value is PG_OK (0) or a negative pg_status.  Outputs are
+ *    written only when PG_OK is returned.  pg_last_error() describes the
+ *    most recent failure of the calling thread.
+ *  - Pointers documented as host memory are plain host pointers owned by
+ *    the caller.  With PG_DEVICE_PTRS the graph arrays are device pointers
+ *    owned by the caller and read only during the call.
+ *  - The library owns every device buffer it allocates.  The graph is copied
+ *    to device memory at load time and freed by pg_graph_free.
+ *  - Mining calls are synchronous: they enqueue their kernels on the
+ *    graph's stream and return after the results are on the host.  A graph
+ *    is never modified after loading; several threads may mine one graph
+ *    concurrently only if each uses its own graph handle.
+ *  - There is no CPU fallback: without a usable HIP device every call that
+ *    needs one returns PG_EDEVICE.
+ */
+#ifndef PANGOLIN_HIP_H
+#define PANGOLIN_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PG_OK = 0,
+    PG_EINVAL = -1,        /* invalid argument or CSR violating the input rules */
+    PG_ENOMEM = -2,        /* device allocation failed or budget too small */
+    PG_EUNSUPPORTED = -3,  /* size k / max_edges outside the supported range */
+    PG_EDEVICE = -4,       /* HIP runtime error or no device */
+    PG_EOVERFLOW = -5      /* an index or count exceeded its integer width */
+} pg_status;
+
+typedef struct pg_graph pg_graph;   /* opaque, device resident */
+typedef struct pg_batch pg_batch;   /* opaque, many small graphs, device resident */
+
+/* flags for pg_graph_load_csr / pg_batch_load */
+#define PG_DEVICE_PTRS 1u   /* the CSR arrays are device pointers */
+
+#define PG_KMAX 8           /* largest clique size */
+
+/* ----------------------------------------------------------------- graphs */
+
+/*
+ * Loads an undirected graph in CSR form (the input format of section 6.1:
+ * symmetric, no self-loops, no duplicate edges, each neighbour list sorted
+ * ascending).
+ *   n         number of vertices, 0 <= n < 2^31
+ *   nnz       number of directed entries (twice the edges), < 2^40
+ *   row_ptr   int64[n+1], row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing
+ *   col_idx   int32[nnz], neighbours of v at row_ptr[v] .. row_ptr[v+1]-1
+ *   labels    int32[n] vertex labels in [0, n_labels), or NULL (unlabelled)
+ *   n_labels  number of labels (0 when labels == NULL), at most 64
+ *   flags     PG_DEVICE_PTRS or 0
+ *   stream    hipStream_t for all work on this graph, or NULL (null stream)
+ *   out       receives the handle
+ * The CSR is validated on the device; a violation returns PG_EINVAL.
+ */
+int pg_graph_load_csr(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                      const int32_t* labels, int32_t n_labels, unsigned flags, void* stream,
+                      pg_graph** out);
+
+/* Frees the graph and every device buffer it owns.  NULL is accepted. */
+int pg_graph_free(pg_graph* g);
+
+/* Replaces the stream the graph's work is enqueued on. */
+int pg_graph_set_stream(pg_graph* g, void* stream);
+
+/* Vertex count, directed entry count and maximum degree (host outputs,
+ * any may be NULL). */
+int pg_graph_info(const pg_graph* g, int64_t* n, int64_t* nnz, int64_t* max_degree);
+
+/*
+ * Bound on the device bytes one mining call may hold for materialised
+ * embedding levels.  When a level would exceed it, the initial single-edge
+ * embeddings are processed in chunks through all levels (edge blocking,
+ * section 5.2) and the results summed.  0 restores the default (a quarter
+ * of the device memory).  Values below 1 MiB are raised to 1 MiB.
+ */
+int pg_set_memory_budget(pg_graph* g, uint64_t bytes);
+
+/*
+ * Number of k-cliques (k pairwise adjacent vertices; section 2.2, with
+ * triangle counting as k = 3).  Vertex-induced extension of the last vertex
+ * only (eager pruning, section 4.1) on the degree-ordered DAG (section 4.1:
+ * each edge points to the endpoint of higher degree, ties to the larger
+ * id), toAdd = adjacency to every earlier vertex (the clique listing of
+ * section 3.3).
+ *   k      1 <= k <= PG_KMAX (k = 1 gives n, k = 2 the number of edges)
+ *   count  host uint64, receives the count
+ * The first call builds and caches the DAG on the device.
+ */
+int pg_count_cliques(pg_graph* g, int k, uint64_t* count);
+
+/*
+ * Vertex-induced motif counts for k = 3 or 4 (section 2.2 motif counting,
+ * section 3.3 Listing of motif counting with customised classification,
+ * section 4.2).  Every connected induced k-vertex subgraph is counted once,
+ * in the slot of its isomorphism class:
+ *   k = 3: counts[0] wedge (path on 3 vertices), counts[1] triangle
+ *   k = 4: counts[0] path, [1] 3-star, [2] 4-cycle, [3] paw (triangle with
+ *          a pendant edge), [4] diamond (4-cycle with one chord), [5] 4-clique
+ *   counts  host uint64[2] or uint64[6]
+ */
+int pg_count_motifs(pg_graph* g, int k, uint64_t* counts);
+
+/*
+ * Frequent subgraph mining with minimum-image (domain) support (sections
+ * 2.2 and 3.3, Listing of FSM): edge-induced embeddings over a labelled
+ * graph, extended one edge per level up to max_edges edges (the paper's
+ * "k-FSM" mines patterns of k-1 edges, so k-FSM is max_edges = k-1).  Before
+ * each extension the embeddings of patterns whose support is below
+ * min_support are dropped (Filter; pattern is frequent iff support >=
+ * min_support).
+ *   max_edges     1..3
+ *   min_support   threshold sigma
+ *   supports      host uint64[supports_len]; supports[i] = support of the
+ *                 pattern with dense index i if it is frequent, else 0
+ *   supports_len  >= pg_fsm_num_patterns(max_edges, n_labels)
+ *   n_frequent    host, receives the number of frequent patterns (may be NULL)
+ * Requires a labelled graph.
+ */
+int pg_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports,
+           size_t supports_len, size_t* n_frequent);
+
+/*
+ * Size of the dense pattern index used by pg_fsm for n_labels labels.  The
+ * index enumerates, block after block and each block in lexicographic order
+ * of its label tuple:
+ *   shape 0  single edge, labels (a, b) with a <= b
+ *   shape 1  wedge, labels (centre, a, b) with a <= b            [>= 2 edges]
+ *   shape 2  triangle, labels (a, b, c) with a <= b <= c         [>= 3 edges]
+ *   shape 3  path on 4 vertices, labels (a, b, c, d) read from the end that
+ *            makes the tuple lexicographically smaller            [>= 3 edges]
+ *   shape 4  3-star, labels (centre, a, b, c) with a <= b <= c    [>= 3 edges]
+ * Returns 0 for arguments out of range.
+ */
+uint64_t pg_fsm_num_patterns(int max_edges, int n_labels);
+
+/* Decodes a dense index into its shape and its 2-4 labels (host outputs;
+ * unused label slots are set to -1). */
+int pg_fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* labels4);
+
+/* ---------------------------------------------------- many small graphs */
+
+/*
+ * Loads a batch of small graphs into one device allocation.  Graph g owns
+ * vertices voff[g] .. voff[g+1]-1; row_ptr (int64[voff[n_graphs]+1]) gives
+ * positions in col (int32, total row_ptr[voff[n_graphs]] entries); col
+ * holds graph-local vertex ids.  Each graph must follow the CSR rules of
+ * pg_graph_load_csr and have at most PG_BATCH_MAX_VERTICES vertices.
+ * voff is host memory (int64[n_graphs+1]) in every case; row_ptr and col are
+ * device pointers when PG_DEVICE_PTRS is set.
+ */
+#define PG_BATCH_MAX_VERTICES 1024
+int pg_batch_load(int64_t n_graphs, const int64_t* voff, const int64_t* row_ptr,
+                  const int32_t* col, unsigned flags, void* stream, pg_batch** out);
+int pg_batch_free(pg_batch* b);
+
+/*
+ * 4-motif (k = 4) or 3-motif (k = 3) counts of the graphs ids[0..n_ids) of a
+ * batch (all graphs when ids == NULL, then n_ids is ignored), computed in
+ * one persistent launch that takes graphs from a work queue, largest
+ * estimated work first.  counts (host) receives n_ids rows of 6 (k = 4) or 2
+ * (k = 3) uint64, in the order of ids.  Same slot order as pg_count_motifs.
+ */
+int pg_batch_count_motifs(pg_batch* b, int k, const int64_t* ids, int64_t n_ids, uint64_t* counts);
+
+/*
+ * Asynchronous form for a serving loop: enqueues the same work on `stream`
+ * and returns at once.  ids_dev (device int64[n_ids]) and counts_dev (device
+ * uint64[n_ids * 6]) are caller-owned device buffers that must stay valid
+ * until the stream reaches this point; the results are in counts_dev then.
+ * Calls on different streams may overlap on the device; they share only the
+ * read-only batch.
+ */
+int pg_batch_count_motifs_async(pg_batch* b, int k, const int64_t* ids_dev, int64_t n_ids,
+                                uint64_t* counts_dev, void* stream);
+
+/* Estimated device work of each graph (host double[n_graphs]), the
+ * quantity the batch scheduler orders graphs by. */
+int pg_batch_work_estimate(const pg_batch* b, double* work);
+
+/* Tile/work-split parameters of the batch kernel.  0 keeps the current
+ * value.  block_threads in {64, 128, 256, 512}; waves_per_graph_split is
+ * the estimated work above which a graph is split into several queue
+ * items; grid_blocks is the persistent grid size. */
+int pg_batch_set_params(pg_batch* b, int block_threads, double split_work, int grid_blocks);
+
+/* --------------------------------------------------------------- runtime */
+
+/* Text of the last failure on this thread (never NULL). */
+const char* pg_last_error(void);
+
+/*
+ * Routes the library's device allocations through alloc/free_ (for example
+ * a caching allocator).  alloc(bytes, ctx) returns device memory or NULL;
+ * free_(ptr, ctx) releases it.  Passing NULL for both restores hipMalloc /
+ * hipFree.  Must be called while no graph or batch is loaded.
+ */
+int pg_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_)(void* ptr, void* ctx),
+                     void* ctx);
+
+/*
+ * Kernel timing.  When enabled, every kernel launch is bracketed by HIP
+ * events on the stream it runs on and its duration is added to the named
+ * kernel's total.  pg_profile_query returns the total milliseconds, the
+ * number of launches and the work units reported for `kernel` (returns
+ * PG_EINVAL for an unknown name).  pg_profile_list writes up to `cap`
+ * kernel names, separated by newlines, into buf.
+ */
+int pg_profile_enable(int on);
+int pg_profile_reset(void);
+int pg_profile_query(const char* kernel, double* total_ms, uint64_t* launches, double* units);
+int pg_profile_list(char* buf, size_t cap);
+
+/* Library version string. */
+const char* pg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PANGOLIN_HIP_H */

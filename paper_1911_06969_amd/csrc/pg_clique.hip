@@ -1,0 +1,368 @@
+// k-clique counting: vertex-induced extension of the last vertex only, on
+// the degree-ordered DAG (Pangolin sections 3.3 and 4.1, clique Listing).
+//
+// Embedding list.  Level L1 holds the single-edge embeddings (the DAG
+// edges); level L_i holds (i+1)-cliques.  Each level is a structure of
+// arrays: vid[] (the newest vertex of every embedding) plus the offsets
+// seg[] of the children of every embedding of the previous level, which is
+// the prefix sum the count pass produces (section 5.3) and encodes the
+// idx[] column of section 5.1 in compressed form: the parent of entry x is
+// the p with seg[p] <= x < seg[p+1].
+//
+// Extension.  toExtend = last vertex only, toAdd = adjacent to every earlier
+// vertex.  The siblings of an entry x (the children of x's parent) are
+// exactly the vertices adjacent to all of x's earlier vertices and later in
+// the order; so the children of x are out(vid[x]) intersected with the
+// siblings after x.  One wave takes one parent segment, stages the sibling
+// list in LDS, streams the out-lists of the siblings from HBM (coalesced,
+// several siblings per 64-lane step) and tests each candidate by a
+// branch-free binary search in the LDS copy.
+//
+// Three modes share the kernel: COUNT (children per entry, for the scan),
+// WRITE (children at their scanned offsets, ascending) and LAST (the fused
+// last level: candidates are tested and counted, never stored; each wave
+// keeps its count in a register and adds it once, section 5.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+
+constexpr int CQ_THREADS = 256;
+constexpr int CQ_WAVES = CQ_THREADS / WAVE;
+constexpr int CQ_SMAX = 1024;          // sibling lists up to this length live in LDS
+constexpr int CQ_TRIM_MIN = 48;        // out-lists at least this long are trimmed to max(S)
+
+enum { MODE_COUNT = 0, MODE_WRITE = 1, MODE_LAST = 2 };
+
+struct CliqueArgs {
+    XcdQueue Q;                         // items: parent segments [p_lo, p_lo + n_items)
+    int64_t p_lo;
+    const int64_t* seg;                 // seg[p] - seg_base = first entry of segment p
+    int64_t seg_base;
+    const int32_t* vid;                 // entries of this level
+    int64_t x_lo, x_hi;                 // only entries in [x_lo, x_hi) are extended
+    const int64_t* rp;                  // DAG
+    const int32_t* col;
+    uint32_t* count;                    // COUNT: children of entry x
+    const uint64_t* start;              // WRITE: children of x begin at start[x] - start_base
+    uint64_t start_base;
+    int32_t* out_vid;                   // WRITE
+    unsigned long long* stats;          // LAST: [0] cliques, [1] input entries, [2] sum of out-degrees
+};
+
+struct CliqueLds {
+    int32_t S[CQ_WAVES][CQ_SMAX];
+    uint32_t pre[CQ_WAVES][WAVE];
+    int64_t lo[CQ_WAVES][WAVE];
+    uint32_t cnt[CQ_WAVES][WAVE];
+};
+
+struct CliqueAcc {
+    uint64_t found = 0, n_in = 0, deg_sum = 0;
+};
+
+// Extends the entries of one parent segment whose sibling list is S
+// (LDS or global; the pointer's address space is known after inlining).
+template <int MODE, class SPtr>
+__device__ __forceinline__ void clique_segment(const CliqueArgs& A, CliqueLds& L, int w, SPtr S, int32_t s,
+                                               int64_t b, CliqueAcc& acc) {
+    const int32_t s_last = S[s - 1];
+    const int32_t x0 = (int32_t)max<int64_t>(0, A.x_lo - b);
+    const int32_t x1 = (int32_t)min<int64_t>(s, A.x_hi - b);
+    for (int32_t xc = x0; xc < x1; xc += WAVE) {
+        const int32_t x = xc + lane();
+        int64_t lo = 0;
+        uint32_t d = 0;
+        if (x < x1) {
+            const int32_t v = S[x];
+            const int64_t r0 = A.rp[v], r1 = A.rp[v + 1];
+            if (MODE == MODE_LAST) {
+                acc.n_in += 1;
+                acc.deg_sum += (uint64_t)(r1 - r0);
+            }
+            if (x < s - 1) {
+                // candidates lie in (S[x], S[s-1]]: out(v) is above v already
+                const int64_t hi = (r1 - r0 >= CQ_TRIM_MIN) ? upper_bound(A.col, r0, r1, s_last) : r1;
+                lo = r0;
+                d = (uint32_t)(hi - r0);
+            }
+        }
+        const uint32_t inc = wave_incl_scan(d);
+        const uint32_t W = bcast(inc, WAVE - 1);
+        L.pre[w][lane()] = inc - d;
+        L.lo[w][lane()] = lo;
+        if (MODE != MODE_LAST) L.cnt[w][lane()] = 0;
+        wave_sync();
+        const int nx = min(WAVE, x1 - xc);
+        for (uint32_t t0 = 0; t0 < W; t0 += WAVE) {
+            const uint32_t t = t0 + lane();
+            const bool valid = t < W;
+            // xi: the entry whose candidate range holds t
+            int xi = 0;
+            {
+                int n_i = nx;
+                while (n_i > 1) {
+                    const int half = n_i >> 1;
+                    if (L.pre[w][xi + half] <= t) xi += half;
+                    n_i -= half;
+                }
+            }
+            bool found = false;
+            int32_t u = 0;
+            if (valid) {
+                u = A.col[L.lo[w][xi] + (t - L.pre[w][xi])];
+                const int32_t after = xc + xi + 1;
+                found = contains(S + after, s - after, u);
+            }
+            if (MODE == MODE_LAST) {
+                acc.found += found;
+            } else if (MODE == MODE_COUNT) {
+                if (found) atomicAdd(&L.cnt[w][xi], 1u);
+            } else {
+                // lanes of one entry are contiguous; rank found candidates in lane order
+                const int key = valid ? xi : WAVE;   // invalid lanes form their own group
+                const int prev = __shfl_up(key, 1, WAVE);
+                const bool head = lane() == 0 || prev != key;
+                const uint64_t H = ballot(head);
+                const uint64_t F = ballot(found);
+                const uint64_t le = lanemask_lt() | (1ull << lane());
+                const int h = 63 - __clzll(H & le);
+                const uint64_t grp = le & ~((1ull << h) - 1ull);
+                const uint32_t base = valid ? L.cnt[w][xi] : 0u;
+                if (found) {
+                    const uint64_t dst = A.start[b + xc + xi] - A.start_base + base +
+                                         (uint64_t)popc64(F & grp & lanemask_lt());
+                    A.out_vid[dst] = u;
+                }
+                const bool next_head = (lane() == WAVE - 1) || ((H >> (lane() + 1)) & 1ull);
+                wave_sync();
+                if (valid && next_head) L.cnt[w][xi] = base + (uint32_t)popc64(F & grp);
+                wave_sync();
+            }
+        }
+        if (MODE == MODE_COUNT) {
+            wave_sync();
+            if (x < x1) A.count[b + x] = L.cnt[w][lane()];
+        }
+        wave_sync();
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(CQ_THREADS) void k_clique_ext(CliqueArgs A) {
+    __shared__ CliqueLds L;
+    const int w = threadIdx.x / WAVE;
+    CliqueAcc acc;
+    QueueCursor cur = queue_start();
+    int64_t it_end = 0;
+    for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
+        for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
+            const int64_t b = A.seg[p] - A.seg_base;
+            const int64_t e = A.seg[p + 1] - A.seg_base;
+            const int32_t s = (int32_t)(e - b);
+            if (s <= 0) continue;
+            if (s <= CQ_SMAX) {
+                for (int i = lane(); i < s; i += WAVE) L.S[w][i] = A.vid[b + i];
+                wave_sync();
+                clique_segment<MODE>(A, L, w, &L.S[w][0], s, b, acc);
+            } else {
+                clique_segment<MODE>(A, L, w, A.vid + b, s, b, acc);
+            }
+            wave_sync();
+        }
+    }
+    if (MODE == MODE_LAST) {
+        const uint64_t f = wave_sum_u64(acc.found);
+        const uint64_t ni = wave_sum_u64(acc.n_in);
+        const uint64_t ds = wave_sum_u64(acc.deg_sum);
+        if (lane() == 0 && (f | ni)) {
+            atomicAdd(&A.stats[0], (unsigned long long)f);
+            atomicAdd(&A.stats[1], (unsigned long long)ni);
+            atomicAdd(&A.stats[2], (unsigned long long)ds);
+        }
+    }
+}
+
+// Chunk boundaries for edge blocking: entry c_j = largest c with
+// start[c] <= j * cap (j = 1..nb-1), plus the segment of the previous level
+// that holds entry c_j.
+__global__ void k_chunk_bounds(const uint64_t* __restrict__ start, int64_t m, uint64_t cap, int64_t nb,
+                               const int64_t* __restrict__ seg, int64_t seg_base, int64_t n_seg,
+                               int64_t* __restrict__ out_c, int64_t* __restrict__ out_p,
+                               uint64_t* __restrict__ out_s) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j > nb) return;
+    int64_t c;
+    if (j == 0) c = 0;
+    else if (j == nb) c = m;
+    else {
+        const uint64_t target = start[0] + (uint64_t)j * cap;
+        int64_t lo = 0, hi = m;   // largest c in [0, m] with start[c] <= target
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= target) lo = mid; else hi = mid - 1;
+        }
+        c = lo;
+    }
+    // segment p with seg[p] - seg_base <= c < seg[p+1] - seg_base (last such p)
+    int64_t lo = 0, hi = n_seg;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (seg[mid] - seg_base <= c) lo = mid; else hi = mid - 1;
+    }
+    out_c[j] = c;
+    out_p[j] = lo;
+    out_s[j] = start[c];
+}
+
+struct CliqueRun {
+    pg_graph* g;
+    int k;
+    hipStream_t s;
+    unsigned long long* stats;
+    unsigned long long* qctr;   // N_XCD counters
+    int64_t waves;
+    int blocks;
+};
+
+template <int MODE>
+static void launch(CliqueRun& R, CliqueArgs A, int64_t p_lo, int64_t n_seg, const char* name, double units) {
+    if (n_seg <= 0) return;
+    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, R.s);
+    A.Q.next = R.qctr;
+    A.Q.n_items = n_seg;
+    A.Q.chunk = n_seg >= R.waves * 64 ? 16 : (n_seg >= R.waves * 8 ? 4 : 1);
+    A.p_lo = p_lo;
+    A.stats = R.stats;
+    ProfScope ps(name, R.s, units);
+    k_clique_ext<MODE><<<R.blocks, CQ_THREADS, 0, R.s>>>(A);
+    PG_HIP(hipGetLastError());
+}
+
+// Extends the entries [x_lo, x_hi) of level `lev` (segments [p_lo, p_hi) of
+// its parents cover them) through the remaining levels.
+static void extend_level(CliqueRun& R, int lev, const int64_t* seg, int64_t seg_base, int64_t p_lo, int64_t p_hi,
+                         const int32_t* vid, int64_t x_lo, int64_t x_hi) {
+    pg_graph* g = R.g;
+    Arena& ar = g->arena;
+    CliqueArgs A{};
+    A.seg = seg;
+    A.seg_base = seg_base;
+    A.vid = vid;
+    A.x_lo = x_lo;
+    A.x_hi = x_hi;
+    A.rp = g->dag.rp.as<int64_t>();
+    A.col = g->dag.col.as<int32_t>();
+    if (lev == R.k - 2) {
+        launch<MODE_LAST>(R, A, p_lo, p_hi - p_lo, "clique_last", 0.0);
+        return;
+    }
+    const int64_t m = x_hi - x_lo;
+    if (m <= 0) return;
+    const size_t mk = ar.mark();
+    // count pass (inspection) -> exclusive prefix sum -> exact allocation -> write pass
+    uint32_t* cnt = push<uint32_t>(ar, m);
+    uint64_t* start = push<uint64_t>(ar, m + 1);
+    A.count = cnt - x_lo;   // indexed by entry id
+    launch<MODE_COUNT>(R, A, p_lo, p_hi - p_lo, "clique_count", (double)m);
+    scan_u32(cnt, m, start, ar, R.s);
+    const uint64_t total = read_u64(start + m, R.s);
+    if (total == 0) {
+        ar.reset(mk);
+        return;
+    }
+    PG_REQUIRE(total < (uint64_t(1) << 40), PG_EOVERFLOW, "level size exceeds 2^40 entries");
+    const bool next_last = (lev + 1 == R.k - 2);
+    // bytes per entry of the next level: vid, plus count + start if it is
+    // extended again
+    const uint64_t per = next_last ? 4 : 4 + 4 + 8;
+    const uint64_t room = g->budget > ar.mark() ? (g->budget - ar.mark()) : 0;
+    uint64_t cap = std::max<uint64_t>(room / (per * (next_last ? 1 : 2)), (uint64_t)R.g->dag.max_out + 1);
+    int64_t nb = (int64_t)((total + cap - 1) / cap);
+    std::vector<int64_t> hc(nb + 1), hp(nb + 1);
+    std::vector<uint64_t> hs(nb + 1);
+    if (nb == 1) {
+        hc[0] = 0; hc[1] = m;
+        hp[0] = p_lo; hp[1] = p_hi - 1;
+        hs[0] = 0; hs[1] = total;
+    } else {
+        const size_t mk2 = ar.mark();
+        int64_t* dc = push<int64_t>(ar, nb + 1);
+        int64_t* dp = push<int64_t>(ar, nb + 1);
+        uint64_t* ds = push<uint64_t>(ar, nb + 1);
+        k_chunk_bounds<<<(unsigned)((nb + 1 + 255) / 256), 256, 0, R.s>>>(start, m, cap, nb, seg + p_lo,
+                                                                         seg_base + x_lo, p_hi - p_lo, dc, dp, ds);
+        PG_HIP(hipGetLastError());
+        PG_HIP(hipMemcpyAsync(hc.data(), dc, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, R.s));
+        PG_HIP(hipMemcpyAsync(hp.data(), dp, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, R.s));
+        PG_HIP(hipMemcpyAsync(hs.data(), ds, sizeof(uint64_t) * (nb + 1), hipMemcpyDeviceToHost, R.s));
+        PG_HIP(hipStreamSynchronize(R.s));
+        ar.reset(mk2);
+        for (int64_t j = 0; j <= nb; ++j) hp[j] += p_lo;
+    }
+    uint64_t biggest = 0;
+    for (int64_t j = 0; j < nb; ++j) biggest = std::max<uint64_t>(biggest, hs[j + 1] - hs[j]);
+    int32_t* next_vid = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
+    for (int64_t j = 0; j < nb; ++j) {
+        const int64_t c0 = hc[j], c1 = hc[j + 1];
+        if (c1 <= c0) continue;
+        // write pass for entries [x_lo + c0, x_lo + c1): their segments run
+        // from the one holding c0 to the one holding c1 - 1
+        CliqueArgs W = A;
+        W.x_lo = x_lo + c0;
+        W.x_hi = x_lo + c1;
+        W.start = start - x_lo;
+        W.start_base = hs[j];
+        W.out_vid = next_vid;
+        int64_t q_lo = hp[j], q_hi;
+        if (nb == 1) q_hi = p_hi;
+        else {
+            // the segment holding entry c1 - 1 is the last p with seg[p] <= c1 - 1
+            q_hi = (j + 1 == nb) ? p_hi : hp[j + 1] + 1;
+        }
+        launch<MODE_WRITE>(R, W, q_lo, q_hi - q_lo, "clique_write", (double)(hs[j + 1] - hs[j]));
+        // next level: segments are the entries [c0, c1) of this level, whose
+        // children offsets (rebased by hs[j]) are start[c0..c1]
+        extend_level(R, lev + 1, reinterpret_cast<const int64_t*>(start), (int64_t)hs[j], c0, c1, next_vid, 0,
+                     (int64_t)(hs[j + 1] - hs[j]));
+    }
+    ar.reset(mk);
+}
+
+uint64_t count_cliques(pg_graph* g, int k) {
+    PG_REQUIRE(k >= 1 && k <= PG_KMAX, PG_EUNSUPPORTED, "k must be in [1, PG_KMAX]");
+    if (k == 1) return (uint64_t)g->n;
+    if (k == 2) return (uint64_t)(g->nnz / 2);
+    build_dag(g);
+    if (g->dag.n_edges == 0) return 0;
+    hipStream_t s = g->stream;
+    Arena& ar = g->arena;
+    CliqueRun R;
+    R.g = g;
+    R.k = k;
+    R.s = s;
+    R.waves = grid_waves(32);
+    R.blocks = (int)(R.waves / CQ_WAVES);
+    uint64_t* small = push<uint64_t>(ar, 16);
+    R.stats = reinterpret_cast<unsigned long long*>(small);
+    R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
+    fill_u64(small, 8, 0, s);
+    // level L1: entries = DAG edges, parents = vertices (segment = out-list)
+    extend_level(R, 1, g->dag.rp.as<int64_t>(), 0, 0, g->n, g->dag.col.as<int32_t>(), 0, g->dag.n_edges);
+    uint64_t st[3] = {0, 0, 0};
+    PG_HIP(hipMemcpyAsync(st, small, sizeof(st), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (prof_on()) {
+        // record the last level's algorithmic work: input entries and the
+        // out-degrees of their newest vertices
+        ProfScope ps("clique_last_work", s, 16.0 * (double)st[1] + 4.0 * (double)st[2]);
+    }
+    return st[0];
+}
+
+}  // namespace pg

@@ -1,0 +1,144 @@
+// Device-side helpers for 64-lane CDNA wavefronts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pg {
+
+constexpr int WAVE = 64;
+constexpr int N_XCD = 8;   // MI355X: 8 accelerator complex dies, 32 CUs each
+
+__device__ __forceinline__ int lane() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Makes LDS writes of every lane visible to the other lanes of the wave.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (lane() == 0) ? 0ull : (~0ull >> (64 - lane()));
+}
+
+__device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
+
+template <class T>
+__device__ __forceinline__ T bcast(T v, int src) {
+    return __shfl(v, src, WAVE);
+}
+
+__device__ __forceinline__ int64_t bcast64(int64_t v, int src) {
+    return (int64_t)__shfl((long long)v, src, WAVE);
+}
+
+// Inclusive prefix sum across the wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, WAVE);
+        if (lane() >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, d, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// First index in [lo, hi) with a[i] >= key.
+template <class P>
+__device__ __forceinline__ int64_t lower_bound(P a, int64_t lo, int64_t hi, int32_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// First index in [lo, hi) with a[i] > key.
+template <class P>
+__device__ __forceinline__ int64_t upper_bound(P a, int64_t lo, int64_t hi, int32_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Branch-free membership test in a sorted array of length len (len >= 0).
+template <class P>
+__device__ __forceinline__ bool contains(P a, int32_t len, int32_t key) {
+    if (len <= 0) return false;
+    int32_t base = 0;
+    int32_t n = len;
+    while (n > 1) {
+        int32_t half = n >> 1;
+        base = (a[base + half] <= key) ? base + half : base;
+        n -= half;
+    }
+    return a[base] == key;
+}
+
+// ---------------------------------------------------------- work queues
+//
+// Items [0, n_items) are split into N_XCD contiguous ranges, one per die,
+// so that neighbouring items (which share adjacency lists) run on the same
+// die and share its L2.  Workgroups are dispatched to dies round-robin, so
+// a workgroup's home die is blockIdx.x % N_XCD.  A wave takes `chunk` items
+// at a time from its home range and, when that is exhausted, from the
+// other ranges in turn; every wave stops after all eight are exhausted.
+struct XcdQueue {
+    unsigned long long* next;   // N_XCD counters, zeroed before the launch
+    int64_t n_items;
+    int64_t chunk;
+};
+
+struct QueueCursor {
+    int q;        // current range
+    int tried;    // ranges found exhausted
+};
+
+__device__ __forceinline__ int64_t xcd_lo(const XcdQueue& Q, int q) {
+    return (Q.n_items * q) / N_XCD;
+}
+
+// Returns the first item of the next chunk (its end is min(first + chunk,
+// range end)) or -1 when all ranges are exhausted.  Wave-uniform.
+__device__ __forceinline__ int64_t queue_next(const XcdQueue& Q, QueueCursor& c, int64_t& end) {
+    while (c.tried < N_XCD) {
+        int64_t lo = xcd_lo(Q, c.q), hi = xcd_lo(Q, c.q + 1);
+        int64_t got = 0;
+        if (lane() == 0) got = (int64_t)atomicAdd(&Q.next[c.q], (unsigned long long)Q.chunk);
+        got = bcast64(got, 0);
+        int64_t first = lo + got;
+        if (first < hi) {
+            end = min(first + Q.chunk, hi);
+            return first;
+        }
+        c.q = (c.q + 1) % N_XCD;
+        c.tried++;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ QueueCursor queue_start() {
+    QueueCursor c;
+    c.q = blockIdx.x % N_XCD;
+    c.tried = 0;
+    return c;
+}
+
+}  // namespace pg

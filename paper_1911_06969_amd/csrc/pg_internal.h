@@ -1,0 +1,178 @@
+// Internal declarations shared by the HIP sources of the mining library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pangolin_hip.h"
+
+namespace pg {
+
+// ------------------------------------------------------------ error state
+
+void set_error(const std::string& msg);
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define PG_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::pg::Error{PG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define PG_REQUIRE(cond, code, msg)                     \
+    do {                                                \
+        if (!(cond)) throw ::pg::Error{(code), (msg)};  \
+    } while (0)
+
+// Runs body, converting exceptions to a status code.
+template <class F>
+int guarded(F&& body) {
+    try {
+        body();
+        return PG_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return PG_EINVAL;
+    }
+}
+
+// ---------------------------------------------------------------- memory
+
+void* dev_alloc(size_t bytes);       // throws Error{PG_ENOMEM}
+void dev_free(void* p);
+
+// Grow-only device buffer.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    void reserve(size_t need);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(p); }
+    ~DevBuf() { release(); }
+};
+
+// Stack allocator over one device buffer: per-call temporaries are pushed
+// and popped in LIFO order; the buffer grows only between calls.
+struct Arena {
+    DevBuf buf;
+    size_t top = 0;
+    size_t high = 0;   // high-water mark of the last call
+    size_t want = 0;   // capacity to grow to before the next call
+    void begin_call();
+    void* push(size_t bytes);   // 256-byte aligned; throws PG_ENOMEM when full
+    size_t mark() const { return top; }
+    void reset(size_t m) { top = m; }
+    size_t avail() const { return buf.bytes > top ? buf.bytes - top : 0; }
+};
+
+template <class T>
+T* push(Arena& a, size_t count) {
+    return static_cast<T*>(a.push(count * sizeof(T)));
+}
+
+// --------------------------------------------------------------- profiling
+
+bool prof_on();
+// Brackets one kernel launch with events on `s` when profiling is on.
+struct ProfScope {
+    int slot = -1;
+    hipStream_t s;
+    ProfScope(const char* kernel, hipStream_t s, double units = 0.0);
+    ~ProfScope();
+};
+void prof_flush();   // resolves pending events; stream must be synchronised
+
+// ------------------------------------------------------------- device info
+
+struct DeviceInfo {
+    int device = 0;
+    int n_cu = 256;
+    size_t total_mem = 0;
+};
+const DeviceInfo& device_info();
+
+// --------------------------------------------------------------- graph
+
+struct Dag {
+    bool built = false;
+    int64_t n_edges = 0;     // directed DAG edges (= undirected edges)
+    int64_t max_out = 0;
+    DevBuf rank_of;          // int32[n]: rank of each original vertex in the degree order
+    DevBuf rp;               // int64[n+1] over ranks
+    DevBuf col;              // int32[n_edges], out-neighbours (ranks), ascending
+};
+
+struct MotifL1 {
+    bool built = false;
+    int64_t n_edges = 0;     // undirected edges (u < v)
+    DevBuf seg;              // int64[n+1]: edges of vertex u are seg[u]..seg[u+1]-1
+    DevBuf src;              // int32[n_edges] = u
+    DevBuf dst;              // int32[n_edges] = v (> u), ascending within u
+};
+
+}  // namespace pg
+
+struct pg_graph {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n = 0, nnz = 0, max_deg = 0;
+    int32_t n_labels = 0;
+    pg::DevBuf rp, col, labels;
+    pg::Dag dag;
+    pg::MotifL1 ml1;
+    uint64_t budget = 0;     // bytes for materialised levels
+    pg::Arena arena;
+};
+
+struct pg_batch;
+
+namespace pg {
+
+// ----------------------------------------------------------- primitives
+
+// Exclusive prefix sum of m uint32 values into out[0..m] (out[m] = total),
+// returns nothing; temporaries come from the arena.
+void scan_u32(const uint32_t* in, int64_t m, uint64_t* out, Arena& a, hipStream_t s);
+void scan_u64(const uint64_t* in, int64_t m, uint64_t* out, Arena& a, hipStream_t s);
+
+// Stable LSD radix sort of uint64 keys on bits [lo_bit, hi_bit).  keys and
+// tmp hold m entries; the sorted keys end in keys.
+void radix_sort_u64(uint64_t* keys, uint64_t* tmp, int64_t m, int lo_bit, int hi_bit, Arena& a,
+                    hipStream_t s);
+
+// Sets n uint64 values to v (a kernel, so it is safe under graph capture).
+void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+
+uint64_t read_u64(const uint64_t* dev, hipStream_t s);   // synchronous
+
+// ------------------------------------------------------------- pipelines
+
+void graph_load(pg_graph* g, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
+                const int32_t* labels, int32_t n_labels, unsigned flags);
+void build_dag(pg_graph* g);
+void build_motif_l1(pg_graph* g);
+uint64_t count_cliques(pg_graph* g, int k);
+void count_motifs(pg_graph* g, int k, uint64_t* counts);
+void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports, size_t len,
+             size_t* n_frequent);
+
+uint64_t fsm_num_patterns(int max_edges, int n_labels);
+
+int64_t grid_waves(int waves_per_cu);
+
+}  // namespace pg

@@ -1,0 +1,430 @@
+// Runtime pieces of the mining library: error state, device memory,
+// kernel timing, and the scan / radix-sort / fill primitives the level
+// pipelines are built from.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pg_device.h"
+#include "pg_internal.h"
+
+namespace pg {
+
+// ------------------------------------------------------------ error state
+
+static thread_local std::string t_last_error = "";
+
+void set_error(const std::string& msg) { t_last_error = msg; }
+
+const char* last_error() { return t_last_error.c_str(); }
+
+// ---------------------------------------------------------------- memory
+
+static void* (*g_alloc)(size_t, void*) = nullptr;
+static void (*g_free)(void*, void*) = nullptr;
+static void* g_alloc_ctx = nullptr;
+
+void* dev_alloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void* p = nullptr;
+    if (g_alloc) {
+        p = g_alloc(bytes, g_alloc_ctx);
+        if (!p) throw Error{PG_ENOMEM, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes"};
+        return p;
+    }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{PG_ENOMEM, "hipMalloc(" + std::to_string(bytes) + ") failed: " + hipGetErrorString(e)};
+    }
+    return p;
+}
+
+void dev_free(void* p) {
+    if (!p) return;
+    if (g_free) g_free(p, g_alloc_ctx);
+    else (void)hipFree(p);
+}
+
+void set_allocator(void* (*a)(size_t, void*), void (*f)(void*, void*), void* ctx) {
+    g_alloc = a;
+    g_free = f;
+    g_alloc_ctx = ctx;
+}
+
+void DevBuf::reserve(size_t need) {
+    if (need <= bytes && p) return;
+    release();
+    p = dev_alloc(need);
+    bytes = need;
+}
+
+void DevBuf::release() {
+    if (p) dev_free(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+void Arena::begin_call() {
+    top = 0;
+    high = 0;
+    want = std::max<size_t>(want, size_t(64) << 20);
+    if (want > buf.bytes) buf.reserve(want);
+}
+
+void* Arena::push(size_t bytes) {
+    size_t b = (bytes + 255) & ~size_t(255);
+    if (top + b > buf.bytes) {
+        // Remember the size this call needed; the caller retries after growth.
+        want = std::max(want, top + b + (top + b) / 4);
+        throw Error{PG_ENOMEM, "arena"};
+    }
+    void* p = static_cast<char*>(buf.p) + top;
+    top += b;
+    high = std::max(high, top);
+    return p;
+}
+
+// ------------------------------------------------------------- device info
+
+const DeviceInfo& device_info() {
+    static DeviceInfo info;
+    static bool done = false;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!done) {
+        int dev = 0;
+        PG_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        PG_HIP(hipGetDeviceProperties(&prop, dev));
+        info.device = dev;
+        info.n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+        info.total_mem = prop.totalGlobalMem;
+        done = true;
+    }
+    return info;
+}
+
+int64_t grid_waves(int waves_per_cu) { return (int64_t)device_info().n_cu * waves_per_cu; }
+
+// --------------------------------------------------------------- profiling
+
+struct ProfStat {
+    double ms = 0;
+    uint64_t launches = 0;
+    double units = 0;
+};
+struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double units;
+};
+static std::mutex g_prof_mu;
+static bool g_prof = false;
+static std::map<std::string, ProfStat> g_stats;
+static std::vector<Pending> g_pending;
+static std::vector<hipEvent_t> g_event_pool;
+
+bool prof_on() { return g_prof; }
+
+static hipEvent_t get_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    PG_HIP(hipEventCreate(&e));
+    return e;
+}
+
+ProfScope::ProfScope(const char* kernel, hipStream_t st, double units) : s(st) {
+    if (!g_prof) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    Pending p{kernel, get_event(), get_event(), units};
+    PG_HIP(hipEventRecord(p.a, s));
+    g_pending.push_back(p);
+    slot = (int)g_pending.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (slot < (int)g_pending.size()) (void)hipEventRecord(g_pending[slot].b, s);
+}
+
+void prof_flush() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto& p : g_pending) {
+        float ms = 0;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto& st = g_stats[p.name];
+            st.ms += ms;
+            st.launches += 1;
+            st.units += p.units;
+        }
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+
+void prof_enable(bool on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof = on;
+}
+
+void prof_reset() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_stats.clear();
+}
+
+bool prof_query(const char* name, double* ms, uint64_t* launches, double* units) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    auto it = g_stats.find(name);
+    if (it == g_stats.end()) return false;
+    if (ms) *ms = it->second.ms;
+    if (launches) *launches = it->second.launches;
+    if (units) *units = it->second.units;
+    return true;
+}
+
+std::string prof_list() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    std::string s;
+    for (auto& kv : g_stats) {
+        s += kv.first;
+        s += "\n";
+    }
+    return s;
+}
+
+// ------------------------------------------------------------------ fill
+
+template <class T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    k_fill<uint64_t><<<blocks, 256, 0, s>>>(p, n, v);
+    PG_HIP(hipGetLastError());
+}
+
+void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    k_fill<uint32_t><<<blocks, 256, 0, s>>>(p, n, v);
+    PG_HIP(hipGetLastError());
+}
+
+uint64_t read_u64(const uint64_t* dev, hipStream_t s) {
+    uint64_t h = 0;
+    PG_HIP(hipMemcpyAsync(&h, dev, sizeof(h), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+// ------------------------------------------------------------------ scan
+//
+// Three phases (inspection-execution's prefix sum, section 5.3):
+// per-tile sums, an exclusive scan of the tile sums (recursively), then a
+// per-tile exclusive scan offset by the tile's base.  A tile is 256 threads
+// x 8 consecutive items.
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int64_t SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+template <class Tin>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_sums(const Tin* __restrict__ in, int64_t m,
+                                                                 uint64_t* __restrict__ sums) {
+    __shared__ uint64_t part[SCAN_THREADS / WAVE];
+    const int64_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i)
+        if (base + i < m) s += (uint64_t)in[base + i];
+    s = wave_sum_u64(s);
+    if (lane() == 0) part[threadIdx.x / WAVE] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < SCAN_THREADS / WAVE; ++w) t += part[w];
+        sums[blockIdx.x] = t;
+    }
+}
+
+template <class Tin>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const Tin* __restrict__ in, int64_t m,
+                                                             const uint64_t* __restrict__ tile_base,
+                                                             uint64_t* __restrict__ out) {
+    __shared__ uint64_t wave_tot[SCAN_THREADS / WAVE];
+    const int64_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    uint64_t v[SCAN_ITEMS];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < m) ? (uint64_t)in[base + i] : 0;
+        s += v[i];
+    }
+    // inclusive scan of per-thread sums within the wave
+    uint64_t inc = s;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint64_t t = (uint64_t)__shfl_up((unsigned long long)inc, d, WAVE);
+        if (lane() >= d) inc += t;
+    }
+    const int w = threadIdx.x / WAVE;
+    if (lane() == WAVE - 1) wave_tot[w] = inc;
+    __syncthreads();
+    uint64_t before = tile_base[blockIdx.x];
+    for (int j = 0; j < w; ++j) before += wave_tot[j];
+    uint64_t run = before + inc - s;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < m) out[base + i] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) out[m] = run;
+}
+
+template <class Tin>
+static void scan_impl(const Tin* in, int64_t m, uint64_t* out, Arena& a, hipStream_t s) {
+    if (m <= 0) {
+        fill_u64(out, 1, 0, s);
+        return;
+    }
+    const int64_t tiles = (m + SCAN_TILE - 1) / SCAN_TILE;
+    size_t mk = a.mark();
+    uint64_t* sums = push<uint64_t>(a, tiles);
+    uint64_t* base = push<uint64_t>(a, tiles + 1);
+    {
+        ProfScope ps("scan", s, (double)m);
+        k_scan_tile_sums<Tin><<<(unsigned)tiles, SCAN_THREADS, 0, s>>>(in, m, sums);
+        PG_HIP(hipGetLastError());
+    }
+    if (tiles == 1) fill_u64(base, 1, 0, s);
+    else scan_impl<uint64_t>(sums, tiles, base, a, s);
+    {
+        ProfScope ps("scan", s, 0.0);
+        k_scan_tiles<Tin><<<(unsigned)tiles, SCAN_THREADS, 0, s>>>(in, m, base, out);
+        PG_HIP(hipGetLastError());
+    }
+    a.reset(mk);
+}
+
+void scan_u32(const uint32_t* in, int64_t m, uint64_t* out, Arena& a, hipStream_t s) {
+    scan_impl<uint32_t>(in, m, out, a, s);
+}
+
+void scan_u64(const uint64_t* in, int64_t m, uint64_t* out, Arena& a, hipStream_t s) {
+    scan_impl<uint64_t>(in, m, out, a, s);
+}
+
+// ------------------------------------------------------------ radix sort
+//
+// Stable LSD radix sort, 8-bit digits.  Each pass: a digit histogram per
+// tile (laid out digit-major), an exclusive scan of the histograms, then a
+// stable scatter.  Inside a tile every wave owns a contiguous run of keys
+// and ranks them in order; the ranks of equal digits within one 64-key
+// step come from eight ballots (one per digit bit).
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_WAVES = RS_THREADS / WAVE;
+constexpr int RS_PER_WAVE = 512;   // keys per wave per tile
+constexpr int64_t RS_TILE = (int64_t)RS_WAVES * RS_PER_WAVE;
+
+__global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t m,
+                                                           int shift, int64_t n_tiles,
+                                                           uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t0 = blockIdx.x * RS_TILE;
+    for (int64_t i = threadIdx.x; i < RS_TILE; i += RS_THREADS) {
+        int64_t j = t0 + i;
+        if (j < m) atomicAdd(&h[(keys[j] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t* __restrict__ keys, int64_t m,
+                                                              int shift, int64_t n_tiles,
+                                                              const uint64_t* __restrict__ offs,
+                                                              uint64_t* __restrict__ out) {
+    __shared__ uint32_t wcount[RS_WAVES][256];
+    __shared__ uint32_t run[RS_WAVES][256];
+    const int w = threadIdx.x / WAVE;
+    for (int d = lane(); d < 256; d += WAVE) wcount[w][d] = 0;
+    __syncthreads();
+    const int64_t wbase = blockIdx.x * RS_TILE + (int64_t)w * RS_PER_WAVE;
+    for (int it = 0; it < RS_PER_WAVE; it += WAVE) {
+        int64_t j = wbase + it + lane();
+        if (j < m) atomicAdd(&wcount[w][(keys[j] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    // run[w][d] = tile offset of digit d + keys of digit d in earlier waves
+    for (int d = threadIdx.x; d < 256; d += RS_THREADS) {
+        uint32_t acc = 0;
+        for (int ww = 0; ww < RS_WAVES; ++ww) {
+            run[ww][d] = acc;
+            acc += wcount[ww][d];
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < RS_PER_WAVE; it += WAVE) {
+        int64_t j = wbase + it + lane();
+        bool valid = j < m;
+        uint64_t k = valid ? keys[j] : 0;
+        uint32_t d = (uint32_t)((k >> shift) & 255u);
+        uint64_t peers = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t mb = ballot(((d >> b) & 1u) != 0);
+            peers &= ((d >> b) & 1u) ? mb : ~mb;
+        }
+        uint32_t before = (uint32_t)popc64(peers & lanemask_lt());
+        uint32_t base = valid ? run[w][d] : 0;
+        if (valid) out[offs[(int64_t)d * n_tiles + blockIdx.x] + base + before] = k;
+        // the highest lane of each digit group advances the running count
+        bool last = valid && ((peers >> lane()) == 1ull);
+        if (last) run[w][d] = base + before + 1;
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+void radix_sort_u64(uint64_t* keys, uint64_t* tmp, int64_t m, int lo_bit, int hi_bit, Arena& a,
+                    hipStream_t s) {
+    if (m <= 1) return;
+    const int64_t n_tiles = (m + RS_TILE - 1) / RS_TILE;
+    size_t mk = a.mark();
+    uint32_t* hist = push<uint32_t>(a, 256 * n_tiles);
+    uint64_t* offs = push<uint64_t>(a, 256 * n_tiles + 1);
+    uint64_t* src = keys;
+    uint64_t* dst = tmp;
+    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
+        ProfScope ps("radix_sort", s, (double)m);
+        k_radix_hist<<<(unsigned)n_tiles, RS_THREADS, 0, s>>>(src, m, shift, n_tiles, hist);
+        PG_HIP(hipGetLastError());
+        scan_u32(hist, 256 * n_tiles, offs, a, s);
+        k_radix_scatter<<<(unsigned)n_tiles, RS_THREADS, 0, s>>>(src, m, shift, n_tiles, offs, dst);
+        PG_HIP(hipGetLastError());
+        std::swap(src, dst);
+    }
+    if (src != keys) PG_HIP(hipMemcpyAsync(keys, src, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
+    a.reset(mk);
+}
+
+}  // namespace pg

@@ -1,0 +1,131 @@
+"""GPU parity of k-clique counting (pg_count_cliques) against the CPU oracle.
+Exact integer counts: the bar is equality."""
+from math import comb
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_1911_06969_amd import binding, synth
+from tests.gpu_common import golden, gpu_or_skip, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return gpu_or_skip()
+
+
+def gpu_cliques(g, ks, budget=None):
+    with binding.Graph.from_csr(g) as G:
+        if budget:
+            G.set_memory_budget(budget)
+        return [G.cliques(k) for k in ks]
+
+
+def test_complete_graphs(torch):
+    for n in (1, 2, 3, 4, 7, 12, 20):
+        g = synth.complete(n)
+        say("K", n)
+        assert gpu_cliques(g, range(1, 9)) == [comb(n, k) for k in range(1, 9)]
+
+
+def test_empty_and_edge_cases(torch):
+    assert gpu_cliques(synth.empty(5), [1, 2, 3, 4]) == [5, 0, 0, 0]
+    assert gpu_cliques(synth.empty(0), [1, 3]) == [0, 0]
+    assert gpu_cliques(synth.path(2), [2, 3]) == [1, 0]
+    g = synth.disjoint_union(synth.complete(6), synth.empty(50), synth.star(30))
+    assert gpu_cliques(g, [3, 4, 5, 6]) == [comb(6, 3), comb(6, 4), comb(6, 5), 1]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_brute_force_small(torch, seed):
+    rng = np.random.default_rng(seed)
+    g = synth.gnp_small(int(rng.integers(4, 13)), float(rng.uniform(0.2, 0.9)), seed)
+    want = [brute.clique_count(g, k) for k in (3, 4, 5)]
+    assert gpu_cliques(g, (3, 4, 5)) == want
+
+
+@pytest.mark.parametrize("sizes", [[2, 3, 4], [5, 5, 5, 5], [1, 7, 2, 9, 3]])
+def test_complete_multipartite(torch, sizes):
+    import itertools
+    g = synth.complete_multipartite(sizes)
+    want = [sum(int(np.prod(c)) for c in itertools.combinations(sizes, k)) for k in (3, 4, 5)]
+    assert gpu_cliques(g, (3, 4, 5)) == want
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(9, 8, 1), (11, 16, 2), (12, 8, 3)])
+def test_rmat_against_oracle(torch, scale, ef, seed):
+    g = synth.rmat(scale, ef, seed=seed)
+    ks = (3, 4, 5, 6)
+    want = [oracle.clique_count(g, k) for k in ks]
+    say("rmat", scale, ef, want)
+    assert gpu_cliques(g, ks) == want
+
+
+def test_dense_random_spans_many_tiles(torch):
+    # sibling lists longer than one wave and than the LDS stage
+    g = synth.erdos_renyi(3000, 0.2, seed=9)
+    ks = (3, 4)
+    want = [oracle.clique_count(g, k) for k in ks]
+    assert gpu_cliques(g, ks) == want
+
+
+def test_edge_blocking_same_counts(torch):
+    """A tiny memory budget forces the embedding levels into many chunks."""
+    g = synth.rmat(12, 16, seed=4)
+    ks = (4, 5)
+    want = [oracle.clique_count(g, k) for k in ks]
+    assert gpu_cliques(g, ks, budget=1 << 20) == want
+
+
+def test_relabel_invariance(torch):
+    g = synth.rmat(11, 8, seed=5)
+    h = synth.relabel(g, np.random.default_rng(1).permutation(g.n))
+    assert gpu_cliques(g, (3, 4, 5)) == gpu_cliques(h, (3, 4, 5))
+
+
+def test_device_pointer_input(torch):
+    g = synth.rmat(10, 8, seed=6)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    col = torch.from_numpy(g.col).cuda()
+    stream = torch.cuda.current_stream()
+    with binding.Graph(rp, col, stream=stream) as G:
+        assert G.cliques(4) == oracle.clique_count(g, 4)
+
+
+def test_invalid_csr_rejected(torch):
+    bad = [
+        ([0, 1, 1], [1]),                 # not symmetric
+        ([0, 1, 2], [0, 1]),              # self-loops
+        ([0, 2, 3, 4], [2, 1, 0, 0]),     # unsorted row
+        ([0, 1, 2], [5, 0]),              # out of range
+        ([0, 2, 1], [1, 0]),              # row_ptr decreasing
+    ]
+    for rp, col in bad:
+        with pytest.raises(binding.PgError) as e:
+            binding.Graph(np.array(rp), np.array(col))
+        assert e.value.code == binding.PG_EINVAL
+
+
+def test_triangle_rmat_config(torch):
+    """R-MAT scale 14, edge factor 8 (triangle counting workload)."""
+    g = synth.triangle_rmat()
+    want = golden("full_configs.json")["triangle_rmat_s14"]
+    with binding.Graph.from_csr(g) as G:
+        assert G.cliques(3) == want["k3"]
+        assert G.cliques(4) == want["k4"]
+
+
+@pytest.mark.slow
+def test_clique_rmat_config_k4(torch):
+    """R-MAT scale 21, edge factor 13: the k-clique workload at full size."""
+    g = synth.clique_rmat()
+    want = golden("full_configs.json")["clique_rmat_s21"]
+    with binding.Graph.from_csr(g) as G:
+        say("scale-21 k=3")
+        assert G.cliques(3) == want["k3"]
+        say("scale-21 k=4")
+        assert G.cliques(4) == want["k4"]
