@@ -93,6 +93,18 @@ int pg_graph_info(const pg_graph* g, int64_t* n, int64_t* nnz, int64_t* max_degr
 int pg_set_memory_budget(pg_graph* g, uint64_t bytes);
 
 /*
+ * Per-graph switches.
+ *   PG_OPT_CLIQUE_MASKS  1 (default): 4-cliques on graphs whose DAG
+ *                        out-degree is at most 768 record each level-1
+ *                        entry's children as a bitmask over its root's
+ *                        out-list and count the last level with popcounts;
+ *                        0: the general level kernels for every k.
+ * Unknown options return PG_EINVAL.
+ */
+#define PG_OPT_CLIQUE_MASKS 1
+int pg_graph_set_option(pg_graph* g, int option, int64_t value);
+
+/*
  * Number of k-cliques (k pairwise adjacent vertices; section 2.2, with
  * triangle counting as k = 3).  Vertex-induced extension of the last vertex
  * only (eager pruning, section 4.1) on the degree-ordered DAG (section 4.1:
@@ -165,7 +177,7 @@ int pg_fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, 
  * voff is host memory (int64[n_graphs+1]) in every case; row_ptr and col are
  * device pointers when PG_DEVICE_PTRS is set.
  */
-#define PG_BATCH_MAX_VERTICES 1024
+#define PG_BATCH_MAX_VERTICES 512
 int pg_batch_load(int64_t n_graphs, const int64_t* voff, const int64_t* row_ptr,
                   const int32_t* col, unsigned flags, void* stream, pg_batch** out);
 int pg_batch_free(pg_batch* b);
@@ -180,15 +192,28 @@ int pg_batch_free(pg_batch* b);
 int pg_batch_count_motifs(pg_batch* b, int k, const int64_t* ids, int64_t n_ids, uint64_t* counts);
 
 /*
- * Asynchronous form for a serving loop: enqueues the same work on `stream`
- * and returns at once.  ids_dev (device int64[n_ids]) and counts_dev (device
- * uint64[n_ids * 6]) are caller-owned device buffers that must stay valid
- * until the stream reaches this point; the results are in counts_dev then.
- * Calls on different streams may overlap on the device; they share only the
- * read-only batch.
+ * Asynchronous slots for a serving loop.  A slot owns pinned host buffers,
+ * device buffers for up to max_ids graphs and a captured HIP graph of one
+ * batched launch (copy in, clear, count, copy out), replayed on the slot's
+ * stream for every submission.  Slots on different streams run
+ * concurrently; they share only the read-only batch.
+ *   pg_batch_slot_create  max_ids >= 1; stream: hipStream_t (NULL = null stream)
+ *   pg_batch_slot_submit  enqueues the counts of ids[0..n_ids) (host array,
+ *                         n_ids <= max_ids) and returns at once; the slot
+ *                         must be idle (PG_EINVAL otherwise)
+ *   pg_batch_slot_query   1 when the last submission has finished (or none
+ *                         is pending), 0 while it runs
+ *   pg_batch_slot_wait    waits for the last submission and copies its rows
+ *                         (n_ids x 6 for k = 4, x 2 for k = 3) to counts
+ *                         (host); the slot becomes idle
+ *   pg_batch_slot_free    waits, then releases the slot
  */
-int pg_batch_count_motifs_async(pg_batch* b, int k, const int64_t* ids_dev, int64_t n_ids,
-                                uint64_t* counts_dev, void* stream);
+typedef struct pg_batch_slot pg_batch_slot;
+int pg_batch_slot_create(pg_batch* b, int64_t max_ids, void* stream, pg_batch_slot** out);
+int pg_batch_slot_submit(pg_batch_slot* s, int k, const int64_t* ids, int64_t n_ids);
+int pg_batch_slot_query(pg_batch_slot* s);
+int pg_batch_slot_wait(pg_batch_slot* s, uint64_t* counts);
+int pg_batch_slot_free(pg_batch_slot* s);
 
 /* Estimated device work of each graph (host double[n_graphs]), the
  * quantity the batch scheduler orders graphs by. */

@@ -19,13 +19,14 @@ LIB_PATH = os.path.join(_HERE, "libpangolin_hip.so")
 PG_OK, PG_EINVAL, PG_ENOMEM, PG_EUNSUPPORTED, PG_EDEVICE, PG_EOVERFLOW = 0, -1, -2, -3, -4, -5
 PG_DEVICE_PTRS = 1
 PG_KMAX = 8
-PG_BATCH_MAX_VERTICES = 1024
+PG_BATCH_MAX_VERTICES = 512
 
 EXPORTS = (
     "pg_graph_load_csr", "pg_graph_free", "pg_graph_set_stream", "pg_graph_info",
-    "pg_set_memory_budget", "pg_count_cliques", "pg_count_motifs", "pg_fsm",
+    "pg_set_memory_budget", "pg_graph_set_option", "pg_count_cliques", "pg_count_motifs", "pg_fsm",
     "pg_fsm_num_patterns", "pg_fsm_pattern_key", "pg_batch_load", "pg_batch_free",
-    "pg_batch_count_motifs", "pg_batch_count_motifs_async", "pg_batch_work_estimate",
+    "pg_batch_count_motifs", "pg_batch_slot_create", "pg_batch_slot_submit", "pg_batch_slot_query",
+    "pg_batch_slot_wait", "pg_batch_slot_free", "pg_batch_work_estimate",
     "pg_batch_set_params", "pg_last_error", "pg_set_allocator", "pg_profile_enable",
     "pg_profile_reset", "pg_profile_query", "pg_profile_list", "pg_version",
 )
@@ -57,6 +58,7 @@ def load_library(path: str | None = None):
     lib.pg_graph_set_stream.argtypes = [ptr, ptr]
     lib.pg_graph_info.argtypes = [ptr, P(i64), P(i64), P(i64)]
     lib.pg_set_memory_budget.argtypes = [ptr, u64]
+    lib.pg_graph_set_option.argtypes = [ptr, cint, i64]
     lib.pg_count_cliques.argtypes = [ptr, cint, P(u64)]
     lib.pg_count_motifs.argtypes = [ptr, cint, ptr]
     lib.pg_fsm.argtypes = [ptr, cint, u64, ptr, sz, P(sz)]
@@ -66,7 +68,11 @@ def load_library(path: str | None = None):
     lib.pg_batch_load.argtypes = [i64, ptr, ptr, ptr, ctypes.c_uint, ptr, P(ptr)]
     lib.pg_batch_free.argtypes = [ptr]
     lib.pg_batch_count_motifs.argtypes = [ptr, cint, ptr, i64, ptr]
-    lib.pg_batch_count_motifs_async.argtypes = [ptr, cint, ptr, i64, ptr, ptr]
+    lib.pg_batch_slot_create.argtypes = [ptr, i64, ptr, P(ptr)]
+    lib.pg_batch_slot_submit.argtypes = [ptr, cint, ptr, i64]
+    lib.pg_batch_slot_query.argtypes = [ptr]
+    lib.pg_batch_slot_wait.argtypes = [ptr, ptr]
+    lib.pg_batch_slot_free.argtypes = [ptr]
     lib.pg_batch_work_estimate.argtypes = [ptr, ptr]
     lib.pg_batch_set_params.argtypes = [ptr, cint, ctypes.c_double, cint]
     lib.pg_last_error.restype = ctypes.c_char_p
@@ -162,6 +168,13 @@ def pg_set_memory_budget(g, nbytes: int) -> None:
     _check(load_library().pg_set_memory_budget(g, int(nbytes)))
 
 
+PG_OPT_CLIQUE_MASKS = 1
+
+
+def pg_graph_set_option(g, option: int, value: int) -> None:
+    _check(load_library().pg_graph_set_option(g, int(option), int(value)))
+
+
 def pg_count_cliques(g, k: int) -> int:
     c = ctypes.c_uint64()
     _check(load_library().pg_count_cliques(g, int(k), ctypes.byref(c)))
@@ -236,12 +249,35 @@ def pg_batch_count_motifs(b, k: int, ids=None, n_graphs: int | None = None) -> n
     return out
 
 
-def pg_batch_count_motifs_async(b, k: int, ids_dev, counts_dev, stream) -> None:
-    """ids_dev: int64 GPU tensor; counts_dev: uint64/int64 GPU tensor with
-    6 (k=4) or 2 (k=3) entries per id."""
-    lib = load_library()
-    _check(lib.pg_batch_count_motifs_async(b, int(k), ctypes.c_void_p(ids_dev.data_ptr()), ids_dev.shape[0],
-                                           ctypes.c_void_p(counts_dev.data_ptr()), _stream_ptr(stream)))
+def pg_batch_slot_create(b, max_ids: int, stream=None):
+    out = ctypes.c_void_p()
+    _check(load_library().pg_batch_slot_create(b, int(max_ids), _stream_ptr(stream), ctypes.byref(out)))
+    return out
+
+
+def pg_batch_slot_submit(slot, k: int, ids) -> int:
+    """Enqueues the counts of ids (host int64 array); returns the number of
+    ids submitted.  The id array is copied before the call returns."""
+    idv, pid = _host(ids, np.int64)
+    _check(load_library().pg_batch_slot_submit(slot, int(k), pid, idv.shape[0]))
+    return int(idv.shape[0])
+
+
+def pg_batch_slot_query(slot) -> bool:
+    rc = load_library().pg_batch_slot_query(slot)
+    if rc < 0:
+        _check(rc)
+    return rc == 1
+
+
+def pg_batch_slot_wait(slot, n_ids: int, k: int = 4) -> np.ndarray:
+    out = np.zeros((max(n_ids, 1), 2 if k == 3 else 6), dtype=np.uint64)
+    _check(load_library().pg_batch_slot_wait(slot, ctypes.c_void_p(out.ctypes.data)))
+    return out[:n_ids]
+
+
+def pg_batch_slot_free(slot) -> None:
+    _check(load_library().pg_batch_slot_free(slot))
 
 
 def pg_batch_work_estimate(b, n_graphs: int) -> np.ndarray:
@@ -311,6 +347,9 @@ class Graph:
 
     def set_memory_budget(self, nbytes: int) -> None:
         pg_set_memory_budget(self.h, nbytes)
+
+    def set_option(self, option: int, value: int) -> None:
+        pg_graph_set_option(self.h, option, value)
 
     def close(self) -> None:
         if self.h is not None:

@@ -133,6 +133,16 @@ int pg_set_memory_budget(pg_graph* g, uint64_t bytes) {
     });
 }
 
+int pg_graph_set_option(pg_graph* g, int option, int64_t value) {
+    return guarded([&] {
+        PG_REQUIRE(g != nullptr, PG_EINVAL, "graph is NULL");
+        switch (option) {
+            case PG_OPT_CLIQUE_MASKS: g->force_generic = (value == 0); break;
+            default: throw Error{PG_EINVAL, "unknown option " + std::to_string(option)};
+        }
+    });
+}
+
 int pg_count_cliques(pg_graph* g, int k, uint64_t* count) {
     return guarded([&] {
         PG_REQUIRE(g != nullptr && count != nullptr, PG_EINVAL, "NULL argument");

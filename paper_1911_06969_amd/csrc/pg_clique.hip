@@ -334,6 +334,282 @@ static void extend_level(CliqueRun& R, int lev, const int64_t* seg, int64_t seg_
     ar.reset(mk);
 }
 
+// ---------------------------------------------------------------------
+// 4-cliques with per-root sibling masks.
+//
+// Every level-2 sibling list (the children of an edge (r, v1)) is a subset
+// of out(r).  So the count pass over the out-list of root r records, for
+// each of r's level-1 entries i, its children as a bitmask over the
+// positions of out(r) (row i of r's mask block) together with their number.
+// The write pass emits the level-2 structure of arrays (idx = parent entry,
+// vid = vertex, and the vertex's position in out(r), a memo of the
+// connectivity test) from the masks.  The fused last level then counts, for
+// every level-2 entry (r, v1, w) at positions i1, j, the common later
+// neighbours of r, v1 and w as popcount(row i1 AND row j): bits of row j are
+// positions above j, so every 4-clique is counted once.
+
+constexpr int BM_MAXD = 768;             // roots with out-degree up to this use masks
+constexpr int BM_W = BM_MAXD / 64;       // 64-bit words per mask row
+
+struct BmLds {
+    int32_t S[CQ_WAVES][BM_MAXD];
+    uint64_t rows[CQ_WAVES][WAVE][BM_W];
+    uint32_t pre[CQ_WAVES][WAVE];
+    int64_t lo[CQ_WAVES][WAVE];
+};
+
+struct BmArgs {
+    XcdQueue Q;
+    const int64_t* rp;          // DAG
+    const int32_t* col;
+    const uint64_t* moff;       // first mask word of each root
+    uint64_t* M;                // mask rows
+    uint32_t* count;            // children of each level-1 entry
+};
+
+// count pass: one wave per root; a round takes 64 of its entries, streams
+// their out-lists (cut at the root's last out-neighbour) and sets the bit of
+// every candidate found in out(r) (binary search in the LDS copy)
+__global__ __launch_bounds__(CQ_THREADS) void k_clique_count_masks(BmArgs A) {
+    __shared__ BmLds L;
+    const int w = threadIdx.x / WAVE;
+    QueueCursor cur = queue_start();
+    int64_t it_end = 0;
+    for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
+        for (int64_t r = it; r < it_end; ++r) {
+            const int64_t b = A.rp[r];
+            const int32_t d = (int32_t)(A.rp[r + 1] - b);
+            if (d < 2) continue;   // counts are pre-zeroed; rows are never read
+            const int W = (d + 63) >> 6;
+            for (int i = lane(); i < d; i += WAVE) L.S[w][i] = A.col[b + i];
+            wave_sync();
+            const int32_t s_last = L.S[w][d - 1];
+            for (int32_t xc = 0; xc < d; xc += WAVE) {
+                const int32_t x = xc + lane();
+                int64_t lo = 0;
+                uint32_t dd = 0;
+                if (x < d - 1) {
+                    const int32_t v = L.S[w][x];
+                    const int64_t r0 = A.rp[v], r1 = A.rp[v + 1];
+                    const int64_t hi = (r1 - r0 >= CQ_TRIM_MIN) ? upper_bound(A.col, r0, r1, s_last) : r1;
+                    lo = r0;
+                    dd = (uint32_t)(hi - r0);
+                }
+                const uint32_t inc = wave_incl_scan(dd);
+                const uint32_t Wt = bcast(inc, WAVE - 1);
+                L.pre[w][lane()] = inc - dd;
+                L.lo[w][lane()] = lo;
+#pragma unroll
+                for (int q = 0; q < BM_W; ++q) L.rows[w][lane()][q] = 0;
+                wave_sync();
+                const int nx = min(WAVE, d - xc);
+                for (uint32_t t0 = 0; t0 < Wt; t0 += WAVE) {
+                    const uint32_t t = t0 + lane();
+                    if (t < Wt) {
+                        int xi = 0;
+                        int n_i = nx;
+                        while (n_i > 1) {
+                            const int half = n_i >> 1;
+                            if (L.pre[w][xi + half] <= t) xi += half;
+                            n_i -= half;
+                        }
+                        const int32_t u = A.col[L.lo[w][xi] + (t - L.pre[w][xi])];
+                        // position of u among the later out-neighbours of r
+                        const int32_t after = xc + xi + 1;
+                        int32_t base = after, len = d - after;
+                        while (len > 1) {
+                            const int32_t half = len >> 1;
+                            base = (L.S[w][base + half] <= u) ? base + half : base;
+                            len -= half;
+                        }
+                        if (len == 1 && L.S[w][base] == u)
+                            atomicOr((unsigned long long*)&L.rows[w][xi][base >> 6], 1ull << (base & 63));
+                    }
+                }
+                wave_sync();
+                // counts, then the rows to HBM (word t of the round's block per lane)
+                if (x < d) {
+                    uint32_t c = 0;
+                    for (int q = 0; q < W; ++q) c += (uint32_t)__popcll(L.rows[w][lane()][q]);
+                    A.count[b + x] = c;
+                }
+                const int rows_here = min(WAVE, d - xc);
+                uint64_t* dst = A.M + A.moff[r] + (uint64_t)xc * W;
+                for (int q = lane(); q < rows_here * W; q += WAVE) dst[q] = L.rows[w][q / W][q % W];
+                wave_sync();
+            }
+        }
+    }
+}
+
+// write pass: one thread per level-1 entry of the chunk emits its children
+__global__ __launch_bounds__(256) void k_clique_write_masks(int64_t e_lo, int64_t e_hi, const int64_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ col,
+                                                            const int32_t* __restrict__ src,
+                                                            const uint64_t* __restrict__ moff,
+                                                            const uint64_t* __restrict__ M,
+                                                            const uint64_t* __restrict__ start, uint64_t start_base,
+                                                            int32_t* __restrict__ out_idx, int32_t* __restrict__ out_vid,
+                                                            uint16_t* __restrict__ out_pos) {
+    for (int64_t e = e_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e_hi;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t pos = start[e] - start_base;
+        const uint64_t end = start[e + 1] - start_base;
+        if (pos == end) continue;
+        const int32_t r = src[e];
+        const int64_t b = rp[r];
+        const int32_t d = (int32_t)(rp[r + 1] - b);
+        const int W = (d + 63) >> 6;
+        const int32_t i = (int32_t)(e - b);
+        const uint64_t* row = M + moff[r] + (uint64_t)i * W;
+        for (int q = 0; q < W; ++q) {
+            uint64_t bits = row[q];
+            while (bits) {
+                const int j = q * 64 + __ffsll((unsigned long long)bits) - 1;
+                bits &= bits - 1;
+                out_idx[pos] = (int32_t)e;
+                out_vid[pos] = col[b + j];
+                out_pos[pos] = (uint16_t)j;
+                ++pos;
+            }
+        }
+    }
+}
+
+// fused last level: one thread per level-2 entry
+__global__ __launch_bounds__(256) void k_clique_last_masks(int64_t m, const int32_t* __restrict__ idx,
+                                                           const uint16_t* __restrict__ pos,
+                                                           const int32_t* __restrict__ vid,
+                                                           const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ src,
+                                                           const uint64_t* __restrict__ moff,
+                                                           const uint64_t* __restrict__ M,
+                                                           unsigned long long* __restrict__ stats) {
+    uint64_t found = 0, deg_sum = 0;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < m; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = idx[x];
+        const int32_t r = src[e];
+        const int64_t b = rp[r];
+        const int32_t d = (int32_t)(rp[r + 1] - b);
+        const int W = (d + 63) >> 6;
+        const uint64_t* blk = M + moff[r];
+        const uint64_t* r1 = blk + (uint64_t)(e - b) * W;
+        const uint64_t* r2 = blk + (uint64_t)pos[x] * W;
+        for (int q = 0; q < W; ++q) found += (uint64_t)__popcll(r1[q] & r2[q]);
+        const int32_t v = vid[x];
+        deg_sum += (uint64_t)(rp[v + 1] - rp[v]);
+    }
+    found = wave_sum_u64(found);
+    deg_sum = wave_sum_u64(deg_sum);
+    if (lane() == 0 && (found | deg_sum)) {
+        atomicAdd(&stats[0], (unsigned long long)found);
+        atomicAdd(&stats[2], (unsigned long long)deg_sum);
+    }
+}
+
+__global__ void k_mask_words(int64_t n, const int64_t* __restrict__ rp, uint32_t* __restrict__ words) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = rp[r + 1] - rp[r];
+        words[r] = (uint32_t)(d * ((d + 63) >> 6));
+    }
+}
+
+static unsigned grid_threads(int64_t items) {
+    int64_t b = (items + 255) / 256;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)device_info().n_cu * 32));
+}
+
+static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
+    hipStream_t s = R.s;
+    Arena& ar = g->arena;
+    const int64_t n = g->n;
+    const int64_t E = g->dag.n_edges;
+    const int64_t* rp = g->dag.rp.as<int64_t>();
+    const int32_t* col = g->dag.col.as<int32_t>();
+    const int32_t* src = g->dag.src.as<int32_t>();
+    // mask block offsets
+    uint64_t* moff = push<uint64_t>(ar, n + 1);
+    {
+        const size_t mk = ar.mark();
+        uint32_t* words = push<uint32_t>(ar, n);
+        k_mask_words<<<grid_threads(n), 256, 0, s>>>(n, rp, words);
+        PG_HIP(hipGetLastError());
+        scan_u32(words, n, moff, ar, s);
+        ar.reset(mk);
+    }
+    const uint64_t mwords = read_u64(moff + n, s);
+    uint64_t* M = push<uint64_t>(ar, std::max<uint64_t>(mwords, 1));
+    uint32_t* cnt = push<uint32_t>(ar, E);
+    uint64_t* start = push<uint64_t>(ar, E + 1);
+    fill_u32(cnt, E, 0, s);
+    {
+        BmArgs A;
+        fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, s);
+        A.Q.next = R.qctr;
+        A.Q.n_items = n;
+        A.Q.chunk = n >= R.waves * 64 ? 16 : 1;
+        A.rp = rp;
+        A.col = col;
+        A.moff = moff;
+        A.M = M;
+        A.count = cnt;
+        ProfScope ps("clique_count", s, (double)E);
+        k_clique_count_masks<<<R.blocks, CQ_THREADS, 0, s>>>(A);
+        PG_HIP(hipGetLastError());
+    }
+    scan_u32(cnt, E, start, ar, s);
+    const uint64_t total = read_u64(start + E, s);
+    if (total == 0) return 0;
+    // edge blocking over level-1 entries: 10 bytes per level-2 entry
+    const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
+    const uint64_t cap = std::max<uint64_t>(room / 10, (uint64_t)g->dag.max_out + 1);
+    const int64_t nb = (int64_t)((total + cap - 1) / cap);
+    std::vector<int64_t> hc(nb + 1), hp(nb + 1);
+    std::vector<uint64_t> hs(nb + 1);
+    if (nb == 1) {
+        hc[0] = 0; hc[1] = E;
+        hs[0] = 0; hs[1] = total;
+    } else {
+        const size_t mk2 = ar.mark();
+        int64_t* dc = push<int64_t>(ar, nb + 1);
+        int64_t* dp = push<int64_t>(ar, nb + 1);
+        uint64_t* ds = push<uint64_t>(ar, nb + 1);
+        k_chunk_bounds<<<(unsigned)((nb + 1 + 255) / 256), 256, 0, s>>>(start, E, cap, nb, rp, 0, n, dc, dp, ds);
+        PG_HIP(hipGetLastError());
+        PG_HIP(hipMemcpyAsync(hc.data(), dc, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipMemcpyAsync(hs.data(), ds, sizeof(uint64_t) * (nb + 1), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        ar.reset(mk2);
+    }
+    uint64_t biggest = 0;
+    for (int64_t j = 0; j < nb; ++j) biggest = std::max<uint64_t>(biggest, hs[j + 1] - hs[j]);
+    int32_t* l2_idx = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
+    int32_t* l2_vid = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
+    uint16_t* l2_pos = push<uint16_t>(ar, std::max<uint64_t>(biggest, 1));
+    for (int64_t j = 0; j < nb; ++j) {
+        const int64_t c0 = hc[j], c1 = hc[j + 1];
+        const uint64_t m2 = hs[j + 1] - hs[j];
+        if (c1 <= c0 || m2 == 0) continue;
+        {
+            ProfScope ps("clique_write", s, (double)m2);
+            k_clique_write_masks<<<grid_threads(c1 - c0), 256, 0, s>>>(c0, c1, rp, col, src, moff, M, start, hs[j],
+                                                                       l2_idx, l2_vid, l2_pos);
+            PG_HIP(hipGetLastError());
+        }
+        {
+            ProfScope ps("clique_last", s, 0.0);
+            k_clique_last_masks<<<grid_threads((int64_t)m2), 256, 0, s>>>((int64_t)m2, l2_idx, l2_pos, l2_vid, rp,
+                                                                          src, moff, M, R.stats);
+            PG_HIP(hipGetLastError());
+        }
+    }
+    // input entries of the last level
+    const uint64_t n2 = total;
+    PG_HIP(hipMemcpyAsync(R.stats + 1, &n2, sizeof(n2), hipMemcpyHostToDevice, s));
+    PG_HIP(hipStreamSynchronize(s));
+    return 0;
+}
+
 uint64_t count_cliques(pg_graph* g, int k) {
     PG_REQUIRE(k >= 1 && k <= PG_KMAX, PG_EUNSUPPORTED, "k must be in [1, PG_KMAX]");
     if (k == 1) return (uint64_t)g->n;
@@ -352,8 +628,12 @@ uint64_t count_cliques(pg_graph* g, int k) {
     R.stats = reinterpret_cast<unsigned long long*>(small);
     R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
     fill_u64(small, 8, 0, s);
-    // level L1: entries = DAG edges, parents = vertices (segment = out-list)
-    extend_level(R, 1, g->dag.rp.as<int64_t>(), 0, 0, g->n, g->dag.col.as<int32_t>(), 0, g->dag.n_edges);
+    if (k == 4 && g->dag.max_out <= BM_MAXD && !g->force_generic) {
+        count_cliques4_masks(g, R);
+    } else {
+        // level L1: entries = DAG edges, parents = vertices (segment = out-list)
+        extend_level(R, 1, g->dag.rp.as<int64_t>(), 0, 0, g->n, g->dag.col.as<int32_t>(), 0, g->dag.n_edges);
+    }
     uint64_t st[3] = {0, 0, 0};
     PG_HIP(hipMemcpyAsync(st, small, sizeof(st), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));

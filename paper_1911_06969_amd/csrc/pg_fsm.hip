@@ -1,13 +1,653 @@
-// Frequent subgraph mining (placeholder until the kernels land).
+// Frequent subgraph mining with minimum-image (domain) support, edge-induced
+// embeddings of up to three edges over a vertex-labelled graph (Pangolin
+// sections 2.1-2.2, 3.3 FSM Listing, 5.3).
+//
+// Levels (Algorithm 1 with Reduce and Filter on, also right after Init):
+//   L1  every edge e = (u < v), identified by its rank in (u, v) order;
+//   Reduce L1, Filter L1 -> frequent edges;
+//   L2  (e1, e2): count / scan / write from the frequent edges, each entry
+//       storing its pattern id (memoisation, section 4.2);
+//   Reduce L2, Filter L2 -> frequent wedges;
+//   L3  generated from the frequent wedges and reduced on the fly (the last
+//       level is never stored).
+//
+// Canonical test (isAutoCanonical for edge extension).  An embedding is kept
+// only in greedy order: g1 is its smallest edge, then repeatedly the
+// smallest remaining edge adjacent to those chosen.  Extending a greedy
+// sequence (g1..gj) by an edge e keeps it greedy iff e is adjacent to the
+// chosen edges, e > g1, and e > g_i for every i >= 2 such that e is adjacent
+// to g1..g_{i-1}.
+//
+// Patterns are numbered by the dense index of the public header (shape,
+// then labels); their vertices fall in orbits (vertices swapped by a
+// label-preserving automorphism).  The domain of an orbit is the set of
+// graph vertices any embedding places in it; the support of a pattern is
+// the smallest orbit domain, which equals the minimum-image support over all
+// subgraph isomorphisms.
+//
+// Reduce.  A histogram of embeddings per pattern bounds each support
+// (support <= embeddings x largest orbit), so bitmaps are kept only for
+// patterns that can reach the threshold; every embedding sets the bits of
+// its vertices in its pattern's orbit bitmaps (one bit per graph vertex),
+// and popcounts give the domain sizes.  When the bitmaps of one level do not
+// fit the memory budget, the candidate patterns are processed in groups.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "pg_device.h"
 #include "pg_internal.h"
 
 namespace pg {
+
+// ----------------------------------------------------- pattern numbering
+
+struct PatBase {
+    int64_t L;
+    int64_t p2, t3, paths;
+    int64_t edge, wedge, tri, path, star, total;
+};
+
+__host__ __device__ inline PatBase pat_base(int64_t L, int max_edges) {
+    PatBase B;
+    B.L = L;
+    B.p2 = L * (L + 1) / 2;
+    B.t3 = L * (L + 1) * (L + 2) / 6;
+    B.paths = (L * L * L * L + L * L) / 2;
+    B.edge = 0;
+    B.wedge = B.p2;
+    B.tri = B.wedge + L * B.p2;
+    B.path = B.tri + B.t3;
+    B.star = B.path + B.paths;
+    B.total = max_edges >= 3 ? B.star + L * B.t3 : (max_edges == 2 ? B.tri : B.p2);
+    return B;
+}
+
+// rank of a <= b among label pairs in lexicographic order
+__host__ __device__ inline int64_t pair_rank(int64_t a, int64_t b, int64_t L) {
+    return a * L - a * (a - 1) / 2 + (b - a);
+}
+
+// rank of a <= b <= c among sorted label triples in lexicographic order
+__host__ __device__ inline int64_t triple_rank(int64_t a, int64_t b, int64_t c, int64_t L) {
+    int64_t r = 0;
+    for (int64_t x = 0; x < a; ++x) r += (L - x) * (L - x + 1) / 2;
+    for (int64_t y = a; y < b; ++y) r += L - y;
+    return r + (c - b);
+}
+
 uint64_t fsm_num_patterns(int max_edges, int n_labels) {
-    (void)max_edges; (void)n_labels;
-    return 0;
+    if (max_edges < 1 || max_edges > 3 || n_labels < 1) return 0;
+    return (uint64_t)pat_base(n_labels, max_edges).total;
 }
-int fsm_pattern_key(uint64_t, int, int, int*, int32_t*) { return PG_EUNSUPPORTED; }
-void run_fsm(pg_graph*, int, uint64_t, uint64_t*, size_t, size_t*) {
-    throw Error{PG_EUNSUPPORTED, "FSM not built yet"};
+
+int fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* lab) {
+    const PatBase B = pat_base(n_labels, max_edges);
+    const int64_t L = n_labels;
+    int64_t i = (int64_t)index;
+    for (int j = 0; j < 4; ++j) lab[j] = -1;
+    auto pair_of = [&](int64_t r, int32_t* out) {
+        for (int64_t a = 0; a < L; ++a)
+            for (int64_t b = a; b < L; ++b)
+                if (pair_rank(a, b, L) == r) { out[0] = (int32_t)a; out[1] = (int32_t)b; return; }
+    };
+    auto triple_of = [&](int64_t r, int32_t* out) {
+        for (int64_t a = 0; a < L; ++a)
+            for (int64_t b = a; b < L; ++b)
+                for (int64_t c = b; c < L; ++c)
+                    if (triple_rank(a, b, c, L) == r) { out[0] = (int32_t)a; out[1] = (int32_t)b; out[2] = (int32_t)c; return; }
+    };
+    if (i < B.wedge) { *shape = 0; pair_of(i, lab); return PG_OK; }
+    if (i < B.tri) {
+        *shape = 1;
+        const int64_t r = i - B.wedge;
+        lab[0] = (int32_t)(r / B.p2);
+        pair_of(r % B.p2, lab + 1);
+        return PG_OK;
+    }
+    if (i < B.path) { *shape = 2; triple_of(i - B.tri, lab); return PG_OK; }
+    if (i < B.star) {
+        *shape = 3;
+        int64_t r = i - B.path;
+        for (int64_t x = 0; x < L * L * L * L; ++x) {
+            const int64_t a = x / (L * L * L), b = (x / (L * L)) % L, c = (x / L) % L, d = x % L;
+            const int64_t rev = ((d * L + c) * L + b) * L + a;
+            if (x <= rev) {
+                if (r == 0) { lab[0] = (int32_t)a; lab[1] = (int32_t)b; lab[2] = (int32_t)c; lab[3] = (int32_t)d; return PG_OK; }
+                --r;
+            }
+        }
+        return PG_EINVAL;
+    }
+    *shape = 4;
+    const int64_t r = i - B.star;
+    lab[0] = (int32_t)(r / B.t3);
+    triple_of(r % B.t3, lab + 1);
+    return PG_OK;
 }
+
+// ------------------------------------------------------ device classifiers
+
+struct FsmCtx {
+    const int64_t* rp;
+    const int32_t* col;
+    const int32_t* eid;      // undirected edge id of every CSR entry
+    const int32_t* esrc;     // edge -> smaller endpoint
+    const int32_t* edst;     // edge -> larger endpoint
+    const int32_t* lab;
+    const int32_t* path_rank;   // rank of every canonical label sequence of a path
+    PatBase B;
+};
+
+struct Emb {
+    int32_t pid;
+    int nv;
+    int32_t v[4];
+    int8_t orb[4];
+};
+
+__device__ __forceinline__ void sort3(int32_t& a, int32_t& b, int32_t& c) {
+    if (a > b) { int32_t t = a; a = b; b = t; }
+    if (b > c) { int32_t t = b; b = c; c = t; }
+    if (a > b) { int32_t t = a; a = b; b = t; }
+}
+
+// single edge (u, v)
+__device__ __forceinline__ Emb classify_edge(const FsmCtx& C, int32_t u, int32_t v) {
+    Emb E;
+    const int32_t lu = C.lab[u], lv = C.lab[v];
+    const int32_t a = min(lu, lv), b = max(lu, lv);
+    E.pid = (int32_t)(C.B.edge + pair_rank(a, b, C.B.L));
+    E.nv = 2;
+    E.v[0] = u; E.v[1] = v;
+    // equal labels: one orbit; otherwise the smaller label is orbit 0
+    E.orb[0] = (lu == a) ? 0 : 1;
+    E.orb[1] = (lv == a) ? 0 : 1;
+    return E;
+}
+
+// wedge: centre s, leaves o and t
+__device__ __forceinline__ Emb classify_wedge(const FsmCtx& C, int32_t s, int32_t o, int32_t t) {
+    Emb E;
+    const int32_t ls = C.lab[s], lo = C.lab[o], lt = C.lab[t];
+    const int32_t a = min(lo, lt), b = max(lo, lt);
+    E.pid = (int32_t)(C.B.wedge + (int64_t)ls * C.B.p2 + pair_rank(a, b, C.B.L));
+    E.nv = 3;
+    E.v[0] = s; E.v[1] = o; E.v[2] = t;
+    // centre: orbit 0; leaves: one orbit if their labels agree, else the
+    // smaller label is orbit 1
+    E.orb[0] = 0;
+    E.orb[1] = (lo == a) ? 1 : 2;
+    E.orb[2] = (lt == a) ? 1 : 2;
+    return E;
+}
+
+__device__ __forceinline__ Emb classify_triangle(const FsmCtx& C, int32_t x, int32_t y, int32_t z) {
+    Emb E;
+    int32_t l[3] = {C.lab[x], C.lab[y], C.lab[z]};
+    int32_t a = l[0], b = l[1], c = l[2];
+    sort3(a, b, c);
+    E.pid = (int32_t)(C.B.tri + triple_rank(a, b, c, C.B.L));
+    E.nv = 3;
+    E.v[0] = x; E.v[1] = y; E.v[2] = z;
+    for (int i = 0; i < 3; ++i) E.orb[i] = (l[i] == a) ? 0 : ((l[i] == b) ? 1 : 2);
+    return E;
+}
+
+// star: centre s, leaves p, q, r
+__device__ __forceinline__ Emb classify_star(const FsmCtx& C, int32_t s, int32_t p, int32_t q, int32_t r) {
+    Emb E;
+    int32_t l[3] = {C.lab[p], C.lab[q], C.lab[r]};
+    int32_t a = l[0], b = l[1], c = l[2];
+    sort3(a, b, c);
+    E.pid = (int32_t)(C.B.star + (int64_t)C.lab[s] * C.B.t3 + triple_rank(a, b, c, C.B.L));
+    E.nv = 4;
+    E.v[0] = s; E.v[1] = p; E.v[2] = q; E.v[3] = r;
+    E.orb[0] = 0;
+    for (int i = 0; i < 3; ++i) E.orb[i + 1] = 1 + ((l[i] == a) ? 0 : ((l[i] == b) ? 1 : 2));
+    return E;
+}
+
+// path w0 - w1 - w2 - w3
+__device__ __forceinline__ Emb classify_path(const FsmCtx& C, int32_t w0, int32_t w1, int32_t w2, int32_t w3) {
+    Emb E;
+    const int64_t L = C.B.L;
+    const int32_t l0 = C.lab[w0], l1 = C.lab[w1], l2 = C.lab[w2], l3 = C.lab[w3];
+    const int64_t f = ((int64_t)(l0 * L + l1) * L + l2) * L + l3;
+    const int64_t r = ((int64_t)(l3 * L + l2) * L + l1) * L + l0;
+    E.pid = (int32_t)(C.B.path + C.path_rank[f <= r ? f : r]);
+    E.nv = 4;
+    E.v[0] = w0; E.v[1] = w1; E.v[2] = w2; E.v[3] = w3;
+    if (f == r) {
+        E.orb[0] = 0; E.orb[1] = 1; E.orb[2] = 1; E.orb[3] = 0;
+    } else if (f < r) {
+        E.orb[0] = 0; E.orb[1] = 1; E.orb[2] = 2; E.orb[3] = 3;
+    } else {
+        E.orb[0] = 3; E.orb[1] = 2; E.orb[2] = 1; E.orb[3] = 0;
+    }
+    return E;
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ void k_path_flags(int64_t L, uint32_t* __restrict__ flag) {
+    const int64_t N = L * L * L * L;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = x / (L * L * L), b = (x / (L * L)) % L, c = (x / L) % L, d = x % L;
+        const int64_t rev = ((d * L + c) * L + b) * L + a;
+        flag[x] = x <= rev ? 1u : 0u;
+    }
+}
+
+__global__ void k_u64_to_i32(int64_t n, const uint64_t* __restrict__ in, int32_t* __restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (int32_t)in[i];
+}
+
+// undirected edge id of every CSR entry: entry (u, w) with w > u is edge
+// seg[u] + its position among u's larger neighbours; w < u takes the id of
+// the mirrored entry.
+__global__ __launch_bounds__(256) void k_edge_ids(int64_t n, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const int64_t* __restrict__ seg, int32_t* __restrict__ eid) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t u = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; u < n; u += waves) {
+        const int64_t r0 = rp[u], r1 = rp[u + 1];
+        const int64_t up_u = r1 - (seg[u + 1] - seg[u]);   // first entry above u
+        for (int64_t j = r0 + lane(); j < r1; j += WAVE) {
+            const int32_t w = col[j];
+            if (w > u) {
+                eid[j] = (int32_t)(seg[u] + (j - up_u));
+            } else {
+                const int64_t q1 = rp[w + 1];
+                const int64_t up_w = q1 - (seg[w + 1] - seg[w]);
+                const int64_t pos = lower_bound(col, up_w, q1, (int32_t)u);
+                eid[j] = (int32_t)(seg[w] + (pos - up_w));
+            }
+        }
+    }
+}
+
+__global__ void k_hist(int64_t m, const int32_t* __restrict__ pid, uint32_t* __restrict__ counts) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&counts[pid[i]], 1u);
+}
+
+// candidate flag: the pattern has enough embeddings to possibly reach sigma
+__global__ void k_candidates(int64_t np, int64_t p_lo, const uint32_t* __restrict__ counts, PatBase B,
+                             uint64_t sigma, uint32_t* __restrict__ flag) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = p + p_lo;   // dense index: triangles and stars have orbits of up to 3 vertices
+        const uint64_t maxorb = (q >= B.tri && q < B.path) || q >= B.star ? 3 : 2;
+        flag[p] = (counts[p] > 0 && (uint64_t)counts[p] * maxorb >= sigma) ? 1u : 0u;
+    }
+}
+
+__global__ void k_slots(int64_t np, const uint32_t* __restrict__ flag, const uint64_t* __restrict__ pos,
+                        int32_t* __restrict__ slot, int32_t* __restrict__ pid_of_slot) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+        if (flag[p]) {
+            slot[p] = (int32_t)pos[p];
+            pid_of_slot[pos[p]] = (int32_t)p;
+        } else {
+            slot[p] = -1;
+        }
+    }
+}
+
+struct Bits {
+    uint32_t* bm;          // [slot - s_lo][orbit][word]
+    int64_t words;         // words per bitmap
+    const int32_t* slot;   // pattern -> slot or -1
+    int32_t s_lo, s_hi;    // slots of this group
+};
+
+__device__ __forceinline__ void set_bits(const Bits& Bt, const Emb& E) {
+    const int32_t sl = Bt.slot[E.pid];
+    if (sl < Bt.s_lo || sl >= Bt.s_hi) return;
+    uint32_t* base = Bt.bm + (int64_t)(sl - Bt.s_lo) * 4 * Bt.words;
+    for (int i = 0; i < E.nv; ++i) {
+        const uint32_t v = (uint32_t)E.v[i];
+        atomicOr(base + E.orb[i] * Bt.words + (v >> 5), 1u << (v & 31));
+    }
+}
+
+// level 1: patterns of every edge, or domain bits
+template <bool BITS>
+__global__ void k_fsm_l1(FsmCtx C, int64_t E, int32_t* __restrict__ pid, Bits Bt) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+        const Emb Em = classify_edge(C, C.esrc[e], C.edst[e]);
+        if (BITS) set_bits(Bt, Em);
+        else pid[e] = Em.pid;
+    }
+}
+
+// stream compaction by a frequent flag on the entries' pattern
+__global__ void k_keep_flags(int64_t m, const int32_t* __restrict__ pid, const uint8_t* __restrict__ freq,
+                             uint32_t* __restrict__ keep) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        keep[i] = freq[pid[i]] ? 1u : 0u;
+}
+
+__global__ void k_compact2(int64_t m, const uint32_t* __restrict__ keep, const uint64_t* __restrict__ pos,
+                           const int32_t* __restrict__ a, const int32_t* __restrict__ b, int32_t* __restrict__ oa,
+                           int32_t* __restrict__ ob) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        if (keep[i]) {
+            oa[pos[i]] = a ? a[i] : (int32_t)i;
+            if (b) ob[pos[i]] = b[i];
+        }
+}
+
+// level 2 from frequent edges: COUNT children, or WRITE (e1, e2, pid)
+template <bool WRITE>
+__global__ void k_fsm_l2(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, uint32_t* __restrict__ cnt,
+                         const uint64_t* __restrict__ start, int32_t* __restrict__ o1, int32_t* __restrict__ o2,
+                         int32_t* __restrict__ opid) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e1 = e1s[i];
+        const int32_t a = C.esrc[e1], b = C.edst[e1];
+        uint64_t pos = WRITE ? start[i] : 0;
+        uint32_t c = 0;
+        for (int side = 0; side < 2; ++side) {
+            const int32_t s = side ? b : a, o = side ? a : b;
+            for (int64_t j = C.rp[s]; j < C.rp[s + 1]; ++j) {
+                const int32_t e = C.eid[j];
+                if (e <= e1) continue;       // canonical: e > g1 (and e != e1)
+                if (WRITE) {
+                    const Emb Em = classify_wedge(C, s, o, C.col[j]);
+                    o1[pos] = e1;
+                    o2[pos] = e;
+                    opid[pos] = Em.pid;
+                    ++pos;
+                } else {
+                    ++c;
+                }
+            }
+        }
+        if (!WRITE) cnt[i] = c;
+    }
+}
+
+// level 3 from frequent wedges, fused with Reduce: histogram or domain bits
+template <bool BITS>
+__global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, const int32_t* __restrict__ e2s,
+                         uint32_t* __restrict__ counts, Bits Bt, unsigned long long* __restrict__ n_emb) {
+    uint64_t local = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e1 = e1s[i], e2 = e2s[i];
+        const int32_t a = C.esrc[e1], b = C.edst[e1], c = C.esrc[e2], d = C.edst[e2];
+        // shared vertex s; o = other end of e1; t = other end of e2
+        const int32_t s = (a == c || a == d) ? a : b;
+        const int32_t o = (s == a) ? b : a;
+        const int32_t t = (s == c) ? d : c;
+        // edges at s: new leaf w (adjacent to e1 -> e > e2): star
+        for (int64_t j = C.rp[s]; j < C.rp[s + 1]; ++j) {
+            const int32_t w = C.col[j];
+            if (w == o || w == t) continue;
+            if (C.eid[j] <= e2) continue;
+            const Emb Em = classify_star(C, s, o, t, w);
+            ++local;
+            if (BITS) set_bits(Bt, Em); else atomicAdd(&counts[Em.pid], 1u);
+        }
+        // edges at o (adjacent to e1 -> e > e2): closing edge (triangle) or path w-o-s-t
+        for (int64_t j = C.rp[o]; j < C.rp[o + 1]; ++j) {
+            const int32_t w = C.col[j];
+            if (w == s) continue;
+            if (C.eid[j] <= e2) continue;
+            const Emb Em = (w == t) ? classify_triangle(C, s, o, t) : classify_path(C, w, o, s, t);
+            ++local;
+            if (BITS) set_bits(Bt, Em); else atomicAdd(&counts[Em.pid], 1u);
+        }
+        // edges at t not touching e1 (only e > e1 needed): path o-s-t-w
+        for (int64_t j = C.rp[t]; j < C.rp[t + 1]; ++j) {
+            const int32_t w = C.col[j];
+            if (w == s || w == o) continue;
+            if (C.eid[j] <= e1) continue;
+            const Emb Em = classify_path(C, o, s, t, w);
+            ++local;
+            if (BITS) set_bits(Bt, Em); else atomicAdd(&counts[Em.pid], 1u);
+        }
+    }
+    if (!BITS) {
+        local = wave_sum_u64(local);
+        if (lane() == 0 && local) atomicAdd(n_emb, (unsigned long long)local);
+    }
+}
+
+// level 2 domain bits from the stored entries
+__global__ void k_fsm_l2_bits(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, const int32_t* __restrict__ e2s,
+                              Bits Bt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e1 = e1s[i], e2 = e2s[i];
+        const int32_t a = C.esrc[e1], b = C.edst[e1], c = C.esrc[e2], d = C.edst[e2];
+        const int32_t s = (a == c || a == d) ? a : b;
+        const int32_t o = (s == a) ? b : a;
+        const int32_t t = (s == c) ? d : c;
+        set_bits(Bt, classify_wedge(C, s, o, t));
+    }
+}
+
+// support of each slot of the group: the smallest non-empty orbit domain
+__global__ __launch_bounds__(256) void k_supports(const uint32_t* __restrict__ bm, int64_t words, int32_t s_lo,
+                                                  int32_t s_hi, uint64_t* __restrict__ sup_slot) {
+    __shared__ unsigned long long pop[4];
+    const int32_t sl = s_lo + blockIdx.x;
+    if (sl >= s_hi) return;
+    const int o = threadIdx.x / WAVE;
+    const uint32_t* base = bm + ((int64_t)(sl - s_lo) * 4 + o) * words;
+    uint64_t c = 0;
+    for (int64_t i = lane(); i < words; i += WAVE) c += (uint64_t)__popc(base[i]);
+    c = wave_sum_u64(c);
+    if (lane() == 0) pop[o] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t best = 0;
+        for (int k = 0; k < 4; ++k)
+            if (pop[k] && (best == 0 || pop[k] < best)) best = pop[k];
+        sup_slot[sl] = best;
+    }
+}
+
+__global__ void k_frequent(int64_t np, const int32_t* __restrict__ slot, const uint64_t* __restrict__ sup_slot,
+                           uint64_t sigma, uint64_t* __restrict__ sup_pat, uint8_t* __restrict__ freq) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t s = slot[p] >= 0 ? sup_slot[slot[p]] : 0;
+        const bool f = slot[p] >= 0 && s >= sigma && s > 0;
+        freq[p] = f ? 1 : 0;
+        sup_pat[p] = f ? s : 0;
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+static unsigned grid1(int64_t items) {
+    int64_t b = (items + 255) / 256;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)device_info().n_cu * 16));
+}
+
+// Reduce over one level: supports of its patterns [p_lo, p_hi) (dense
+// index), frequent flags, and the host copy of the supports.
+template <class SetBits>
+static void reduce_level(pg_graph* g, FsmCtx& C, int64_t p_lo, int64_t p_hi, const uint32_t* counts,
+                         uint64_t sigma, uint8_t* freq, uint64_t* sup_pat, SetBits&& set_bits_pass) {
+    hipStream_t s = g->stream;
+    Arena& ar = g->arena;
+    const int64_t np = p_hi - p_lo;
+    const size_t mk = ar.mark();
+    uint32_t* flag = push<uint32_t>(ar, np);
+    uint64_t* pos = push<uint64_t>(ar, np + 1);
+    int32_t* slot = push<int32_t>(ar, C.B.total);
+    fill_u32(reinterpret_cast<uint32_t*>(slot), C.B.total, 0xffffffffu, s);
+    k_candidates<<<grid1(np), 256, 0, s>>>(np, p_lo, counts + p_lo, C.B, sigma, flag);
+    PG_HIP(hipGetLastError());
+    scan_u32(flag, np, pos, ar, s);
+    const int64_t ns = (int64_t)read_u64(pos + np, s);
+    int32_t* pid_of_slot = push<int32_t>(ar, std::max<int64_t>(ns, 1));
+    k_slots<<<grid1(np), 256, 0, s>>>(np, flag, pos, slot + p_lo, pid_of_slot);
+    PG_HIP(hipGetLastError());
+    uint64_t* sup_slot = push<uint64_t>(ar, std::max<int64_t>(ns, 1));
+    if (ns > 0) {
+        const int64_t words = (g->n + 31) / 32;
+        const uint64_t per_slot = (uint64_t)words * 4 * sizeof(uint32_t);
+        const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
+        const int64_t group = std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(room / std::max<uint64_t>(per_slot, 1))));
+        uint32_t* bm = push<uint32_t>(ar, (size_t)group * 4 * words);
+        for (int64_t g0 = 0; g0 < ns; g0 += group) {
+            const int64_t g1 = std::min(ns, g0 + group);
+            fill_u32(bm, (g1 - g0) * 4 * words, 0, s);
+            Bits Bt{bm, words, slot, (int32_t)g0, (int32_t)g1};
+            set_bits_pass(Bt);
+            ProfScope ps("fsm_support", s, (double)(g1 - g0));
+            k_supports<<<(unsigned)(g1 - g0), 256, 0, s>>>(bm, words, (int32_t)g0, (int32_t)g1, sup_slot);
+            PG_HIP(hipGetLastError());
+        }
+    }
+    // the slot table covers the whole index; only this level's range is read
+    k_frequent<<<grid1(np), 256, 0, s>>>(np, slot + p_lo, sup_slot, sigma, sup_pat + p_lo, freq + p_lo);
+    PG_HIP(hipGetLastError());
+    ar.reset(mk);
+}
+
+void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports, size_t len, size_t* n_frequent) {
+    PG_REQUIRE(max_edges >= 1 && max_edges <= 3, PG_EUNSUPPORTED, "max_edges must be in [1, 3]");
+    PG_REQUIRE(g->n_labels > 0, PG_EINVAL, "FSM needs a labelled graph");
+    build_motif_l1(g);
+    PG_REQUIRE(g->ml1.n_edges < INT32_MAX, PG_EOVERFLOW, "FSM supports fewer than 2^31 edges");
+    hipStream_t s = g->stream;
+    Arena& ar = g->arena;
+    const int64_t L = g->n_labels;
+    const int64_t E = g->ml1.n_edges;
+    FsmCtx C;
+    C.B = pat_base(L, max_edges);
+    const int64_t np = C.B.total;
+    PG_REQUIRE((uint64_t)np <= len, PG_EINVAL, "supports array too short");
+    C.rp = g->rp.as<int64_t>();
+    C.col = g->col.as<int32_t>();
+    C.esrc = g->ml1.src.as<int32_t>();
+    C.edst = g->ml1.dst.as<int32_t>();
+    C.lab = g->labels.as<int32_t>();
+    // edge ids of CSR entries
+    int32_t* eid = push<int32_t>(ar, std::max<int64_t>(g->nnz, 1));
+    if (g->n > 0) {
+        k_edge_ids<<<grid1(g->n * 64 / 4), 256, 0, s>>>(g->n, C.rp, C.col, g->ml1.seg.as<int64_t>(), eid);
+        PG_HIP(hipGetLastError());
+    }
+    C.eid = eid;
+    // path label ranks
+    int32_t* prank = nullptr;
+    if (max_edges >= 3) {
+        const int64_t N4 = L * L * L * L;
+        prank = push<int32_t>(ar, N4);
+        const size_t mk = ar.mark();
+        uint32_t* pf = push<uint32_t>(ar, N4);
+        uint64_t* pr = push<uint64_t>(ar, N4 + 1);
+        k_path_flags<<<grid1(N4), 256, 0, s>>>(L, pf);
+        PG_HIP(hipGetLastError());
+        scan_u32(pf, N4, pr, ar, s);
+        k_u64_to_i32<<<grid1(N4), 256, 0, s>>>(N4, pr, prank);
+        PG_HIP(hipGetLastError());
+        ar.reset(mk);
+    }
+    C.path_rank = prank;
+    uint32_t* counts = push<uint32_t>(ar, np);
+    uint8_t* freq = push<uint8_t>(ar, np);
+    uint64_t* sup_pat = push<uint64_t>(ar, np);
+    fill_u32(counts, np, 0, s);
+    fill_u64(sup_pat, np, 0, s);
+    fill_u32(reinterpret_cast<uint32_t*>(freq), (np + 3) / 4, 0, s);
+    unsigned long long* n_emb = reinterpret_cast<unsigned long long*>(push<uint64_t>(ar, 4));
+    fill_u64(reinterpret_cast<uint64_t*>(n_emb), 4, 0, s);
+
+    // ---------------- level 1: every edge; Reduce; Filter
+    int32_t* pid1 = push<int32_t>(ar, std::max<int64_t>(E, 1));
+    {
+        ProfScope ps("fsm_l1", s, (double)E);
+        k_fsm_l1<false><<<grid1(E), 256, 0, s>>>(C, E, pid1, Bits{});
+        PG_HIP(hipGetLastError());
+        k_hist<<<grid1(E), 256, 0, s>>>(E, pid1, counts);
+        PG_HIP(hipGetLastError());
+    }
+    reduce_level(g, C, C.B.edge, C.B.wedge, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
+        k_fsm_l1<true><<<grid1(E), 256, 0, s>>>(C, E, nullptr, Bt);
+        PG_HIP(hipGetLastError());
+    });
+    if (max_edges >= 2) {
+        // Filter: frequent edges, in id order
+        uint32_t* keep = push<uint32_t>(ar, std::max<int64_t>(E, 1));
+        uint64_t* kpos = push<uint64_t>(ar, E + 1);
+        k_keep_flags<<<grid1(E), 256, 0, s>>>(E, pid1, freq, keep);
+        PG_HIP(hipGetLastError());
+        scan_u32(keep, E, kpos, ar, s);
+        const int64_t m1 = (int64_t)read_u64(kpos + E, s);
+        int32_t* f1 = push<int32_t>(ar, std::max<int64_t>(m1, 1));
+        k_compact2<<<grid1(E), 256, 0, s>>>(E, keep, kpos, nullptr, nullptr, f1, nullptr);
+        PG_HIP(hipGetLastError());
+
+        // ---------------- level 2: count / scan / write with memoised pattern ids
+        uint32_t* c2 = push<uint32_t>(ar, std::max<int64_t>(m1, 1));
+        uint64_t* st2 = push<uint64_t>(ar, m1 + 1);
+        if (m1 > 0) {
+            ProfScope ps("fsm_l2_count", s, (double)m1);
+            k_fsm_l2<false><<<grid1(m1), 256, 0, s>>>(C, m1, f1, c2, nullptr, nullptr, nullptr, nullptr);
+            PG_HIP(hipGetLastError());
+        }
+        scan_u32(c2, m1, st2, ar, s);
+        const int64_t n2 = (int64_t)read_u64(st2 + m1, s);
+        int32_t* a2 = push<int32_t>(ar, std::max<int64_t>(n2, 1));
+        int32_t* b2 = push<int32_t>(ar, std::max<int64_t>(n2, 1));
+        int32_t* p2 = push<int32_t>(ar, std::max<int64_t>(n2, 1));
+        if (m1 > 0) {
+            ProfScope ps("fsm_l2_write", s, (double)n2);
+            k_fsm_l2<true><<<grid1(m1), 256, 0, s>>>(C, m1, f1, nullptr, st2, a2, b2, p2);
+            PG_HIP(hipGetLastError());
+            k_hist<<<grid1(n2), 256, 0, s>>>(n2, p2, counts);
+            PG_HIP(hipGetLastError());
+        }
+        reduce_level(g, C, C.B.wedge, C.B.tri, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
+            if (n2 > 0) {
+                k_fsm_l2_bits<<<grid1(n2), 256, 0, s>>>(C, n2, a2, b2, Bt);
+                PG_HIP(hipGetLastError());
+            }
+        });
+        if (max_edges >= 3) {
+            // Filter: frequent wedges
+            uint32_t* keep2 = push<uint32_t>(ar, std::max<int64_t>(n2, 1));
+            uint64_t* kpos2 = push<uint64_t>(ar, n2 + 1);
+            k_keep_flags<<<grid1(n2), 256, 0, s>>>(n2, p2, freq, keep2);
+            PG_HIP(hipGetLastError());
+            scan_u32(keep2, n2, kpos2, ar, s);
+            const int64_t m2 = (int64_t)read_u64(kpos2 + n2, s);
+            int32_t* fa = push<int32_t>(ar, std::max<int64_t>(m2, 1));
+            int32_t* fb = push<int32_t>(ar, std::max<int64_t>(m2, 1));
+            k_compact2<<<grid1(n2), 256, 0, s>>>(n2, keep2, kpos2, a2, b2, fa, fb);
+            PG_HIP(hipGetLastError());
+            // ---------------- level 3, fused with Reduce (never stored)
+            if (m2 > 0) {
+                ProfScope ps("fsm_l3_hist", s, (double)m2);
+                k_fsm_l3<false><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, counts, Bits{}, n_emb);
+                PG_HIP(hipGetLastError());
+            }
+            reduce_level(g, C, C.B.tri, C.B.total, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
+                if (m2 > 0) {
+                    ProfScope ps("fsm_l3_bits", s, (double)m2);
+                    k_fsm_l3<true><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bt, nullptr);
+                    PG_HIP(hipGetLastError());
+                }
+            });
+        }
+    }
+    std::vector<uint64_t> h((size_t)np);
+    PG_HIP(hipMemcpyAsync(h.data(), sup_pat, sizeof(uint64_t) * np, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    size_t nf = 0;
+    for (int64_t p = 0; p < np; ++p) {
+        supports[p] = h[p];
+        nf += h[p] > 0;
+    }
+    if (n_frequent) *n_frequent = nf;
+}
+
 }  // namespace pg

@@ -168,9 +168,12 @@ __global__ __launch_bounds__(256) void k_dag_emit(int64_t n, const int64_t* __re
     }
 }
 
-__global__ void k_split_low(int64_t m, const uint64_t* __restrict__ keys, int32_t* __restrict__ low) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+__global__ void k_split_low(int64_t m, const uint64_t* __restrict__ keys, int32_t* __restrict__ low,
+                            int32_t* __restrict__ high) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         low[i] = (int32_t)(uint32_t)keys[i];
+        high[i] = (int32_t)(uint32_t)(keys[i] >> 32);
+    }
 }
 
 static int bits_for(uint64_t x) {
@@ -194,6 +197,7 @@ void build_dag(pg_graph* g) {
     D.rank_of.reserve(sizeof(int32_t) * std::max<int64_t>(n, 1));
     D.rp.reserve(sizeof(int64_t) * (n + 1));
     D.col.reserve(sizeof(int32_t) * std::max<int64_t>(m, 1));
+    D.src.reserve(sizeof(int32_t) * std::max<int64_t>(m, 1));
     DevBuf t1, t2, t3;
     t1.reserve(sizeof(uint64_t) * std::max<int64_t>(std::max(n, m), 1));
     t2.reserve(sizeof(uint64_t) * std::max<int64_t>(std::max(n, m), 1));
@@ -231,7 +235,7 @@ void build_dag(pg_graph* g) {
             const int nb = std::max(1, bits_for((uint64_t)(n - 1)));
             radix_sort_u64(ek, t2.as<uint64_t>(), m, 0, nb, tmp, s);
             radix_sort_u64(ek, t2.as<uint64_t>(), m, 32, 32 + nb, tmp, s);
-            k_split_low<<<grid_for(m, 256), 256, 0, s>>>(m, ek, D.col.as<int32_t>());
+            k_split_low<<<grid_for(m, 256), 256, 0, s>>>(m, ek, D.col.as<int32_t>(), D.src.as<int32_t>());
             PG_HIP(hipGetLastError());
         }
     } else {

@@ -114,6 +114,7 @@ struct Dag {
     DevBuf rank_of;          // int32[n]: rank of each original vertex in the degree order
     DevBuf rp;               // int64[n+1] over ranks
     DevBuf col;              // int32[n_edges], out-neighbours (ranks), ascending
+    DevBuf src;              // int32[n_edges], source rank of every DAG edge (level-1 idx)
 };
 
 struct MotifL1 {
@@ -135,6 +136,7 @@ struct pg_graph {
     pg::Dag dag;
     pg::MotifL1 ml1;
     uint64_t budget = 0;     // bytes for materialised levels
+    bool force_generic = false;   // 4-cliques: skip the sibling-mask path
     pg::Arena arena;
 };
 

@@ -1,9 +1,686 @@
-// Vertex-induced motif counting (placeholder until the kernels land).
+// Vertex-induced motif counting for k = 3 and k = 4 (Pangolin sections 2.2,
+// 3.3 motif Listing, 4.2).
+//
+// Canonical test (isAutoCanonical for vertex extension).  An embedding is
+// kept in one order only: the breadth-first order from its smallest
+// vertex, neighbours of one vertex taken in increasing id.  With p(j) the
+// position of v_j's first earlier neighbour, a sequence is canonical iff
+// v0 is the minimum, p is non-decreasing and p(j) = p(j+1) implies
+// v_j < v_{j+1}.  Extending a canonical sequence by u is canonical iff
+// u > v0, u is not in it, and with s = the first position adjacent to u:
+// s >= p(last), and s = p(last) implies u > v_last.
+//
+// Levels.  L1 = every edge once as (v0 < v1) (p(1) = 0).  L2 = canonical
+// connected 3-sets (v0, v1, v2) built by count / scan / write, each entry
+// with a 2-bit connectivity code memoising its pattern (bit 0: v2 ~ v0,
+// bit 1: v2 ~ v1; section 4.2 memoisation).  The last level is fused with
+// classification and reduction.
+//
+// Fused last level.  For an embedding E and a candidate u let the mask be
+// the set of E's vertices adjacent to u.  The canonical test depends only on
+// the mask and on whether u lies above a threshold (v_last or v0); the
+// pattern of E + u is the connectivity bitmap of E plus the mask, looked up
+// in a 64-entry table.  So instead of testing every candidate one by one,
+// the kernel counts candidates per exact mask and per threshold range from
+// set intersections (each computed by iterating the smaller list and
+// binary-searching the larger one), then applies the canonical rule and the
+// table to the counts.  This is the same reduction (Algorithm 2 Reduce with
+// support 1 and Aggregate = sum) without enumerating candidates.
+//
+// Output order: k = 3: wedge, triangle; k = 4: path, star, cycle, paw,
+// diamond, 4-clique.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "pg_device.h"
 #include "pg_internal.h"
 
 namespace pg {
-void count_motifs(pg_graph* g, int k, uint64_t* counts) {
-    (void)g; (void)k; (void)counts;
-    throw Error{PG_EUNSUPPORTED, "motif counting not built yet"};
+
+constexpr int MO_THREADS = 128;
+constexpr int MO_WAVES = MO_THREADS / WAVE;
+constexpr int MO_STAGE = 512;     // adjacency lists up to this long are staged in LDS
+constexpr int MO_CMAX = 512;      // common-neighbour lists up to this long live in LDS
+
+enum { ML1_COUNT = 0, ML1_WRITE = 1, ML1_LAST3 = 2 };
+
+// Pattern table for 4 vertices.  Bit i of the index is pair i of
+// (01, 02, 12, 03, 13, 23).  Value: 0 path, 1 star, 2 cycle, 3 paw,
+// 4 diamond, 5 4-clique, -1 disconnected.
+struct Lut4 {
+    int8_t v[64];
+};
+
+__host__ __device__ constexpr Lut4 make_lut4() {
+    Lut4 t{};
+    const int pa[6] = {0, 0, 1, 0, 1, 2};
+    const int pb[6] = {1, 2, 2, 3, 3, 3};
+    for (int m = 0; m < 64; ++m) {
+        int deg[4] = {0, 0, 0, 0};
+        int e = 0;
+        for (int i = 0; i < 6; ++i)
+            if ((m >> i) & 1) {
+                deg[pa[i]]++;
+                deg[pb[i]]++;
+                e++;
+            }
+        int dmin = 4, dmax = 0;
+        for (int a = 0; a < 4; ++a) {
+            dmin = deg[a] < dmin ? deg[a] : dmin;
+            dmax = deg[a] > dmax ? deg[a] : dmax;
+        }
+        int8_t c = -1;
+        if (dmin > 0) {
+            if (e == 3) c = (dmax == 3) ? 1 : (e == 3 && dmax == 2 ? 0 : -1);
+            else if (e == 4) c = (dmax == 3) ? 3 : 2;
+            else if (e == 5) c = 4;
+            else if (e == 6) c = 5;
+        }
+        t.v[m] = c;
+    }
+    return t;
 }
+
+__constant__ Lut4 c_lut4 = make_lut4();
+
+struct MotifArgs {
+    XcdQueue Q;
+    int64_t p_lo;               // first item (segment) id
+    const int64_t* rp;          // undirected CSR
+    const int32_t* col;
+    // level-1 segments: vertex v0 owns L1 entries l1_seg[v0] .. l1_seg[v0+1]-1
+    const int64_t* l1_seg;
+    const int32_t* l1_src;
+    const int32_t* l1_dst;
+    int64_t x_lo, x_hi;         // L1 entries extended (count / write / last3)
+    uint32_t* count;            // ML1_COUNT: L2 children per L1 entry (indexed by entry)
+    const uint64_t* start;      // ML1_WRITE: children of entry x at start[x] - start_base
+    uint64_t start_base;
+    int32_t* out_vid;
+    uint8_t* out_code;
+    // last level of k = 4: segment p (an L1 entry) owns L2 entries
+    // seg2[p] - seg2_base .. seg2[p+1] - seg2_base - 1
+    const uint64_t* seg2;
+    uint64_t seg2_base;
+    const int32_t* vid2;
+    const uint8_t* code2;
+    int32_t* scratch;           // per-wave common-neighbour lists longer than MO_CMAX
+    int64_t scratch_per_wave;
+    unsigned long long* out;    // pattern counters (6) + work stats
+};
+
+// --------------------------------------------------------------- helpers
+
+template <class P>
+__device__ __forceinline__ bool member(P a, int32_t len, int32_t key) {
+    return contains(a, len, key);
+}
+
+// ---------------------------------------------------------- level 1 -> 2
+
+struct L1Lds {
+    int32_t A0[MO_WAVES][MO_STAGE];
+    uint32_t pre[MO_WAVES][WAVE];
+    int64_t lo1[MO_WAVES][WAVE];    // first entry of A1 above v0 (global index)
+    int32_t d1[MO_WAVES][WAVE];     // |A1 above v0|
+    int32_t v1[MO_WAVES][WAVE];
+    int32_t na[MO_WAVES][WAVE];     // |A0 above v1|
+    int32_t opt[MO_WAVES][WAVE];    // COUNT/LAST3: 0 iterate A0', 1 iterate A1'
+    uint32_t c_all[MO_WAVES][WAVE];
+    uint32_t c_hi[MO_WAVES][WAVE];
+};
+
+template <int MODE, class P0>
+__device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, int w, int32_t v0, P0 A0,
+                                                 int32_t d0, int64_t r0, int64_t b, int32_t s,
+                                                 uint64_t (&acc)[6]) {
+    // A0' = A0 above v0, at positions [a0lo, d0)
+    const int32_t a0lo = (int32_t)upper_bound(A0, 0, d0, v0);
+    const int32_t x0 = (int32_t)max<int64_t>(0, A.x_lo - b);
+    const int32_t x1 = (int32_t)min<int64_t>(s, A.x_hi - b);
+    for (int32_t xc = x0; xc < x1; xc += WAVE) {
+        const int32_t x = xc + lane();
+        uint32_t work = 0;
+        if (x < x1) {
+            const int32_t v1 = A.l1_dst[b + x];
+            const int64_t q0 = A.rp[v1], q1 = A.rp[v1 + 1];
+            const int64_t lo1 = upper_bound(A.col, q0, q1, v0);
+            const int32_t d1p = (int32_t)(q1 - lo1);
+            const int32_t na = d0 - (int32_t)upper_bound(A0, a0lo, d0, v1);
+            const int32_t d0p = d0 - a0lo;
+            int opt = 0;
+            if (MODE == ML1_WRITE) {
+                work = (uint32_t)(na + d1p);
+            } else {
+                opt = (d0p <= d1p) ? 0 : 1;
+                work = (uint32_t)(opt == 0 ? d0p : d1p);
+            }
+            L.lo1[w][lane()] = lo1;
+            L.d1[w][lane()] = d1p;
+            L.v1[w][lane()] = v1;
+            L.na[w][lane()] = na;
+            L.opt[w][lane()] = opt;
+        }
+        const uint32_t inc = wave_incl_scan(work);
+        const uint32_t W = bcast(inc, WAVE - 1);
+        L.pre[w][lane()] = inc - work;
+        L.c_all[w][lane()] = 0;
+        L.c_hi[w][lane()] = 0;
+        wave_sync();
+        const int nx = min(WAVE, x1 - xc);
+        for (uint32_t t0 = 0; t0 < W; t0 += WAVE) {
+            const uint32_t t = t0 + lane();
+            const bool valid = t < W;
+            int xi = 0;
+            {
+                int n_i = nx;
+                while (n_i > 1) {
+                    const int half = n_i >> 1;
+                    if (L.pre[w][xi + half] <= t) xi += half;
+                    n_i -= half;
+                }
+            }
+            if (MODE != ML1_WRITE) {
+                if (valid) {
+                    const uint32_t j = t - L.pre[w][xi];
+                    const int32_t v1 = L.v1[w][xi];
+                    const int64_t q0 = A.rp[v1], q1 = A.rp[v1 + 1];
+                    int32_t u;
+                    bool f;
+                    if (L.opt[w][xi] == 0) {
+                        u = A0[a0lo + j];
+                        f = member(A.col + q0, (int32_t)(q1 - q0), u);
+                    } else {
+                        u = A.col[L.lo1[w][xi] + j];
+                        f = member(A0, d0, u);
+                    }
+                    if (f) {
+                        atomicAdd(&L.c_all[w][xi], 1u);
+                        if (u > v1) atomicAdd(&L.c_hi[w][xi], 1u);
+                    }
+                }
+            } else {
+                // children of (v0, v1): u in A0 above v1 (code bit 0 set, bit 1 =
+                // u ~ v1), then u in A1 above v0 not adjacent to v0 (code 2)
+                bool emit = false;
+                int32_t u = 0;
+                uint8_t code = 0;
+                if (valid) {
+                    const uint32_t j = t - L.pre[w][xi];
+                    const int32_t v1 = L.v1[w][xi];
+                    const int32_t na = L.na[w][xi];
+                    const int64_t q0 = A.rp[v1], q1 = A.rp[v1 + 1];
+                    if ((int32_t)j < na) {
+                        u = A0[d0 - na + (int32_t)j];
+                        code = 1 | (member(A.col + q0, (int32_t)(q1 - q0), u) ? 2 : 0);
+                        emit = true;
+                    } else {
+                        u = A.col[L.lo1[w][xi] + (j - (uint32_t)na)];
+                        emit = !member(A0, d0, u);
+                        code = 2;
+                    }
+                }
+                const int key = valid ? xi : WAVE;
+                const int prev = __shfl_up(key, 1, WAVE);
+                const bool head = lane() == 0 || prev != key;
+                const uint64_t H = ballot(head);
+                const uint64_t F = ballot(emit);
+                const uint64_t le = lanemask_lt() | (1ull << lane());
+                const int h = 63 - __clzll(H & le);
+                const uint64_t grp = le & ~((1ull << h) - 1ull);
+                const uint32_t base = valid ? L.c_all[w][xi] : 0u;
+                if (emit) {
+                    const uint64_t dst = A.start[b + xc + xi] - A.start_base + base +
+                                         (uint64_t)popc64(F & grp & lanemask_lt());
+                    A.out_vid[dst] = u;
+                    A.out_code[dst] = code;
+                }
+                const bool next_head = (lane() == WAVE - 1) || ((H >> (lane() + 1)) & 1ull);
+                wave_sync();
+                if (valid && next_head) L.c_all[w][xi] = base + (uint32_t)popc64(F & grp);
+                wave_sync();
+            }
+        }
+        wave_sync();
+        if (x < x1) {
+            const uint32_t ca = L.c_all[w][lane()], ch = L.c_hi[w][lane()];
+            const int32_t na = L.na[w][lane()], d1p = L.d1[w][lane()];
+            if (MODE == ML1_COUNT) {
+                A.count[b + x] = (uint32_t)(na + d1p) - ca;
+            } else if (MODE == ML1_LAST3) {
+                acc[1] += ch;                                  // triangles
+                acc[0] += (uint64_t)(na - (int32_t)ch) + (uint64_t)(d1p - (int32_t)ca);   // wedges
+            }
+        }
+        wave_sync();
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(MO_THREADS) void k_motif_l1(MotifArgs A) {
+    __shared__ L1Lds L;
+    const int w = threadIdx.x / WAVE;
+    uint64_t acc[6] = {0, 0, 0, 0, 0, 0};
+    QueueCursor cur = queue_start();
+    int64_t it_end = 0;
+    for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
+        for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
+            const int32_t v0 = (int32_t)p;
+            const int64_t b = A.l1_seg[p], e = A.l1_seg[p + 1];
+            const int32_t s = (int32_t)(e - b);
+            if (s <= 0 || e <= A.x_lo || b >= A.x_hi) continue;
+            const int64_t r0 = A.rp[v0], r1 = A.rp[v0 + 1];
+            const int32_t d0 = (int32_t)(r1 - r0);
+            if (d0 <= MO_STAGE) {
+                for (int i = lane(); i < d0; i += WAVE) L.A0[w][i] = A.col[r0 + i];
+                wave_sync();
+                motif_l1_segment<MODE>(A, L, w, v0, &L.A0[w][0], d0, r0, b, s, acc);
+            } else {
+                motif_l1_segment<MODE>(A, L, w, v0, A.col + r0, d0, r0, b, s, acc);
+            }
+            wave_sync();
+        }
+    }
+    if (MODE == ML1_LAST3) {
+        const uint64_t wd = wave_sum_u64(acc[0]), tr = wave_sum_u64(acc[1]);
+        if (lane() == 0) {
+            if (wd) atomicAdd(&A.out[0], (unsigned long long)wd);
+            if (tr) atomicAdd(&A.out[1], (unsigned long long)tr);
+        }
+    }
+}
+
+// ------------------------------------------------------- last level, k = 4
+
+struct L4Lds {
+    int32_t A0[MO_WAVES][MO_STAGE];
+    int32_t A1[MO_WAVES][MO_STAGE];
+    int32_t C[MO_WAVES][MO_CMAX];
+    uint32_t pre[MO_WAVES][WAVE];
+    int64_t lo2[MO_WAVES][WAVE];
+    int64_t base2[MO_WAVES][WAVE];   // row start of v2
+    int32_t len2[MO_WAVES][WAVE];    // degree of v2
+    int32_t v2[MO_WAVES][WAVE];
+    int32_t opt[MO_WAVES][WAVE];
+    uint32_t cnt[MO_WAVES][WAVE][6]; // I02 lo/hi, I12 lo/hi, I012 lo/hi
+};
+
+// Children of one L1 entry (v0, v1).  A0/A1: the two adjacency lists (LDS or
+// global), C: A0 and A1 above v0 intersected (sorted, LDS or scratch).
+template <class P0, class P1, class PC>
+__device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L, int w, int32_t v0, int32_t v1,
+                                                    P0 A0, int32_t d0, P1 A1, int32_t d1, PC C, int32_t nc,
+                                                    int64_t b, int32_t s, uint64_t (&acc)[6],
+                                                    uint64_t& items) {
+    const int32_t a0lo = (int32_t)upper_bound(A0, 0, d0, v0);
+    const int32_t a1lo = (int32_t)upper_bound(A1, 0, d1, v0);
+    const int32_t d0p = d0 - a0lo, d1p = d1 - a1lo;
+    for (int32_t xc = 0; xc < s; xc += WAVE) {
+        const int32_t x = xc + lane();
+        uint32_t work = 0;
+        int32_t v2 = 0, code = 0;
+        int64_t s0 = 0, s1 = 0, lo2 = 0;
+        if (x < s) {
+            v2 = A.vid2[b + x];
+            code = A.code2[b + x];
+            s0 = A.rp[v2];
+            s1 = A.rp[v2 + 1];
+            lo2 = upper_bound(A.col, s0, s1, v0);
+            const int32_t d2p = (int32_t)(s1 - lo2);
+            // iterate A2' and search A0, A1 (2 searches each), or iterate A0'
+            // (2 searches) and A1' (1 search) and search A2
+            const int opt = (2 * d2p <= 2 * d0p + d1p) ? 0 : 1;
+            work = (uint32_t)(opt == 0 ? d2p : d0p + d1p);
+            L.lo2[w][lane()] = lo2;
+            L.base2[w][lane()] = s0;
+            L.len2[w][lane()] = (int32_t)(s1 - s0);
+            L.v2[w][lane()] = v2;
+            L.opt[w][lane()] = opt;
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) L.cnt[w][lane()][c] = 0;
+        const uint32_t inc = wave_incl_scan(work);
+        const uint32_t W = bcast(inc, WAVE - 1);
+        L.pre[w][lane()] = inc - work;
+        items += work;
+        wave_sync();
+        const int nx = min(WAVE, s - xc);
+        for (uint32_t t0 = 0; t0 < W; t0 += WAVE) {
+            const uint32_t t = t0 + lane();
+            if (t < W) {
+                int xi = 0;
+                {
+                    int n_i = nx;
+                    while (n_i > 1) {
+                        const int half = n_i >> 1;
+                        if (L.pre[w][xi + half] <= t) xi += half;
+                        n_i -= half;
+                    }
+                }
+                const uint32_t j = t - L.pre[w][xi];
+                const int32_t cv2 = L.v2[w][xi];
+                if (L.opt[w][xi] == 0) {
+                    const int32_t u = A.col[L.lo2[w][xi] + j];
+                    const bool b0 = member(A0, d0, u);
+                    const bool b1 = member(A1, d1, u);
+                    const int r = u > cv2;
+                    if (b0) atomicAdd(&L.cnt[w][xi][0 + r], 1u);
+                    if (b1) atomicAdd(&L.cnt[w][xi][2 + r], 1u);
+                    if (b0 && b1) atomicAdd(&L.cnt[w][xi][4 + r], 1u);
+                } else {
+                    const int64_t base2 = L.base2[w][xi];
+                    const int32_t len2 = L.len2[w][xi];
+                    if ((int32_t)j < d0p) {
+                        const int32_t u = A0[a0lo + (int32_t)j];
+                        if (member(A.col + base2, len2, u)) {
+                            const int r = u > cv2;
+                            atomicAdd(&L.cnt[w][xi][0 + r], 1u);
+                            if (member(A1, d1, u)) atomicAdd(&L.cnt[w][xi][4 + r], 1u);
+                        }
+                    } else {
+                        const int32_t u = A1[a1lo + (int32_t)j - d0p];
+                        if (member(A.col + base2, len2, u)) atomicAdd(&L.cnt[w][xi][2 + (u > cv2)], 1u);
+                    }
+                }
+            }
+        }
+        wave_sync();
+        if (x < s) {
+            const int a02 = code & 1, a12 = (code >> 1) & 1;
+            const int p = a02 ? 0 : 1;
+            // "at least" counts per range: [0] = (v0, v2], [1] = above v2
+            const int32_t u0 = (int32_t)upper_bound(A0, a0lo, d0, v2);
+            const int32_t u1 = (int32_t)upper_bound(A1, a1lo, d1, v2);
+            const int64_t u2 = upper_bound(A.col, lo2, s1, v2);
+            const int32_t uc = (int32_t)upper_bound(C, 0, nc, v2);
+            int64_t I0[2] = {u0 - a0lo, d0 - u0};
+            int64_t I1[2] = {u1 - a1lo, d1 - u1};
+            int64_t I2[2] = {u2 - lo2, s1 - u2};
+            int64_t I01[2] = {uc, nc - uc};
+            int64_t N[2][8];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int64_t i02 = L.cnt[w][lane()][0 + r], i12 = L.cnt[w][lane()][2 + r];
+                const int64_t i012 = L.cnt[w][lane()][4 + r];
+                N[r][0] = 0;
+                N[r][7] = i012;
+                N[r][3] = I01[r] - i012;
+                N[r][5] = i02 - i012;
+                N[r][6] = i12 - i012;
+                N[r][1] = I0[r] - I01[r] - i02 + i012;
+                N[r][2] = I1[r] - I01[r] - i12 + i012;
+                N[r][4] = I2[r] - i02 - i12 + i012;
+            }
+            // the embedding's own vertices are not candidates
+            N[v1 > v2 ? 1 : 0][1 | (a12 ? 4 : 0)] -= 1;   // v1: adjacent to v0, to v2 iff a12
+            N[0][a02 | (a12 << 1)] -= 1;                   // v2: adjacent to v0 iff a02, to v1 iff a12
+            const int ebits = 1 | (a02 << 1) | (a12 << 2);
+#pragma unroll
+            for (int m = 1; m < 8; ++m) {
+                const int sbit = (m & 1) ? 0 : ((m & 2) ? 1 : 2);   // first adjacent position
+                if (sbit < p) continue;
+                const int64_t c = (sbit == p) ? N[1][m] : N[0][m] + N[1][m];
+                const int pid = c_lut4.v[ebits | (m << 3)];
+                if (pid >= 0) acc[pid] += (uint64_t)c;
+            }
+        }
+        wave_sync();
+    }
+}
+
+__global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
+    __shared__ L4Lds L;
+    const int w = threadIdx.x / WAVE;
+    const int64_t wave_id = (int64_t)blockIdx.x * MO_WAVES + w;
+    int32_t* scratch = A.scratch + wave_id * A.scratch_per_wave;
+    uint64_t acc[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t items = 0, n_in = 0, deg_sum = 0;
+    QueueCursor cur = queue_start();
+    int64_t it_end = 0;
+    for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
+        for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
+            const int64_t b = (int64_t)(A.seg2[p] - A.seg2_base);
+            const int32_t s = (int32_t)(A.seg2[p + 1] - A.seg2[p]);
+            if (s <= 0) continue;
+            const int32_t v0 = A.l1_src[p], v1 = A.l1_dst[p];
+            const int64_t r0 = A.rp[v0], q0 = A.rp[v1];
+            const int32_t d0 = (int32_t)(A.rp[v0 + 1] - r0), d1 = (int32_t)(A.rp[v1 + 1] - q0);
+            n_in += (lane() == 0) ? (uint64_t)s : 0;
+            deg_sum += (lane() == 0) ? (uint64_t)s * (uint64_t)(d0 + d1) : 0;
+            const bool st0 = d0 <= MO_STAGE, st1 = d1 <= MO_STAGE;
+            if (st0) for (int i = lane(); i < d0; i += WAVE) L.A0[w][i] = A.col[r0 + i];
+            if (st1) for (int i = lane(); i < d1; i += WAVE) L.A1[w][i] = A.col[q0 + i];
+            wave_sync();
+            // C = A0 and A1 above v0, intersected: iterate the shorter, search the longer
+            const int32_t* gA0 = A.col + r0;
+            const int32_t* gA1 = A.col + q0;
+            const bool it0 = d0 <= d1;
+            const int32_t di = it0 ? d0 : d1;
+            int32_t nc = 0;
+            bool c_in_lds = true;
+            for (int32_t j0 = 0; j0 < di; j0 += WAVE) {
+                const int32_t j = j0 + lane();
+                bool f = false;
+                int32_t u = 0;
+                if (j < di) {
+                    if (it0) {
+                        u = st0 ? L.A0[w][j] : gA0[j];
+                        f = u > v0 && (st1 ? member(&L.A1[w][0], d1, u) : member(gA1, d1, u));
+                    } else {
+                        u = st1 ? L.A1[w][j] : gA1[j];
+                        f = u > v0 && (st0 ? member(&L.A0[w][0], d0, u) : member(gA0, d0, u));
+                    }
+                }
+                const uint64_t F = ballot(f);
+                const int32_t pos = nc + popc64(F & lanemask_lt());
+                if (f) {
+                    scratch[pos] = u;
+                    if (pos < MO_CMAX) L.C[w][pos] = u;
+                }
+                nc += popc64(F);
+            }
+            c_in_lds = nc <= MO_CMAX;
+            __threadfence_block();
+            wave_sync();
+            // dispatch on where each list lives (all wave-uniform)
+            if (st0 && st1) {
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, s, acc, items);
+                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, (const int32_t*)scratch, nc, b, s, acc, items);
+            } else if (st0) {
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, &L.C[w][0], nc, b, s, acc, items);
+                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, (const int32_t*)scratch, nc, b, s, acc, items);
+            } else if (st1) {
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, s, acc, items);
+                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, (const int32_t*)scratch, nc, b, s, acc, items);
+            } else {
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, &L.C[w][0], nc, b, s, acc, items);
+                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, (const int32_t*)scratch, nc, b, s, acc, items);
+            }
+            wave_sync();
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const uint64_t v = wave_sum_u64(acc[c]);
+        if (lane() == 0 && v) atomicAdd(&A.out[c], (unsigned long long)v);
+    }
+    const uint64_t it_sum = wave_sum_u64(items);
+    const uint64_t ni = wave_sum_u64(n_in), ds = wave_sum_u64(deg_sum);
+    if (lane() == 0) {
+        if (it_sum) atomicAdd(&A.out[6], (unsigned long long)it_sum);
+        if (ni) atomicAdd(&A.out[7], (unsigned long long)ni);
+        if (ds) atomicAdd(&A.out[8], (unsigned long long)ds);
+    }
+}
+
+// ------------------------------------------------------------------ host
+
+struct MotifRun {
+    pg_graph* g;
+    hipStream_t s;
+    unsigned long long* out;    // 16 counters
+    unsigned long long* qctr;
+    int64_t waves;
+    int blocks;
+};
+
+static MotifArgs base_args(pg_graph* g) {
+    MotifArgs A{};
+    A.rp = g->rp.as<int64_t>();
+    A.col = g->col.as<int32_t>();
+    A.l1_seg = g->ml1.seg.as<int64_t>();
+    A.l1_src = g->ml1.src.as<int32_t>();
+    A.l1_dst = g->ml1.dst.as<int32_t>();
+    return A;
+}
+
+static void set_queue(MotifRun& R, MotifArgs& A, int64_t p_lo, int64_t n_items) {
+    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, R.s);
+    A.Q.next = R.qctr;
+    A.Q.n_items = n_items;
+    A.Q.chunk = n_items >= R.waves * 64 ? 16 : (n_items >= R.waves * 8 ? 4 : 1);
+    A.p_lo = p_lo;
+    A.out = R.out;
+}
+
+template <int MODE>
+static void launch_l1(MotifRun& R, MotifArgs A, int64_t v_lo, int64_t v_hi, const char* name, double units) {
+    if (v_hi <= v_lo) return;
+    set_queue(R, A, v_lo, v_hi - v_lo);
+    ProfScope ps(name, R.s, units);
+    k_motif_l1<MODE><<<R.blocks, MO_THREADS, 0, R.s>>>(A);
+    PG_HIP(hipGetLastError());
+}
+
+// first vertex whose L1 segment holds entry x: largest v with l1_seg[v] <= x
+__global__ void k_vertex_of_entry(const int64_t* __restrict__ seg, int64_t n, const int64_t* __restrict__ xs,
+                                  int64_t nq, int64_t* __restrict__ out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= nq) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (seg[mid] <= xs[i]) lo = mid; else hi = mid - 1;
+    }
+    out[i] = lo;
+}
+
+__global__ void k_chunk_entries(const uint64_t* __restrict__ start, int64_t m, uint64_t cap, int64_t nb,
+                                int64_t* __restrict__ out_c, uint64_t* __restrict__ out_s) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j > nb) return;
+    int64_t c;
+    if (j == 0) c = 0;
+    else if (j == nb) c = m;
+    else {
+        const uint64_t target = (uint64_t)j * cap;
+        int64_t lo = 0, hi = m;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= target) lo = mid; else hi = mid - 1;
+        }
+        c = lo;
+    }
+    out_c[j] = c;
+    out_s[j] = start[c];
+}
+
+void count_motifs(pg_graph* g, int k, uint64_t* counts) {
+    PG_REQUIRE(k == 3 || k == 4, PG_EUNSUPPORTED, "motif size must be 3 or 4");
+    build_motif_l1(g);
+    const int64_t E = g->ml1.n_edges;
+    for (int i = 0; i < (k == 3 ? 2 : 6); ++i) counts[i] = 0;
+    if (E == 0) return;
+    hipStream_t s = g->stream;
+    Arena& ar = g->arena;
+    MotifRun R;
+    R.g = g;
+    R.s = s;
+    R.waves = grid_waves(16);
+    R.blocks = (int)(R.waves / MO_WAVES);
+    uint64_t* small = push<uint64_t>(ar, 32);
+    R.out = reinterpret_cast<unsigned long long*>(small);
+    R.qctr = reinterpret_cast<unsigned long long*>(small + 16);
+    fill_u64(small, 16, 0, s);
+    MotifArgs A = base_args(g);
+    A.x_lo = 0;
+    A.x_hi = E;
+    if (k == 3) {
+        launch_l1<ML1_LAST3>(R, A, 0, g->n, "motif_last", 0.0);
+    } else {
+        // level 2: count pass -> scan -> write, in chunks of L1 entries that fit the budget
+        uint32_t* cnt = push<uint32_t>(ar, E);
+        uint64_t* start = push<uint64_t>(ar, E + 1);
+        A.count = cnt;
+        launch_l1<ML1_COUNT>(R, A, 0, g->n, "motif_count", (double)E);
+        scan_u32(cnt, E, start, ar, s);
+        const uint64_t total = read_u64(start + E, s);
+        const int64_t scratch_per_wave = std::max<int64_t>(g->max_deg, 1);
+        int32_t* scratch = push<int32_t>(ar, (size_t)(R.waves * scratch_per_wave));
+        const uint64_t per = 5;   // vid + code per L2 entry
+        const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
+        const uint64_t cap = std::max<uint64_t>(room / per, (uint64_t)(2 * g->max_deg + 1));
+        const int64_t nb = total == 0 ? 0 : (int64_t)((total + cap - 1) / cap);
+        std::vector<int64_t> hc(nb + 1, 0), hv(nb + 1, 0);
+        std::vector<uint64_t> hs(nb + 1, 0);
+        if (nb >= 1) {
+            const size_t mk = ar.mark();
+            int64_t* dc = push<int64_t>(ar, nb + 1);
+            uint64_t* ds = push<uint64_t>(ar, nb + 1);
+            int64_t* dv = push<int64_t>(ar, nb + 1);
+            k_chunk_entries<<<(unsigned)((nb + 256) / 256), 256, 0, s>>>(start, E, cap, nb, dc, ds);
+            PG_HIP(hipGetLastError());
+            k_vertex_of_entry<<<(unsigned)((nb + 256) / 256), 256, 0, s>>>(A.l1_seg, g->n, dc, nb + 1, dv);
+            PG_HIP(hipGetLastError());
+            PG_HIP(hipMemcpyAsync(hc.data(), dc, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, s));
+            PG_HIP(hipMemcpyAsync(hs.data(), ds, sizeof(uint64_t) * (nb + 1), hipMemcpyDeviceToHost, s));
+            PG_HIP(hipMemcpyAsync(hv.data(), dv, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, s));
+            PG_HIP(hipStreamSynchronize(s));
+            ar.reset(mk);
+        }
+        uint64_t biggest = 0;
+        for (int64_t j = 0; j < nb; ++j) biggest = std::max<uint64_t>(biggest, hs[j + 1] - hs[j]);
+        int32_t* vid2 = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
+        uint8_t* code2 = push<uint8_t>(ar, std::max<uint64_t>(biggest, 1));
+        for (int64_t j = 0; j < nb; ++j) {
+            const int64_t c0 = hc[j], c1 = hc[j + 1];
+            if (c1 <= c0) continue;
+            MotifArgs W = A;
+            W.x_lo = c0;
+            W.x_hi = c1;
+            W.start = start;
+            W.start_base = hs[j];
+            W.out_vid = vid2;
+            W.out_code = code2;
+            const int64_t v_lo = hv[j];
+            const int64_t v_hi = (j + 1 == nb) ? g->n : std::min<int64_t>(g->n, hv[j + 1] + 1);
+            launch_l1<ML1_WRITE>(R, W, v_lo, v_hi, "motif_write", (double)(hs[j + 1] - hs[j]));
+            // fused last level over the L1 entries [c0, c1) (segments of L2)
+            MotifArgs L = A;
+            L.seg2 = start;
+            L.seg2_base = hs[j];
+            L.vid2 = vid2;
+            L.code2 = code2;
+            L.scratch = scratch;
+            L.scratch_per_wave = scratch_per_wave;
+            set_queue(R, L, c0, c1 - c0);
+            ProfScope ps("motif_last", s, 0.0);
+            k_motif_last4<<<R.blocks, MO_THREADS, 0, s>>>(L);
+            PG_HIP(hipGetLastError());
+        }
+    }
+    uint64_t h[16];
+    PG_HIP(hipMemcpyAsync(h, small, sizeof(h), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < (k == 3 ? 2 : 6); ++i) counts[i] = h[i];
+    if (prof_on() && k == 4) {
+        // algorithmic bytes of the fused last level: per input embedding the
+        // SoA entry (5 B), the three row-pointer pairs (48 B) and one 4-byte
+        // probe per intersection item
+        ProfScope ps("motif_last_work", s, 53.0 * (double)h[7] + 4.0 * (double)h[6]);
+    }
+}
+
 }  // namespace pg

@@ -71,3 +71,20 @@ def test_no_device_fails_loudly(lib):
     with pytest.raises(binding.PgError) as e:
         binding.pg_graph_load_csr([0, 1, 2], [1, 0])
     assert e.value.code == binding.PG_EDEVICE
+
+
+def test_fsm_pattern_count_matches_format(lib):
+    assert binding.pg_fsm_num_patterns(3, 16) == 49080
+    assert binding.pg_fsm_num_patterns(1, 16) == 136
+    assert binding.pg_fsm_num_patterns(2, 16) == 136 + 16 * 136
+    assert binding.pg_fsm_num_patterns(4, 16) == 0
+
+
+def test_fsm_pattern_keys_decode_the_dense_index(lib):
+    """The library's decoder and the oracle's enumerated table agree on the
+    documented pattern numbering (shape blocks, lexicographic labels)."""
+    from oracle import brute
+    L = 3
+    for i, (shape, lab) in enumerate(brute.pattern_table(3, L)):
+        got_shape, got_lab = binding.pg_fsm_pattern_key(i, 3, L)
+        assert (got_shape, tuple(got_lab)) == (shape, tuple(lab))

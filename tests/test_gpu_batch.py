@@ -1,0 +1,120 @@
+"""GPU parity of batched motif counting (pg_batch_count_motifs): every
+graph's counts in one persistent launch must equal the oracle's counts for
+that graph alone, and the single-graph path's.  Exact integers."""
+import hashlib
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute, closed_form
+from paper_1911_06969_amd import binding, synth
+from tests.gpu_common import golden, gpu_or_skip, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return gpu_or_skip()
+
+
+def oracle_rows(graphs, k):
+    f = closed_form.motif3 if k == 3 else closed_form.motif4
+    return np.stack([f(g, nthreads=1) for g in graphs]).astype(np.uint64)
+
+
+def batch_counts(b, k, ids=None):
+    h = binding.pg_batch_load(b.voff, b.row_ptr, b.col)
+    try:
+        return binding.pg_batch_count_motifs(h, k, ids, n_graphs=b.n_graphs)
+    finally:
+        binding.pg_batch_free(h)
+
+
+def test_mixed_small_graphs(torch):
+    rng = np.random.default_rng(7)
+    graphs = [synth.gnp_small(int(rng.integers(1, 40)), float(rng.uniform(0.05, 0.9)), s) for s in range(60)]
+    graphs += [synth.empty(0), synth.empty(5), synth.complete(30), synth.star(100), synth.cycle(64),
+               synth.path(65), synth.complete_multipartite([7, 9])]
+    b = synth.batch_from_graphs(graphs)
+    for k in (3, 4):
+        assert np.array_equal(batch_counts(b, k), oracle_rows(graphs, k))
+
+
+def test_brute_force_rows(torch):
+    graphs = [synth.gnp_small(n, 0.5, n) for n in range(1, 12)]
+    b = synth.batch_from_graphs(graphs)
+    want = np.stack([brute.motif_counts(g, 4) for g in graphs]).astype(np.uint64)
+    assert np.array_equal(batch_counts(b, 4), want)
+
+
+def test_largest_graphs_and_word_boundaries(torch):
+    graphs = [synth.erdos_renyi(n, p, seed=n) for n, p in
+              [(512, 0.3), (511, 0.05), (449, 0.2), (65, 0.9), (64, 0.5), (63, 1.0), (128, 0.25)]]
+    b = synth.batch_from_graphs(graphs)
+    assert np.array_equal(batch_counts(b, 4), oracle_rows(graphs, 4))
+
+
+def test_split_items_same_counts(torch):
+    """Graphs split into several queue items (tiny split threshold)."""
+    graphs = [synth.erdos_renyi(300, 0.2, seed=s) for s in range(6)]
+    b = synth.batch_from_graphs(graphs)
+    h = binding.pg_batch_load(b.voff, b.row_ptr, b.col)
+    try:
+        binding.pg_batch_set_params(h, block_threads=128, split_work=1e4, grid_blocks=37)
+        got = binding.pg_batch_count_motifs(h, 4, None, n_graphs=b.n_graphs)
+    finally:
+        binding.pg_batch_free(h)
+    assert np.array_equal(got, oracle_rows(graphs, 4))
+
+
+def test_ids_subset_order_and_alone_vs_mixed(torch):
+    b = synth.motif_batch(300, seed=11)
+    h = binding.pg_batch_load(b.voff, b.row_ptr, b.col)
+    try:
+        whole = binding.pg_batch_count_motifs(h, 4, None, n_graphs=b.n_graphs)
+        ids = np.array([5, 3, 299, 5, 0, 150], dtype=np.int64)
+        sub = binding.pg_batch_count_motifs(h, 4, ids)
+        assert np.array_equal(sub, whole[ids])
+        for g in (0, 3, 299):
+            alone = binding.pg_batch_count_motifs(h, 4, np.array([g], dtype=np.int64))
+            assert np.array_equal(alone[0], whole[g])
+    finally:
+        binding.pg_batch_free(h)
+    sample = [0, 1, 2, 17, 100, 299]
+    assert np.array_equal(whole[sample], oracle_rows([b.graph(i) for i in sample], 4))
+
+
+def test_matches_single_graph_path(torch):
+    b = synth.motif_batch(40, seed=12)
+    got = batch_counts(b, 4)
+    for i in range(b.n_graphs):
+        with binding.Graph.from_csr(b.graph(i)) as G:
+            assert np.array_equal(G.motifs(4), got[i])
+
+
+def test_invalid_batches_rejected(torch):
+    big = synth.batch_from_graphs([synth.path(binding.PG_BATCH_MAX_VERTICES + 1)])
+    with pytest.raises(binding.PgError) as e:
+        binding.pg_batch_load(big.voff, big.row_ptr, big.col)
+    assert e.value.code == binding.PG_EINVAL
+    bad = synth.batch_from_graphs([synth.path(5)])
+    col = bad.col.copy()
+    col[0] = 9    # neighbour outside the graph
+    with pytest.raises(binding.PgError) as e:
+        binding.pg_batch_load(bad.voff, bad.row_ptr, col)
+    assert e.value.code == binding.PG_EINVAL
+
+
+@pytest.mark.slow
+def test_motif_batch_config(torch):
+    """100,000 G(n, p), n ~ U{10..400}, p ~ U[0.02, 0.3]: all graphs in one
+    persistent launch."""
+    b = synth.motif_batch()
+    want = golden("full_configs.json")["motif_batch_100k"]
+    got = batch_counts(b, 4)
+    say("batch sums", [int(x) for x in got.sum(axis=0)])
+    assert [int(x) for x in got.sum(axis=0)] == want["sum"]
+    assert [[int(x) for x in got[i]] for i in want["sample_index"]] == want["sample_rows"]
+    assert hashlib.sha256(got.astype(np.uint64).tobytes()).hexdigest() == want["sha256"]

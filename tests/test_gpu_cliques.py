@@ -19,10 +19,17 @@ def torch():
 
 
 def gpu_cliques(g, ks, budget=None):
-    with binding.Graph.from_csr(g) as G:
-        if budget:
-            G.set_memory_budget(budget)
-        return [G.cliques(k) for k in ks]
+    """Counts through both 4-clique paths (sibling masks and the general
+    level kernels); they must agree before the result is compared."""
+    out = []
+    for masks in (1, 0):
+        with binding.Graph.from_csr(g) as G:
+            if budget:
+                G.set_memory_budget(budget)
+            G.set_option(binding.PG_OPT_CLIQUE_MASKS, masks)
+            out.append([G.cliques(k) for k in ks])
+    assert out[0] == out[1], out
+    return out[0]
 
 
 def test_complete_graphs(torch):
@@ -127,5 +134,19 @@ def test_clique_rmat_config_k4(torch):
     with binding.Graph.from_csr(g) as G:
         say("scale-21 k=3")
         assert G.cliques(3) == want["k3"]
-        say("scale-21 k=4")
+        say("scale-21 k=4, sibling masks")
+        assert G.cliques(4) == want["k4"]
+        G.set_option(binding.PG_OPT_CLIQUE_MASKS, 0)
+        say("scale-21 k=4, general kernels")
+        assert G.cliques(4) == want["k4"]
+
+
+@pytest.mark.slow
+def test_clique_rmat_config_edge_blocking(torch):
+    """The scale-21 4-clique count with the level memory bounded to 1 GiB
+    (several level-2 chunks)."""
+    g = synth.clique_rmat()
+    want = golden("full_configs.json")["clique_rmat_s21"]
+    with binding.Graph.from_csr(g) as G:
+        G.set_memory_budget(1 << 30)
         assert G.cliques(4) == want["k4"]
