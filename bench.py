@@ -37,6 +37,10 @@ def parse():
                     help="copy: a plain 1 GiB device-to-device copy, the known-size reference "
                          "for scaling HBM counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 4-motif, batched and served measurements")
+    ap.add_argument("--plain-sample", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch of the dominant kernel (from rocprofv3 --pmc)")
@@ -183,14 +187,20 @@ def main():
     ms_per_step = 1000.0 * elapsed / args.steps
     value = found * args.steps / elapsed
 
-    prof = binding.pg_profile_query(dominant)
-    work = binding.pg_profile_query(work_key)
     roofline = None
     kernels = {}
     for name in binding.pg_profile_list():
         q = binding.pg_profile_query(name)
         if q and not name.endswith("_work"):
             kernels[name] = {"ms_per_step": q[0] / args.steps, "launches_per_step": q[1] / args.steps}
+    # the dominant kernel is the one with the largest time per step that
+    # records its algorithmic bytes
+    with_work = [n for n in kernels if binding.pg_profile_query(n + "_work")]
+    if with_work:
+        dominant = max(with_work, key=lambda n: kernels[n]["ms_per_step"])
+        work_key = dominant + "_work"
+    prof = binding.pg_profile_query(dominant)
+    work = binding.pg_profile_query(work_key)
     if prof and work and prof[1] > 0:
         avg_s = prof[0] / 1000.0 / prof[1]
         bytes_per_launch = work[2] / prof[1]
@@ -214,6 +224,12 @@ def main():
         else:
             cpu = cpu_baseline_motifs(g, k, args.cpu_sample_seconds)
 
+    G.close()
+    secondary = {}
+    if w == "clique4" and not args.no_secondary:
+        secondary["motif4"] = measure_motif4()
+        secondary["batch"] = measure_batch_and_serve(args)
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -232,9 +248,100 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "secondary": secondary or None,
     }
-    G.close()
     print(json.dumps(line), flush=True)
+
+
+def measure_motif4(steps: int = 2):
+    """4-motif counting on the R-MAT scale-18 graph (embeddings/s)."""
+    import torch
+
+    from paper_1911_06969_amd import binding, synth
+    g = synth.motif_rmat()
+    with binding.Graph.from_csr(g, stream=torch.cuda.current_stream()) as G:
+        res = G.motifs(4)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            res = G.motifs(4)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+    total = int(sum(int(x) for x in res))
+    return {"workload": "4-motif counting, R-MAT scale 18, edge factor 8, seed 3", "embeddings": total,
+            "ms_per_step": 1000 * dt, "embeddings_per_s": total / dt}
+
+
+def measure_batch_and_serve(args):
+    """Batched 4-motif counting of 100,000 small G(n, p) graphs in one
+    persistent launch, the plain one-graph-per-launch path on a sample of the
+    same graphs, and the serving loop at three offered loads."""
+    import numpy as np
+    import torch
+
+    from paper_1911_06969_amd import binding, serve, synth
+    out = {"workload": "4-motif counting of 100,000 G(n,p), n~U{10..400}, p~U[0.02,0.3], seed 5"}
+    b = synth.motif_batch()
+    h = binding.pg_batch_load(b.voff, b.row_ptr, b.col)
+    try:
+        tuned = os.path.join(ROOT, "profiles", "batch_tuning.json")
+        if os.path.exists(tuned):
+            from paper_1911_06969_amd import tune
+            best = tune.load(tuned)
+            binding.pg_batch_set_params(h, best["block_threads"], best["split_work"], best["grid_blocks"])
+            out["params"] = best
+        counts = binding.pg_batch_count_motifs(h, 4, None, n_graphs=b.n_graphs)   # warm-up
+        torch.cuda.synchronize()
+        reps = 3
+        t = time.perf_counter()
+        for _ in range(reps):
+            counts = binding.pg_batch_count_motifs(h, 4, None, n_graphs=b.n_graphs)
+        dt = (time.perf_counter() - t) / reps
+        emb = int(counts.sum())
+        out["batched_graphs_per_s"] = b.n_graphs / dt
+        out["batched_ms"] = 1000 * dt
+        out["batched_embeddings_per_s"] = emb / dt
+        # plain path: each graph loaded on its own, one pg_count_motifs call per graph
+        rng = np.random.default_rng(6)
+        sample = np.sort(rng.choice(b.n_graphs, args.plain_sample, replace=False))
+        graphs = [binding.Graph.from_csr(b.graph(int(i))) for i in sample]
+        for G in graphs:
+            G.motifs(4)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plain = np.stack([G.motifs(4) for G in graphs])
+        pdt = time.perf_counter() - t
+        for G in graphs:
+            G.close()
+        assert np.array_equal(plain, counts[sample]), "plain and batched counts differ"
+        # the sample's share of the batch's work, to compare like with like
+        work = binding.pg_batch_work_estimate(h, b.n_graphs)
+        frac = float(work[sample].sum() / work.sum())
+        out["plain_sample_graphs"] = int(sample.shape[0])
+        out["plain_graphs_per_s"] = sample.shape[0] / pdt
+        out["plain_seconds_for_sample"] = pdt
+        out["plain_sample_work_fraction"] = frac
+        out["batched_over_plain_graphs_per_s"] = out["batched_graphs_per_s"] / out["plain_graphs_per_s"]
+        # serving: Poisson arrivals at fractions of the batched capacity
+        fp = serve.graph_footprints(b.voff, b.row_ptr)
+        srv = serve.Server(h, fp, n_slots=4, max_batch=1024, budget_bytes=8 << 30)
+        loads = []
+        try:
+            cap = out["batched_graphs_per_s"]
+            for rho in (0.5, 0.8, 0.95):
+                ids = rng.integers(0, b.n_graphs, args.serve_requests)
+                arr = serve.poisson_arrivals(args.serve_requests, rho * cap, seed=int(rho * 100))
+                st = srv.run(ids, arr)
+                assert np.array_equal(st.results, counts[ids]), "served counts differ from the batched run"
+                loads.append({"offered_load": rho, "offered_rate": rho * cap, "requests": st.n_requests,
+                              "throughput": st.throughput, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
+                              "mean_batch": st.mean_batch})
+        finally:
+            srv.close()
+        out["serving"] = loads
+    finally:
+        binding.pg_batch_free(h)
+    return out
 
 
 def kernel_source_sha() -> str:

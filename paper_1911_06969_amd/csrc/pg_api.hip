@@ -35,6 +35,7 @@ static void require_device() {
 // to the memory budget) and the call is run again from the start.
 template <class F>
 static void run_with_arena(pg_graph* g, F&& body) {
+    g->arena.need = 0;
     for (int attempt = 0;; ++attempt) {
         g->arena.begin_call();
         try {
@@ -46,9 +47,11 @@ static void run_with_arena(pg_graph* g, F&& body) {
             (void)hipStreamSynchronize(g->stream);
             prof_flush();
             if (e.code == PG_ENOMEM && e.msg == "arena" && attempt < 12) {
-                if (g->arena.want > g->budget + (64u << 20))
+                const size_t cap = g->budget + (size_t(64) << 20);
+                if (g->arena.need > cap)
                     throw Error{PG_ENOMEM, "memory budget too small for the embedding levels (need " +
-                                               std::to_string(g->arena.want) + " bytes)"};
+                                               std::to_string(g->arena.need) + " bytes)"};
+                g->arena.want = std::min(g->arena.want, std::max(g->arena.need, cap));
                 g->arena.buf.release();
                 continue;
             }

@@ -365,6 +365,7 @@ struct BmArgs {
     const uint64_t* moff;       // first mask word of each root
     uint64_t* M;                // mask rows
     uint32_t* count;            // children of each level-1 entry
+    unsigned long long* stats;  // [3] += out-list entries streamed
 };
 
 // count pass: one wave per root; a round takes 64 of its entries, streams
@@ -373,6 +374,7 @@ struct BmArgs {
 __global__ __launch_bounds__(CQ_THREADS) void k_clique_count_masks(BmArgs A) {
     __shared__ BmLds L;
     const int w = threadIdx.x / WAVE;
+    uint64_t streamed = 0;
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
@@ -391,6 +393,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_count_masks(BmArgs A) {
                 if (x < d - 1) {
                     const int32_t v = L.S[w][x];
                     const int64_t r0 = A.rp[v], r1 = A.rp[v + 1];
+                    streamed += (uint64_t)(r1 - r0);
                     const int64_t hi = (r1 - r0 >= CQ_TRIM_MIN) ? upper_bound(A.col, r0, r1, s_last) : r1;
                     lo = r0;
                     dd = (uint32_t)(hi - r0);
@@ -440,6 +443,8 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_count_masks(BmArgs A) {
             }
         }
     }
+    streamed = wave_sum_u64(streamed);
+    if (lane() == 0 && streamed) atomicAdd(&A.stats[3], (unsigned long long)streamed);
 }
 
 // write pass: one thread per level-1 entry of the chunk emits its children
@@ -507,6 +512,102 @@ __global__ __launch_bounds__(256) void k_clique_last_masks(int64_t m, const int3
     }
 }
 
+// Deeper levels with masks (k >= 5).  An entry's children are the positions
+// set in the AND of the mask rows of all its vertices after the root; for a
+// parent segment that AND is shared, so a child only adds its own row.
+struct MaskChain {
+    const int32_t* idx[PG_KMAX + 1];    // level l >= 2: parent index (level 2: level-1 entry)
+    const uint16_t* pos[PG_KMAX + 1];   // level l >= 2: position in the root's out-list
+};
+
+struct MaskArgs {
+    XcdQueue Q;
+    int64_t p_lo;                // parents (level lev-1 entries)
+    const uint64_t* seg;         // children of parent p: seg[p] - seg_base .. seg[p+1] - seg_base
+    uint64_t seg_base;
+    int lev;                     // level of the children
+    MaskChain ch;
+    int64_t x_lo, x_hi;          // children extended (WRITE chunks)
+    const int64_t* rp;
+    const int32_t* col;
+    const int32_t* src;
+    const uint64_t* moff;
+    const uint64_t* M;
+    uint32_t* count;             // COUNT: per child
+    const uint64_t* start;       // WRITE: grandchildren of child x at start[x] - start_base
+    uint64_t start_base;
+    int32_t* out_idx;
+    int32_t* out_vid;
+    uint16_t* out_pos;
+    unsigned long long* stats;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
+    uint64_t acc = 0;
+    QueueCursor cur = queue_start();
+    int64_t it_end = 0;
+    for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
+        for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
+            const int64_t b = (int64_t)(A.seg[p] - A.seg_base);
+            const int64_t e2 = (int64_t)(A.seg[p + 1] - A.seg_base);
+            if (e2 <= b || e2 <= A.x_lo || b >= A.x_hi) continue;
+            // the parent's ancestry: positions of its vertices after the root
+            int32_t apos[PG_KMAX];
+            int na = 0;
+            int64_t c = p;
+            for (int l = A.lev - 1; l >= 2; --l) {
+                apos[na++] = A.ch.pos[l][c];
+                c = A.ch.idx[l][c];
+            }
+            const int64_t e = c;                  // level-1 entry
+            const int32_t r = A.src[e];
+            const int64_t rb = A.rp[r];
+            const int32_t d = (int32_t)(A.rp[r + 1] - rb);
+            const int W = (d + 63) >> 6;
+            const uint64_t* blk = A.M + A.moff[r];
+            // S of the parent, one word per lane
+            uint64_t sp = 0;
+            if (lane() < W) {
+                sp = blk[(uint64_t)(e - rb) * W + lane()];
+                for (int a = 0; a < na; ++a) sp &= blk[(uint64_t)apos[a] * W + lane()];
+            }
+            const int64_t x0 = max<int64_t>(b, A.x_lo), x1 = min<int64_t>(e2, A.x_hi);
+            for (int64_t xb = x0; xb < x1; xb += WAVE) {
+                const int64_t x = xb + lane();
+                const bool valid = x < x1;
+                const int32_t px = valid ? A.ch.pos[A.lev][x] : 0;
+                const uint64_t* row = blk + (uint64_t)px * W;
+                uint32_t cnt = 0;
+                uint64_t outp = 0;
+                if (MODE == MODE_WRITE && valid) outp = A.start[x] - A.start_base;
+                for (int q = 0; q < W; ++q) {
+                    const uint64_t s = (uint64_t)__shfl((long long)sp, q, WAVE);
+                    uint64_t bits = valid ? (s & row[q]) : 0;
+                    if (MODE == MODE_WRITE) {
+                        while (bits) {
+                            const int j = q * 64 + __ffsll((unsigned long long)bits) - 1;
+                            bits &= bits - 1;
+                            A.out_idx[outp] = (int32_t)x;
+                            A.out_vid[outp] = A.col[rb + j];
+                            A.out_pos[outp] = (uint16_t)j;
+                            ++outp;
+                        }
+                    } else {
+                        cnt += (uint32_t)__popcll(bits);
+                    }
+                }
+                if (MODE == MODE_COUNT && valid) A.count[x] = cnt;
+                if (MODE == MODE_LAST) acc += cnt;
+            }
+        }
+    }
+    if (MODE == MODE_LAST) {
+        acc = wave_sum_u64(acc);
+        if (lane() == 0 && acc) atomicAdd(&A.stats[0], (unsigned long long)acc);
+    }
+}
+
 __global__ void k_mask_words(int64_t n, const int64_t* __restrict__ rp, uint32_t* __restrict__ words) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = rp[r + 1] - rp[r];
@@ -517,6 +618,116 @@ __global__ void k_mask_words(int64_t n, const int64_t* __restrict__ rp, uint32_t
 static unsigned grid_threads(int64_t items) {
     int64_t b = (items + 255) / 256;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)device_info().n_cu * 32));
+}
+
+struct MaskCtx {
+    const int64_t* rp;
+    const int32_t* col;
+    const int32_t* src;
+    const uint64_t* moff;
+    const uint64_t* M;
+};
+
+template <int MODE>
+static void launch_mask(CliqueRun& R, MaskArgs A, int64_t p_lo, int64_t n_par, const char* name, double units) {
+    if (n_par <= 0) return;
+    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, R.s);
+    A.Q.next = R.qctr;
+    A.Q.n_items = n_par;
+    A.Q.chunk = n_par >= R.waves * 64 ? 16 : (n_par >= R.waves * 8 ? 4 : 1);
+    A.p_lo = p_lo;
+    A.stats = R.stats;
+    ProfScope ps(name, R.s, units);
+    k_clique_mask_level<MODE><<<R.blocks, CQ_THREADS, 0, R.s>>>(A);
+    PG_HIP(hipGetLastError());
+}
+
+// Level `lev` (>= 2) entries [0, m), in segments of parents [p_lo, p_hi) at
+// level lev-1, extended through the remaining levels with masks.
+static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, const uint64_t* seg,
+                        uint64_t seg_base, int64_t p_lo, int64_t p_hi, int64_t m) {
+    pg_graph* g = R.g;
+    Arena& ar = g->arena;
+    MaskArgs A{};
+    A.seg = seg;
+    A.seg_base = seg_base;
+    A.lev = lev;
+    A.ch = ch;
+    A.x_lo = 0;
+    A.x_hi = m;
+    A.rp = X.rp;
+    A.col = X.col;
+    A.src = X.src;
+    A.moff = X.moff;
+    A.M = X.M;
+    if (lev == R.k - 2) {
+        launch_mask<MODE_LAST>(R, A, p_lo, p_hi - p_lo, "clique_last", 0.0);
+        return;
+    }
+    if (m <= 0) return;
+    const size_t mk = ar.mark();
+    uint32_t* cnt = push<uint32_t>(ar, m);
+    uint64_t* start = push<uint64_t>(ar, m + 1);
+    A.count = cnt;
+    launch_mask<MODE_COUNT>(R, A, p_lo, p_hi - p_lo, "clique_count_l", (double)m);
+    scan_u32(cnt, m, start, ar, R.s);
+    const uint64_t total = read_u64(start + m, R.s);
+    if (total == 0) {
+        ar.reset(mk);
+        return;
+    }
+    const bool next_last = (lev + 1 == R.k - 2);
+    const uint64_t per = next_last ? 10 : 10 + 4 + 8;
+    const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
+    const uint64_t cap = std::max<uint64_t>(room / (per * (next_last ? 1 : 2)), (uint64_t)g->dag.max_out + 1);
+    const int64_t nb = (int64_t)((total + cap - 1) / cap);
+    std::vector<int64_t> hc(nb + 1), hp(nb + 1);
+    std::vector<uint64_t> hs(nb + 1);
+    if (nb == 1) {
+        hc[0] = 0; hc[1] = m;
+        hp[0] = p_lo; hp[1] = p_hi - 1;
+        hs[0] = 0; hs[1] = total;
+    } else {
+        const size_t mk2 = ar.mark();
+        int64_t* dc = push<int64_t>(ar, nb + 1);
+        int64_t* dp = push<int64_t>(ar, nb + 1);
+        uint64_t* ds = push<uint64_t>(ar, nb + 1);
+        k_chunk_bounds<<<(unsigned)((nb + 1 + 255) / 256), 256, 0, R.s>>>(
+            start, m, cap, nb, reinterpret_cast<const int64_t*>(seg) + p_lo, (int64_t)seg_base, p_hi - p_lo, dc, dp, ds);
+        PG_HIP(hipGetLastError());
+        PG_HIP(hipMemcpyAsync(hc.data(), dc, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, R.s));
+        PG_HIP(hipMemcpyAsync(hp.data(), dp, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost, R.s));
+        PG_HIP(hipMemcpyAsync(hs.data(), ds, sizeof(uint64_t) * (nb + 1), hipMemcpyDeviceToHost, R.s));
+        PG_HIP(hipStreamSynchronize(R.s));
+        ar.reset(mk2);
+        for (int64_t j = 0; j <= nb; ++j) hp[j] += p_lo;
+    }
+    uint64_t biggest = 0;
+    for (int64_t j = 0; j < nb; ++j) biggest = std::max<uint64_t>(biggest, hs[j + 1] - hs[j]);
+    int32_t* n_idx = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
+    int32_t* n_vid = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
+    uint16_t* n_pos = push<uint16_t>(ar, std::max<uint64_t>(biggest, 1));
+    for (int64_t j = 0; j < nb; ++j) {
+        const int64_t c0 = hc[j], c1 = hc[j + 1];
+        const uint64_t mm = hs[j + 1] - hs[j];
+        if (c1 <= c0 || mm == 0) continue;
+        MaskArgs W = A;
+        W.x_lo = c0;
+        W.x_hi = c1;
+        W.start = start;
+        W.start_base = hs[j];
+        W.out_idx = n_idx;
+        W.out_vid = n_vid;
+        W.out_pos = n_pos;
+        const int64_t q_lo = hp[j];
+        const int64_t q_hi = (nb == 1 || j + 1 == nb) ? p_hi : hp[j + 1] + 1;
+        launch_mask<MODE_WRITE>(R, W, q_lo, q_hi - q_lo, "clique_write_l", (double)mm);
+        MaskChain nc = ch;
+        nc.idx[lev + 1] = n_idx;
+        nc.pos[lev + 1] = n_pos;
+        mask_levels(R, X, lev + 1, nc, start, hs[j], c0, c1, (int64_t)mm);
+    }
+    ar.reset(mk);
 }
 
 static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
@@ -553,6 +764,7 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
         A.moff = moff;
         A.M = M;
         A.count = cnt;
+        A.stats = R.stats;
         ProfScope ps("clique_count", s, (double)E);
         k_clique_count_masks<<<R.blocks, CQ_THREADS, 0, s>>>(A);
         PG_HIP(hipGetLastError());
@@ -596,11 +808,17 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
                                                                        l2_idx, l2_vid, l2_pos);
             PG_HIP(hipGetLastError());
         }
-        {
+        if (R.k == 4) {
             ProfScope ps("clique_last", s, 0.0);
             k_clique_last_masks<<<grid_threads((int64_t)m2), 256, 0, s>>>((int64_t)m2, l2_idx, l2_pos, l2_vid, rp,
                                                                           src, moff, M, R.stats);
             PG_HIP(hipGetLastError());
+        } else {
+            MaskCtx X{rp, col, src, moff, M};
+            MaskChain ch{};
+            ch.idx[2] = l2_idx;
+            ch.pos[2] = l2_pos;
+            mask_levels(R, X, 2, ch, start, hs[j], c0, c1, (int64_t)m2);
         }
     }
     // input entries of the last level
@@ -628,19 +846,22 @@ uint64_t count_cliques(pg_graph* g, int k) {
     R.stats = reinterpret_cast<unsigned long long*>(small);
     R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
     fill_u64(small, 8, 0, s);
-    if (k == 4 && g->dag.max_out <= BM_MAXD && !g->force_generic) {
+    if (k >= 4 && g->dag.max_out <= BM_MAXD && !g->force_generic) {
         count_cliques4_masks(g, R);
     } else {
         // level L1: entries = DAG edges, parents = vertices (segment = out-list)
         extend_level(R, 1, g->dag.rp.as<int64_t>(), 0, 0, g->n, g->dag.col.as<int32_t>(), 0, g->dag.n_edges);
     }
-    uint64_t st[3] = {0, 0, 0};
+    uint64_t st[4] = {0, 0, 0, 0};
     PG_HIP(hipMemcpyAsync(st, small, sizeof(st), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (prof_on()) {
-        // record the last level's algorithmic work: input entries and the
-        // out-degrees of their newest vertices
+        // algorithmic bytes: the last level reads per input entry its SoA
+        // entry and two row pointers (16 B) and streams the out-list of its
+        // newest vertex (4 B per entry); the sibling-mask count pass reads
+        // per level-1 entry 24 B and streams the out-list of its vertex
         ProfScope ps("clique_last_work", s, 16.0 * (double)st[1] + 4.0 * (double)st[2]);
+        if (st[3]) ProfScope pc("clique_count_work", s, 24.0 * (double)g->dag.n_edges + 4.0 * (double)st[3]);
     }
     return st[0];
 }

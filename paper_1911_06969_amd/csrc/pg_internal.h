@@ -72,6 +72,7 @@ struct Arena {
     size_t top = 0;
     size_t high = 0;   // high-water mark of the last call
     size_t want = 0;   // capacity to grow to before the next call
+    size_t need = 0;   // largest size a push of this call required
     void begin_call();
     void* push(size_t bytes);   // 256-byte aligned; throws PG_ENOMEM when full
     size_t mark() const { return top; }
@@ -123,6 +124,11 @@ struct MotifL1 {
     DevBuf seg;              // int64[n+1]: edges of vertex u are seg[u]..seg[u+1]-1
     DevBuf src;              // int32[n_edges] = u
     DevBuf dst;              // int32[n_edges] = v (> u), ascending within u
+    // dense adjacency rows of high-degree vertices (membership in O(1))
+    bool hubs_built = false;
+    int64_t n_hubs = 0, hub_words = 0;
+    DevBuf hub_id;           // int32[n]: row of the vertex, or -1
+    DevBuf hub_bits;         // uint32[n_hubs][hub_words]
 };
 
 }  // namespace pg

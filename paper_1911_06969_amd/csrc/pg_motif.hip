@@ -109,6 +109,11 @@ struct MotifArgs {
     int32_t* scratch;           // per-wave common-neighbour lists longer than MO_CMAX
     int64_t scratch_per_wave;
     unsigned long long* out;    // pattern counters (6) + work stats
+    // dense rows of high-degree vertices: hub_id[v] >= 0 selects row
+    // hub_bits + hub_id[v] * hub_words (bit u set iff u ~ v)
+    const int32_t* hub_id;
+    const uint32_t* hub_bits;
+    int64_t hub_words;
 };
 
 // --------------------------------------------------------------- helpers
@@ -116,6 +121,27 @@ struct MotifArgs {
 template <class P>
 __device__ __forceinline__ bool member(P a, int32_t len, int32_t key) {
     return contains(a, len, key);
+}
+
+__device__ __forceinline__ const uint32_t* hub_row(const MotifArgs& A, int32_t v) {
+    const int32_t h = A.hub_id[v];
+    return h >= 0 ? A.hub_bits + (int64_t)h * A.hub_words : nullptr;
+}
+
+__device__ __forceinline__ bool bit_has(const uint32_t* row, int32_t u) {
+    return (row[(uint32_t)u >> 5] >> (u & 31)) & 1u;
+}
+
+// membership in a sorted list, through its dense row when it has one
+template <class P>
+__device__ __forceinline__ bool adj_has(const uint32_t* row, P a, int32_t len, int32_t u) {
+    return row ? bit_has(row, u) : member(a, len, u);
+}
+
+// relative cost of one membership test: 1 through LDS or a dense row,
+// otherwise the depth of a binary search in global memory
+__device__ __forceinline__ int32_t probe_cost(bool cheap, int32_t len) {
+    return cheap ? 1 : 32 - __clz(max(len, 1));
 }
 
 // ---------------------------------------------------------- level 1 -> 2
@@ -128,6 +154,7 @@ struct L1Lds {
     int32_t v1[MO_WAVES][WAVE];
     int32_t na[MO_WAVES][WAVE];     // |A0 above v1|
     int32_t opt[MO_WAVES][WAVE];    // COUNT/LAST3: 0 iterate A0', 1 iterate A1'
+    int32_t hb1[MO_WAVES][WAVE];    // dense row of v1, or -1
     uint32_t c_all[MO_WAVES][WAVE];
     uint32_t c_hi[MO_WAVES][WAVE];
 };
@@ -135,7 +162,7 @@ struct L1Lds {
 template <int MODE, class P0>
 __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, int w, int32_t v0, P0 A0,
                                                  int32_t d0, int64_t r0, int64_t b, int32_t s,
-                                                 uint64_t (&acc)[6]) {
+                                                 uint64_t (&acc)[6], const uint32_t* h0, bool a0_cheap) {
     // A0' = A0 above v0, at positions [a0lo, d0)
     const int32_t a0lo = (int32_t)upper_bound(A0, 0, d0, v0);
     const int32_t x0 = (int32_t)max<int64_t>(0, A.x_lo - b);
@@ -150,11 +177,15 @@ __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, i
             const int32_t d1p = (int32_t)(q1 - lo1);
             const int32_t na = d0 - (int32_t)upper_bound(A0, a0lo, d0, v1);
             const int32_t d0p = d0 - a0lo;
+            const int32_t hb1 = A.hub_id[v1];
             int opt = 0;
             if (MODE == ML1_WRITE) {
                 work = (uint32_t)(na + d1p);
             } else {
-                opt = (d0p <= d1p) ? 0 : 1;
+                // iterate A0' probing A1, or A1' probing A0: the cheaper total
+                const int64_t c0 = (int64_t)d0p * probe_cost(hb1 >= 0, (int32_t)(q1 - q0));
+                const int64_t c1 = (int64_t)d1p * probe_cost(a0_cheap, d0);
+                opt = (c0 <= c1) ? 0 : 1;
                 work = (uint32_t)(opt == 0 ? d0p : d1p);
             }
             L.lo1[w][lane()] = lo1;
@@ -162,6 +193,7 @@ __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, i
             L.v1[w][lane()] = v1;
             L.na[w][lane()] = na;
             L.opt[w][lane()] = opt;
+            L.hb1[w][lane()] = hb1;
         }
         const uint32_t inc = wave_incl_scan(work);
         const uint32_t W = bcast(inc, WAVE - 1);
@@ -186,15 +218,20 @@ __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, i
                 if (valid) {
                     const uint32_t j = t - L.pre[w][xi];
                     const int32_t v1 = L.v1[w][xi];
-                    const int64_t q0 = A.rp[v1], q1 = A.rp[v1 + 1];
+                    const int32_t hb1 = L.hb1[w][xi];
                     int32_t u;
                     bool f;
                     if (L.opt[w][xi] == 0) {
                         u = A0[a0lo + j];
-                        f = member(A.col + q0, (int32_t)(q1 - q0), u);
+                        if (hb1 >= 0) {
+                            f = bit_has(A.hub_bits + (int64_t)hb1 * A.hub_words, u);
+                        } else {
+                            const int64_t q0 = A.rp[v1], q1 = A.rp[v1 + 1];
+                            f = member(A.col + q0, (int32_t)(q1 - q0), u);
+                        }
                     } else {
                         u = A.col[L.lo1[w][xi] + j];
-                        f = member(A0, d0, u);
+                        f = adj_has(h0, A0, d0, u);
                     }
                     if (f) {
                         atomicAdd(&L.c_all[w][xi], 1u);
@@ -211,14 +248,21 @@ __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, i
                     const uint32_t j = t - L.pre[w][xi];
                     const int32_t v1 = L.v1[w][xi];
                     const int32_t na = L.na[w][xi];
-                    const int64_t q0 = A.rp[v1], q1 = A.rp[v1 + 1];
+                    const int32_t hb1 = L.hb1[w][xi];
                     if ((int32_t)j < na) {
                         u = A0[d0 - na + (int32_t)j];
-                        code = 1 | (member(A.col + q0, (int32_t)(q1 - q0), u) ? 2 : 0);
+                        bool a12;
+                        if (hb1 >= 0) {
+                            a12 = bit_has(A.hub_bits + (int64_t)hb1 * A.hub_words, u);
+                        } else {
+                            const int64_t q0 = A.rp[v1], q1 = A.rp[v1 + 1];
+                            a12 = member(A.col + q0, (int32_t)(q1 - q0), u);
+                        }
+                        code = 1 | (a12 ? 2 : 0);
                         emit = true;
                     } else {
                         u = A.col[L.lo1[w][xi] + (j - (uint32_t)na)];
-                        emit = !member(A0, d0, u);
+                        emit = !adj_has(h0, A0, d0, u);
                         code = 2;
                     }
                 }
@@ -276,9 +320,10 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_l1(MotifArgs A) {
             if (d0 <= MO_STAGE) {
                 for (int i = lane(); i < d0; i += WAVE) L.A0[w][i] = A.col[r0 + i];
                 wave_sync();
-                motif_l1_segment<MODE>(A, L, w, v0, &L.A0[w][0], d0, r0, b, s, acc);
+                motif_l1_segment<MODE>(A, L, w, v0, &L.A0[w][0], d0, r0, b, s, acc, nullptr, true);
             } else {
-                motif_l1_segment<MODE>(A, L, w, v0, A.col + r0, d0, r0, b, s, acc);
+                const uint32_t* h0 = hub_row(A, v0);
+                motif_l1_segment<MODE>(A, L, w, v0, A.col + r0, d0, r0, b, s, acc, h0, h0 != nullptr);
             }
             wave_sync();
         }
@@ -304,19 +349,23 @@ struct L4Lds {
     int32_t len2[MO_WAVES][WAVE];    // degree of v2
     int32_t v2[MO_WAVES][WAVE];
     int32_t opt[MO_WAVES][WAVE];
+    int32_t hb2[MO_WAVES][WAVE];     // dense row of v2, or -1
     uint32_t cnt[MO_WAVES][WAVE][6]; // I02 lo/hi, I12 lo/hi, I012 lo/hi
 };
 
 // Children of one L1 entry (v0, v1).  A0/A1: the two adjacency lists (LDS or
-// global), C: A0 and A1 above v0 intersected (sorted, LDS or scratch).
+// global) with their dense rows h0/h1 when they have one, C: A0 and A1
+// above v0 intersected (sorted, LDS or scratch).
 template <class P0, class P1, class PC>
 __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L, int w, int32_t v0, int32_t v1,
                                                     P0 A0, int32_t d0, P1 A1, int32_t d1, PC C, int32_t nc,
                                                     int64_t b, int32_t s, uint64_t (&acc)[6],
-                                                    uint64_t& items) {
+                                                    uint64_t& items, const uint32_t* h0, const uint32_t* h1,
+                                                    bool cheap0, bool cheap1) {
     const int32_t a0lo = (int32_t)upper_bound(A0, 0, d0, v0);
     const int32_t a1lo = (int32_t)upper_bound(A1, 0, d1, v0);
     const int32_t d0p = d0 - a0lo, d1p = d1 - a1lo;
+    const int32_t pc0 = probe_cost(cheap0, d0), pc1 = probe_cost(cheap1, d1);
     for (int32_t xc = 0; xc < s; xc += WAVE) {
         const int32_t x = xc + lane();
         uint32_t work = 0;
@@ -329,15 +378,20 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
             s1 = A.rp[v2 + 1];
             lo2 = upper_bound(A.col, s0, s1, v0);
             const int32_t d2p = (int32_t)(s1 - lo2);
-            // iterate A2' and search A0, A1 (2 searches each), or iterate A0'
-            // (2 searches) and A1' (1 search) and search A2
-            const int opt = (2 * d2p <= 2 * d0p + d1p) ? 0 : 1;
+            const int32_t hb2 = A.hub_id[v2];
+            const int32_t pc2 = probe_cost(hb2 >= 0, (int32_t)(s1 - s0));
+            // iterate A2' probing A0 and A1, or iterate A0' (probing A2 and A1)
+            // and A1' (probing A2): the cheaper total
+            const int64_t cost0 = (int64_t)d2p * (pc0 + pc1);
+            const int64_t cost1 = (int64_t)d0p * (pc2 + pc1) + (int64_t)d1p * pc2;
+            const int opt = (cost0 <= cost1) ? 0 : 1;
             work = (uint32_t)(opt == 0 ? d2p : d0p + d1p);
             L.lo2[w][lane()] = lo2;
             L.base2[w][lane()] = s0;
             L.len2[w][lane()] = (int32_t)(s1 - s0);
             L.v2[w][lane()] = v2;
             L.opt[w][lane()] = opt;
+            L.hb2[w][lane()] = hb2;
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) L.cnt[w][lane()][c] = 0;
@@ -363,25 +417,27 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
                 const int32_t cv2 = L.v2[w][xi];
                 if (L.opt[w][xi] == 0) {
                     const int32_t u = A.col[L.lo2[w][xi] + j];
-                    const bool b0 = member(A0, d0, u);
-                    const bool b1 = member(A1, d1, u);
+                    const bool b0 = adj_has(h0, A0, d0, u);
+                    const bool b1 = adj_has(h1, A1, d1, u);
                     const int r = u > cv2;
                     if (b0) atomicAdd(&L.cnt[w][xi][0 + r], 1u);
                     if (b1) atomicAdd(&L.cnt[w][xi][2 + r], 1u);
                     if (b0 && b1) atomicAdd(&L.cnt[w][xi][4 + r], 1u);
                 } else {
-                    const int64_t base2 = L.base2[w][xi];
+                    const int32_t hb2 = L.hb2[w][xi];
+                    const uint32_t* h2 = hb2 >= 0 ? A.hub_bits + (int64_t)hb2 * A.hub_words : nullptr;
+                    const int32_t* g2 = A.col + L.base2[w][xi];
                     const int32_t len2 = L.len2[w][xi];
                     if ((int32_t)j < d0p) {
                         const int32_t u = A0[a0lo + (int32_t)j];
-                        if (member(A.col + base2, len2, u)) {
+                        if (adj_has(h2, g2, len2, u)) {
                             const int r = u > cv2;
                             atomicAdd(&L.cnt[w][xi][0 + r], 1u);
-                            if (member(A1, d1, u)) atomicAdd(&L.cnt[w][xi][4 + r], 1u);
+                            if (adj_has(h1, A1, d1, u)) atomicAdd(&L.cnt[w][xi][4 + r], 1u);
                         }
                     } else {
                         const int32_t u = A1[a1lo + (int32_t)j - d0p];
-                        if (member(A.col + base2, len2, u)) atomicAdd(&L.cnt[w][xi][2 + (u > cv2)], 1u);
+                        if (adj_has(h2, g2, len2, u)) atomicAdd(&L.cnt[w][xi][2 + (u > cv2)], 1u);
                     }
                 }
             }
@@ -456,6 +512,8 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
             // C = A0 and A1 above v0, intersected: iterate the shorter, search the longer
             const int32_t* gA0 = A.col + r0;
             const int32_t* gA1 = A.col + q0;
+            const uint32_t* h0 = st0 ? nullptr : hub_row(A, v0);
+            const uint32_t* h1 = st1 ? nullptr : hub_row(A, v1);
             const bool it0 = d0 <= d1;
             const int32_t di = it0 ? d0 : d1;
             int32_t nc = 0;
@@ -467,10 +525,10 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
                 if (j < di) {
                     if (it0) {
                         u = st0 ? L.A0[w][j] : gA0[j];
-                        f = u > v0 && (st1 ? member(&L.A1[w][0], d1, u) : member(gA1, d1, u));
+                        f = u > v0 && (st1 ? member(&L.A1[w][0], d1, u) : adj_has(h1, gA1, d1, u));
                     } else {
                         u = st1 ? L.A1[w][j] : gA1[j];
-                        f = u > v0 && (st0 ? member(&L.A0[w][0], d0, u) : member(gA0, d0, u));
+                        f = u > v0 && (st0 ? member(&L.A0[w][0], d0, u) : adj_has(h0, gA0, d0, u));
                     }
                 }
                 const uint64_t F = ballot(f);
@@ -485,18 +543,20 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
             __threadfence_block();
             wave_sync();
             // dispatch on where each list lives (all wave-uniform)
+            const bool ch0 = st0 || h0 != nullptr, ch1 = st1 || h1 != nullptr;
+            const int32_t* sc = scratch;
             if (st0 && st1) {
-                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, s, acc, items);
-                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, (const int32_t*)scratch, nc, b, s, acc, items);
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, s, acc, items, h0, h1, ch0, ch1);
+                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, sc, nc, b, s, acc, items, h0, h1, ch0, ch1);
             } else if (st0) {
-                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, &L.C[w][0], nc, b, s, acc, items);
-                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, (const int32_t*)scratch, nc, b, s, acc, items);
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, &L.C[w][0], nc, b, s, acc, items, h0, h1, ch0, ch1);
+                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, sc, nc, b, s, acc, items, h0, h1, ch0, ch1);
             } else if (st1) {
-                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, s, acc, items);
-                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, (const int32_t*)scratch, nc, b, s, acc, items);
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, s, acc, items, h0, h1, ch0, ch1);
+                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, sc, nc, b, s, acc, items, h0, h1, ch0, ch1);
             } else {
-                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, &L.C[w][0], nc, b, s, acc, items);
-                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, (const int32_t*)scratch, nc, b, s, acc, items);
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, &L.C[w][0], nc, b, s, acc, items, h0, h1, ch0, ch1);
+                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, sc, nc, b, s, acc, items, h0, h1, ch0, ch1);
             }
             wave_sync();
         }
@@ -533,7 +593,67 @@ static MotifArgs base_args(pg_graph* g) {
     A.l1_seg = g->ml1.seg.as<int64_t>();
     A.l1_src = g->ml1.src.as<int32_t>();
     A.l1_dst = g->ml1.dst.as<int32_t>();
+    A.hub_id = g->ml1.hub_id.as<int32_t>();
+    A.hub_bits = g->ml1.hub_bits.as<uint32_t>();
+    A.hub_words = g->ml1.hub_words;
     return A;
+}
+
+__global__ __launch_bounds__(256) void k_hub_rows(int64_t n_hubs, const int32_t* __restrict__ hubs,
+                                                  const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  int64_t words, uint32_t* __restrict__ bits) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t h = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; h < n_hubs; h += waves) {
+        const int32_t v = hubs[h];
+        uint32_t* row = bits + h * words;
+        for (int64_t j = rp[v] + lane(); j < rp[v + 1]; j += WAVE) {
+            const uint32_t u = (uint32_t)col[j];
+            atomicOr(row + (u >> 5), 1u << (u & 31));
+        }
+    }
+}
+
+// Dense adjacency rows for the vertices whose lists are too long to stage in
+// LDS (degree > MO_STAGE), within a memory cap (the highest degrees first
+// when the cap binds).
+static void build_hubs(pg_graph* g) {
+    MotifL1& L = g->ml1;
+    if (L.hubs_built) return;
+    hipStream_t s = g->stream;
+    const int64_t n = g->n;
+    std::vector<int64_t> hrp((size_t)n + 1);
+    PG_HIP(hipMemcpyAsync(hrp.data(), g->rp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    const int64_t words = (n + 31) / 32;
+    const uint64_t cap = std::min<uint64_t>(uint64_t(2) << 30, std::max<uint64_t>(g->budget / 8, 1));
+    int64_t thr = MO_STAGE + 1;
+    std::vector<int32_t> hubs;
+    while (true) {
+        hubs.clear();
+        for (int64_t v = 0; v < n; ++v)
+            if (hrp[v + 1] - hrp[v] >= thr) hubs.push_back((int32_t)v);
+        if ((uint64_t)hubs.size() * (uint64_t)words * 4 <= cap) break;
+        thr *= 2;
+    }
+    std::vector<int32_t> id((size_t)std::max<int64_t>(n, 1), -1);
+    for (size_t h = 0; h < hubs.size(); ++h) id[(size_t)hubs[h]] = (int32_t)h;
+    L.hub_id.reserve(sizeof(int32_t) * id.size());
+    PG_HIP(hipMemcpyAsync(L.hub_id.p, id.data(), sizeof(int32_t) * id.size(), hipMemcpyHostToDevice, s));
+    L.n_hubs = (int64_t)hubs.size();
+    L.hub_words = words;
+    L.hub_bits.reserve(sizeof(uint32_t) * std::max<int64_t>(L.n_hubs * words, 1));
+    if (L.n_hubs > 0) {
+        DevBuf hl;
+        hl.reserve(sizeof(int32_t) * hubs.size());
+        PG_HIP(hipMemcpyAsync(hl.p, hubs.data(), sizeof(int32_t) * hubs.size(), hipMemcpyHostToDevice, s));
+        fill_u32(L.hub_bits.as<uint32_t>(), L.n_hubs * words, 0, s);
+        k_hub_rows<<<(unsigned)std::min<int64_t>((L.n_hubs + 3) / 4, 4096), 256, 0, s>>>(
+            L.n_hubs, hl.as<int32_t>(), g->rp.as<int64_t>(), g->col.as<int32_t>(), words, L.hub_bits.as<uint32_t>());
+        PG_HIP(hipGetLastError());
+        PG_HIP(hipStreamSynchronize(s));
+    }
+    PG_HIP(hipStreamSynchronize(s));
+    L.hubs_built = true;
 }
 
 static void set_queue(MotifRun& R, MotifArgs& A, int64_t p_lo, int64_t n_items) {
@@ -590,6 +710,7 @@ __global__ void k_chunk_entries(const uint64_t* __restrict__ start, int64_t m, u
 void count_motifs(pg_graph* g, int k, uint64_t* counts) {
     PG_REQUIRE(k == 3 || k == 4, PG_EUNSUPPORTED, "motif size must be 3 or 4");
     build_motif_l1(g);
+    build_hubs(g);
     const int64_t E = g->ml1.n_edges;
     for (int i = 0; i < (k == 3 ? 2 : 6); ++i) counts[i] = 0;
     if (E == 0) return;

@@ -74,7 +74,7 @@ void DevBuf::release() {
 void Arena::begin_call() {
     top = 0;
     high = 0;
-    want = std::max<size_t>(want, size_t(64) << 20);
+    want = std::max<size_t>(want, size_t(4) << 20);
     if (want > buf.bytes) buf.reserve(want);
 }
 
@@ -82,7 +82,8 @@ void* Arena::push(size_t bytes) {
     size_t b = (bytes + 255) & ~size_t(255);
     if (top + b > buf.bytes) {
         // Remember the size this call needed; the caller retries after growth.
-        want = std::max(want, top + b + (top + b) / 4);
+        need = std::max(need, top + b);
+        want = std::max(want, need + need / 4);
         throw Error{PG_ENOMEM, "arena"};
     }
     void* p = static_cast<char*>(buf.p) + top;
