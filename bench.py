@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="clique4", choices=["clique4", "clique5", "motif4", "motif3", "tc", "copy"],
+    ap.add_argument("--workload", default="clique4", choices=["clique4", "clique5", "motif4", "motif3", "tc", "fsm", "copy", "tune-batch"],
                     help="copy: a plain 1 GiB device-to-device copy, the known-size reference "
                          "for scaling HBM counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -144,7 +144,28 @@ def main():
         print(json.dumps({"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
                           "ms_per_copy": 1000 * dt, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
         return
-    if w in ("clique4", "clique5"):
+    if w == "tune-batch":
+        from paper_1911_06969_amd import tune
+        b = synth.motif_batch()
+        h = binding.pg_batch_load(b.voff, b.row_ptr, b.col)
+        rng = np.random.default_rng(9)
+        ids = np.sort(rng.choice(b.n_graphs, 20000, replace=False))
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        best, table = tune.tune(h, ids, n_cu, log=lambda r: print(json.dumps(r), flush=True))
+        binding.pg_batch_free(h)
+        out = os.path.join(ROOT, "gpurun_out", "batch_tuning.json")
+        os.makedirs(os.path.dirname(out), exist_ok=True)
+        tune.save(out, best, table, "sample: 20,000 of the 100,000 graphs of the motif batch (seed 9)")
+        print(json.dumps({"best": best}), flush=True)
+        return
+    if w == "fsm":
+        g = synth.fsm_er()
+        run = lambda G: G.fsm(3, 1000)[1]  # noqa: E731
+        dominant, work_key = "fsm_l3_bits", "fsm_l3_bits_work"
+        workload = {"workload": "frequent subgraph mining up to 3 edges, sigma 1000, labelled G(n,p) "
+                                "n=500,000, average degree 8, 16 labels, seed 4",
+                    "vertices": g.n, "edges": g.n_edges}
+    elif w in ("clique4", "clique5"):
         g = synth.clique_rmat()
         k = 4 if w == "clique4" else 5
         run = lambda G: G.cliques(k)  # noqa: E731
@@ -184,6 +205,11 @@ def main():
     binding.pg_profile_enable(False)
 
     found = int(np.sum(result)) if not isinstance(result, int) else result
+    if w == "fsm":
+        # embeddings generated per step (all levels); result = frequent patterns
+        emb = binding.pg_profile_query("fsm_embeddings")
+        workload["frequent_patterns"] = result
+        found = int(emb[2] / args.steps) if emb else 0
     ms_per_step = 1000.0 * elapsed / args.steps
     value = found * args.steps / elapsed
 
@@ -221,7 +247,7 @@ def main():
     if not args.no_cpu_baseline:
         if w.startswith("clique") or w == "tc":
             cpu = cpu_baseline_cliques(g, k, args.cpu_sample_seconds)
-        else:
+        elif w.startswith("motif"):
             cpu = cpu_baseline_motifs(g, k, args.cpu_sample_seconds)
 
     G.close()

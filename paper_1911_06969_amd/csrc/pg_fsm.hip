@@ -561,6 +561,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
     unsigned long long* n_emb = reinterpret_cast<unsigned long long*>(push<uint64_t>(ar, 4));
     fill_u64(reinterpret_cast<uint64_t*>(n_emb), 4, 0, s);
 
+    int64_t n2_total = 0;
     // ---------------- level 1: every edge; Reduce; Filter
     int32_t* pid1 = push<int32_t>(ar, std::max<int64_t>(E, 1));
     {
@@ -596,6 +597,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
         }
         scan_u32(c2, m1, st2, ar, s);
         const int64_t n2 = (int64_t)read_u64(st2 + m1, s);
+        n2_total = n2;
         int32_t* a2 = push<int32_t>(ar, std::max<int64_t>(n2, 1));
         int32_t* b2 = push<int32_t>(ar, std::max<int64_t>(n2, 1));
         int32_t* p2 = push<int32_t>(ar, std::max<int64_t>(n2, 1));
@@ -640,8 +642,15 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
         }
     }
     std::vector<uint64_t> h((size_t)np);
+    uint64_t n3 = 0;
     PG_HIP(hipMemcpyAsync(h.data(), sup_pat, sizeof(uint64_t) * np, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(&n3, n_emb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
+    if (prof_on()) {
+        // embeddings generated at every level (levels 2 and 3 from the
+        // filtered parents)
+        ProfScope ps("fsm_embeddings", s, (double)E + (double)n2_total + (double)n3);
+    }
     size_t nf = 0;
     for (int64_t p = 0; p < np; ++p) {
         supports[p] = h[p];
