@@ -28,6 +28,11 @@ METRIC = "embeddings/s, 4-clique & 4-motif on RMAT; batched graphs/s vs plain, p
 HBM_PEAK_GBS = 8000.0
 
 
+def note(*msg):
+    """Progress of the run, on stderr (stdout carries only the JSON line)."""
+    print("[bench]", *msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,11 +193,13 @@ def main():
         workload = {"workload": f"{k}-motif counting, R-MAT scale 18 (262,144 vertices), edge factor 8, "
                                 f"undirected int32 CSR, seed 3", "k": k, "vertices": g.n, "edges": g.n_edges}
 
+    note("workload", w, "graph ready:", g.n, "vertices")
     G = binding.Graph.from_csr(g, stream=stream)
     result = None
     for _ in range(args.warmup):
         result = run(G)
     torch.cuda.synchronize()
+    note("warm-up done")
 
     binding.pg_profile_reset()
     binding.pg_profile_enable(True)
@@ -203,6 +210,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     binding.pg_profile_enable(False)
+    note(f"timed {args.steps} steps in {elapsed:.3f} s")
 
     found = int(np.sum(result)) if not isinstance(result, int) else result
     if w == "fsm":
@@ -245,6 +253,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        note("cpu baseline (oracle)")
         if w.startswith("clique") or w == "tc":
             cpu = cpu_baseline_cliques(g, k, args.cpu_sample_seconds)
         elif w.startswith("motif"):
@@ -253,7 +262,9 @@ def main():
     G.close()
     secondary = {}
     if w == "clique4" and not args.no_secondary:
+        note("secondary: 4-motif")
         secondary["motif4"] = measure_motif4()
+        note("secondary: batched graphs, plain sample, serving")
         secondary["batch"] = measure_batch_and_serve(args)
 
     line = {
@@ -327,6 +338,7 @@ def measure_batch_and_serve(args):
         out["batched_graphs_per_s"] = b.n_graphs / dt
         out["batched_ms"] = 1000 * dt
         out["batched_embeddings_per_s"] = emb / dt
+        note(f"batched: {1000 * dt:.1f} ms for {b.n_graphs} graphs")
         # plain path: each graph loaded on its own, one pg_count_motifs call per graph
         rng = np.random.default_rng(6)
         sample = np.sort(rng.choice(b.n_graphs, args.plain_sample, replace=False))
@@ -339,6 +351,7 @@ def measure_batch_and_serve(args):
         pdt = time.perf_counter() - t
         for G in graphs:
             G.close()
+        note(f"plain: {pdt:.2f} s for {sample.shape[0]} graphs")
         assert np.array_equal(plain, counts[sample]), "plain and batched counts differ"
         # the sample's share of the batch's work, to compare like with like
         work = binding.pg_batch_work_estimate(h, b.n_graphs)
@@ -358,6 +371,7 @@ def measure_batch_and_serve(args):
                 ids = rng.integers(0, b.n_graphs, args.serve_requests)
                 arr = serve.poisson_arrivals(args.serve_requests, rho * cap, seed=int(rho * 100))
                 st = srv.run(ids, arr)
+                note(f"served load {rho}: p50 {st.p50_ms:.2f} ms p99 {st.p99_ms:.2f} ms")
                 assert np.array_equal(st.results, counts[ids]), "served counts differ from the batched run"
                 loads.append({"offered_load": rho, "offered_rate": rho * cap, "requests": st.n_requests,
                               "throughput": st.throughput, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,

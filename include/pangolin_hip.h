@@ -197,7 +197,10 @@ int pg_batch_count_motifs(pg_batch* b, int k, const int64_t* ids, int64_t n_ids,
  * batched launch (copy in, clear, count, copy out), replayed on the slot's
  * stream for every submission.  Slots on different streams run
  * concurrently; they share only the read-only batch.
- *   pg_batch_slot_create  max_ids >= 1; stream: hipStream_t (NULL = null stream)
+ *   pg_batch_slot_create  max_ids >= 1; stream: hipStream_t; NULL makes the
+ *                         slot create (and later destroy) a non-blocking
+ *                         stream of its own, since the null stream cannot
+ *                         be captured
  *   pg_batch_slot_submit  enqueues the counts of ids[0..n_ids) (host array,
  *                         n_ids <= max_ids) and returns at once; the slot
  *                         must be idle (PG_EINVAL otherwise)

@@ -521,6 +521,7 @@ struct pg_batch_slot {
     hipGraph_t graph[2] = {nullptr, nullptr};          // k = 3, k = 4
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
+    bool own_stream = false;           // created here because the caller passed the null stream
     bool pending = false;
     int pending_k = 4;
     int64_t pending_n = 0;
@@ -534,6 +535,7 @@ struct pg_batch_slot {
         if (h_items) (void)hipHostFree(h_items);
         if (h_n) (void)hipHostFree(h_n);
         if (h_out) (void)hipHostFree(h_out);
+        if (own_stream && s) (void)hipStreamDestroy(s);
     }
 };
 
@@ -606,6 +608,10 @@ int pg_batch_slot_create(pg_batch* b, int64_t max_ids, void* stream, pg_batch_sl
         try {
             S->b = b;
             S->s = static_cast<hipStream_t>(stream);
+            if (S->s == nullptr) {   // the null stream cannot be captured
+                PG_HIP(hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking));
+                S->own_stream = true;
+            }
             S->max_ids = max_ids;
             S->max_items = max_ids * SLOT_PARTS;
             PG_HIP(hipHostMalloc((void**)&S->h_ids, sizeof(int64_t) * max_ids, hipHostMallocDefault));
@@ -668,10 +674,9 @@ int pg_batch_slot_wait(pg_batch_slot* S, uint64_t* counts) {
         PG_REQUIRE(S != nullptr, PG_EINVAL, "slot is NULL");
         if (!S->pending) return;
         PG_HIP(hipEventSynchronize(S->done));
+        // the kernel packs rows of the submission's width (2 for k = 3)
         const int width = S->pending_k == 3 ? 2 : 6;
-        if (counts)
-            for (int64_t i = 0; i < S->pending_n; ++i)
-                for (int c = 0; c < width; ++c) counts[i * width + c] = S->h_out[i * 6 + c];
+        if (counts) std::memcpy(counts, S->h_out, sizeof(uint64_t) * S->pending_n * width);
         S->pending = false;
     });
 }
