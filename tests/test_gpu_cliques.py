@@ -150,3 +150,18 @@ def test_clique_rmat_config_edge_blocking(torch):
     with binding.Graph.from_csr(g) as G:
         G.set_memory_budget(1 << 30)
         assert G.cliques(4) == want["k4"]
+
+
+@pytest.mark.slow
+def test_clique_rmat_config_k5(torch):
+    """R-MAT scale 21: the 5-clique count at full size, on the mask levels
+    and with the general kernels under a 4 GiB level budget (chunked)."""
+    g = synth.clique_rmat()
+    want = golden("full_configs.json")["clique_rmat_s21_k5"]
+    with binding.Graph.from_csr(g) as G:
+        say("scale-21 k=5, sibling masks")
+        assert G.cliques(5) == want["k5"]
+        G.set_option(binding.PG_OPT_CLIQUE_MASKS, 0)
+        G.set_memory_budget(4 << 30)
+        say("scale-21 k=5, general kernels, 4 GiB")
+        assert G.cliques(5) == want["k5"]
