@@ -8,8 +8,9 @@ level, and the fused last level.  The graph and its degree-ordered DAG are
 device resident before timing starts (preprocessing and host-to-device
 copies are excluded, as in the paper's evaluation).
 
-Prints one JSON line.  `roofline` is for the dominant kernel (the fused
-last level), from HIP events recorded around every launch during the timed
+Prints one JSON line.  `roofline` is for the dominant kernel (the one
+with the most time per step among the kernels that record their algorithmic
+bytes), from HIP events recorded around every launch during the timed
 steps; `cpu_baseline` times the CPU oracle on a bounded sample of the same
 workload (rank 0, N = 1 only).
 """

@@ -228,6 +228,7 @@ struct CliqueRun {
     unsigned long long* qctr;   // N_XCD counters
     int64_t waves;
     int blocks;
+    uint64_t mwords = 0;        // mask path: words of all mask rows
 };
 
 template <int MODE>
@@ -341,174 +342,209 @@ static void extend_level(CliqueRun& R, int lev, const int64_t* seg, int64_t seg_
 // of out(r).  So the count pass over the out-list of root r records, for
 // each of r's level-1 entries i, its children as a bitmask over the
 // positions of out(r) (row i of r's mask block) together with their number.
-// The write pass emits the level-2 structure of arrays (idx = parent entry,
-// vid = vertex, and the vertex's position in out(r), a memo of the
-// connectivity test) from the masks.  The fused last level then counts, for
+// The write pass emits the level-2 structure of arrays from the masks:
+// idx = parent entry and pos = the new vertex's position in out(r), which
+// names the vertex (out(r)[pos]) and memoizes where its own row is, so no
+// vid column is stored.  The fused last level then counts, for
 // every level-2 entry (r, v1, w) at positions i1, j, the common later
 // neighbours of r, v1 and w as popcount(row i1 AND row j): bits of row j are
 // positions above j, so every 4-clique is counted once.
 
 constexpr int BM_MAXD = 768;             // roots with out-degree up to this use masks
 constexpr int BM_W = BM_MAXD / 64;       // 64-bit words per mask row
+constexpr int BM_UNROLL = 4;             // out-list elements per lane in flight
+
+// Level-1 entry e = (r, S[i]) is described by one word: the first mask word
+// of r's block, i, and the row width W (words):  base << 14 | i << 4 | W.
+__host__ __device__ constexpr uint64_t row_info(uint64_t base, int i, int W) {
+    return (base << 14) | ((uint64_t)i << 4) | (uint64_t)W;
+}
+__device__ __forceinline__ int info_w(uint64_t info) { return (int)(info & 15); }
+__device__ __forceinline__ int info_i(uint64_t info) { return (int)((info >> 4) & 1023); }
+__device__ __forceinline__ uint64_t info_base(uint64_t info) { return info >> 14; }
 
 struct BmLds {
     int32_t S[CQ_WAVES][BM_MAXD];
-    uint64_t rows[CQ_WAVES][WAVE][BM_W];
-    uint32_t pre[CQ_WAVES][WAVE];
-    int64_t lo[CQ_WAVES][WAVE];
+    unsigned long long row[CQ_WAVES][BM_W];
 };
 
 struct BmArgs {
-    XcdQueue Q;
+    XcdQueue Q;                 // items: roots, heaviest (highest rank) first
     const int64_t* rp;          // DAG
     const int32_t* col;
     const uint64_t* moff;       // first mask word of each root
     uint64_t* M;                // mask rows
     uint32_t* count;            // children of each level-1 entry
+    uint64_t* info;             // row_info of each level-1 entry
     unsigned long long* stats;  // [3] += out-list entries streamed
 };
 
-// count pass: one wave per root; a round takes 64 of its entries, streams
-// their out-lists (cut at the root's last out-neighbour) and sets the bit of
-// every candidate found in out(r) (binary search in the LDS copy)
-__global__ __launch_bounds__(CQ_THREADS) void k_clique_count_masks(BmArgs A) {
+// count pass: one wave per root r, out(r) staged in LDS.  The wave walks
+// r's level-1 entries in order; for entry i (vertex v = S[i]) all 64 lanes
+// stream out(v) together, BM_UNROLL coalesced loads per lane in flight,
+// and look each candidate up in S[i+1, d) with a branch-free binary search
+// whose trip count is the same for every lane.  Hits set bits of row i in
+// LDS; the finished row goes to HBM and its popcount is i's child count.
+// The stream stops once it passes the root's last out-neighbour.
+__global__ __launch_bounds__(CQ_THREADS, 8) void k_clique_count_masks(BmArgs A) {
     __shared__ BmLds L;
     const int w = threadIdx.x / WAVE;
-    uint64_t streamed = 0;
+    int32_t* S = L.S[w];
+    unsigned long long* row = L.row[w];
+    uint64_t streamed = 0;   // wave-uniform
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
-        for (int64_t r = it; r < it_end; ++r) {
+        for (int64_t item = it; item < it_end; ++item) {
+            const int64_t r = A.Q.n_items - 1 - item;
             const int64_t b = A.rp[r];
             const int32_t d = (int32_t)(A.rp[r + 1] - b);
-            if (d < 2) continue;   // counts are pre-zeroed; rows are never read
+            if (d < 2) continue;   // counts are pre-zeroed; rows and infos are never read
             const int W = (d + 63) >> 6;
-            for (int i = lane(); i < d; i += WAVE) L.S[w][i] = A.col[b + i];
+            for (int k = lane(); k < d; k += WAVE) S[k] = A.col[b + k];
             wave_sync();
-            const int32_t s_last = L.S[w][d - 1];
+            const int32_t s_last = S[d - 1];
+            const uint64_t base = A.moff[r];
+            uint64_t* Mr = A.M + base;
             for (int32_t xc = 0; xc < d; xc += WAVE) {
-                const int32_t x = xc + lane();
-                int64_t lo = 0;
-                uint32_t dd = 0;
-                if (x < d - 1) {
-                    const int32_t v = L.S[w][x];
-                    const int64_t r0 = A.rp[v], r1 = A.rp[v + 1];
-                    streamed += (uint64_t)(r1 - r0);
-                    const int64_t hi = (r1 - r0 >= CQ_TRIM_MIN) ? upper_bound(A.col, r0, r1, s_last) : r1;
-                    lo = r0;
-                    dd = (uint32_t)(hi - r0);
+                // out-list bounds of the round's entries, one per lane
+                const int32_t xl = xc + lane();
+                int64_t lo = 0, hi = 0;
+                if (xl < d - 1) {
+                    const int32_t v = S[xl];
+                    lo = A.rp[v];
+                    hi = A.rp[v + 1];
                 }
-                const uint32_t inc = wave_incl_scan(dd);
-                const uint32_t Wt = bcast(inc, WAVE - 1);
-                L.pre[w][lane()] = inc - dd;
-                L.lo[w][lane()] = lo;
-#pragma unroll
-                for (int q = 0; q < BM_W; ++q) L.rows[w][lane()][q] = 0;
-                wave_sync();
+                uint32_t mine = 0;
                 const int nx = min(WAVE, d - xc);
-                for (uint32_t t0 = 0; t0 < Wt; t0 += WAVE) {
-                    const uint32_t t = t0 + lane();
-                    if (t < Wt) {
-                        int xi = 0;
-                        int n_i = nx;
-                        while (n_i > 1) {
-                            const int half = n_i >> 1;
-                            if (L.pre[w][xi + half] <= t) xi += half;
-                            n_i -= half;
+                for (int xi = 0; xi < nx; ++xi) {
+                    const int32_t x = xc + xi;
+                    const int64_t l = (int64_t)readlane64((uint64_t)lo, xi);
+                    const int64_t h = (int64_t)readlane64((uint64_t)hi, xi);
+                    if (lane() < W) row[lane()] = 0ull;
+                    wave_sync();
+                    const int32_t len = d - x - 1;   // >= 1 whenever l < h
+                    for (int64_t t0 = l; t0 < h; t0 += WAVE * BM_UNROLL) {
+                        int32_t u[BM_UNROLL], p[BM_UNROLL];
+#pragma unroll
+                        for (int q = 0; q < BM_UNROLL; ++q) {
+                            const int64_t t = t0 + q * WAVE + lane();
+                            u[q] = t < h ? A.col[t] : 0x7fffffff;
+                            p[q] = x + 1;
                         }
-                        const int32_t u = A.col[L.lo[w][xi] + (t - L.pre[w][xi])];
-                        // position of u among the later out-neighbours of r
-                        const int32_t after = xc + xi + 1;
-                        int32_t base = after, len = d - after;
-                        while (len > 1) {
-                            const int32_t half = len >> 1;
-                            base = (L.S[w][base + half] <= u) ? base + half : base;
-                            len -= half;
+                        // invariant: the answer lies in [p, p + n) within [x + 1, d)
+                        for (int32_t n = len; n > 1;) {
+                            const int32_t half = n >> 1;
+#pragma unroll
+                            for (int q = 0; q < BM_UNROLL; ++q) p[q] = (S[p[q] + half] <= u[q]) ? p[q] + half : p[q];
+                            n -= half;
                         }
-                        if (len == 1 && L.S[w][base] == u)
-                            atomicOr((unsigned long long*)&L.rows[w][xi][base >> 6], 1ull << (base & 63));
+#pragma unroll
+                        for (int q = 0; q < BM_UNROLL; ++q)
+                            if (S[p[q]] == u[q]) atomicOr(&row[p[q] >> 6], 1ull << (p[q] & 63));
+                        streamed += (uint64_t)min<int64_t>(h - t0, WAVE * BM_UNROLL);
+                        if (readlane(u[BM_UNROLL - 1], WAVE - 1) > s_last) break;
                     }
+                    wave_sync();
+                    const unsigned long long word = lane() < W ? row[lane()] : 0ull;
+                    if (lane() < W) Mr[(uint64_t)x * W + lane()] = word;
+                    const uint32_t c = wave_sum_u32((uint32_t)__popcll(word));
+                    if (lane() == xi) mine = c;
+                    wave_sync();
                 }
-                wave_sync();
-                // counts, then the rows to HBM (word t of the round's block per lane)
-                if (x < d) {
-                    uint32_t c = 0;
-                    for (int q = 0; q < W; ++q) c += (uint32_t)__popcll(L.rows[w][lane()][q]);
-                    A.count[b + x] = c;
+                if (xl < d) {
+                    A.count[b + xl] = mine;
+                    A.info[b + xl] = row_info(base, xl, W);
                 }
-                const int rows_here = min(WAVE, d - xc);
-                uint64_t* dst = A.M + A.moff[r] + (uint64_t)xc * W;
-                for (int q = lane(); q < rows_here * W; q += WAVE) dst[q] = L.rows[w][q / W][q % W];
-                wave_sync();
             }
         }
     }
-    streamed = wave_sum_u64(streamed);
     if (lane() == 0 && streamed) atomicAdd(&A.stats[3], (unsigned long long)streamed);
 }
 
-// write pass: one thread per level-1 entry of the chunk emits its children
-__global__ __launch_bounds__(256) void k_clique_write_masks(int64_t e_lo, int64_t e_hi, const int64_t* __restrict__ rp,
-                                                            const int32_t* __restrict__ col,
-                                                            const int32_t* __restrict__ src,
-                                                            const uint64_t* __restrict__ moff,
+// write pass: a wave takes 64 consecutive level-1 entries (one per lane,
+// which loads its row), then, entry by entry, compacts the set bits of the
+// row a word at a time with a ballot: lane j handles bit j, so consecutive
+// children go to consecutive slots and the stores coalesce.  A level-2
+// entry is (parent level-1 entry, position in the root's out-list); its
+// vertex is the root's out-neighbour at that position.
+__global__ __launch_bounds__(256) void k_clique_write_masks(int64_t e_lo, int64_t e_hi,
+                                                            const uint64_t* __restrict__ info,
                                                             const uint64_t* __restrict__ M,
                                                             const uint64_t* __restrict__ start, uint64_t start_base,
-                                                            int32_t* __restrict__ out_idx, int32_t* __restrict__ out_vid,
-                                                            uint16_t* __restrict__ out_pos) {
-    for (int64_t e = e_lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < e_hi;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t pos = start[e] - start_base;
-        const uint64_t end = start[e + 1] - start_base;
-        if (pos == end) continue;
-        const int32_t r = src[e];
-        const int64_t b = rp[r];
-        const int32_t d = (int32_t)(rp[r + 1] - b);
-        const int W = (d + 63) >> 6;
-        const int32_t i = (int32_t)(e - b);
-        const uint64_t* row = M + moff[r] + (uint64_t)i * W;
-        for (int q = 0; q < W; ++q) {
-            uint64_t bits = row[q];
-            while (bits) {
-                const int j = q * 64 + __ffsll((unsigned long long)bits) - 1;
-                bits &= bits - 1;
-                out_idx[pos] = (int32_t)e;
-                out_vid[pos] = col[b + j];
-                out_pos[pos] = (uint16_t)j;
-                ++pos;
+                                                            int32_t* __restrict__ out_idx,
+                                                            uint16_t* __restrict__ out_pos,
+                                                            unsigned long long* __restrict__ stats) {
+    uint64_t read = 0;   // info and row bytes of the entries with children
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    for (int64_t e0 = e_lo + wave_id * WAVE; e0 < e_hi; e0 += n_waves * WAVE) {
+        const int64_t e = e0 + lane();
+        uint64_t s0 = 0, s1 = 0;
+        if (e < e_hi) {
+            s0 = start[e] - start_base;
+            s1 = start[e + 1] - start_base;
+        }
+        const bool has = s1 > s0;
+        int Wl = 0;
+        uint64_t words[BM_W];
+        {
+            const uint64_t f = has ? info[e] : 0;
+            Wl = info_w(f);
+            const uint64_t* rowp = M + info_base(f) + (uint64_t)info_i(f) * Wl;
+#pragma unroll
+            for (int q = 0; q < BM_W; ++q) words[q] = q < Wl ? rowp[q] : 0ull;
+            if (has) read += 8u + 8u * (uint64_t)Wl;
+        }
+        uint64_t todo = ballot(has);
+        while (todo) {
+            const int li = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            uint64_t pos = readlane64(s0, li);
+            const int Wi = readlane(Wl, li);
+            const int32_t parent = (int32_t)(e0 + li);
+#pragma unroll
+            for (int q = 0; q < BM_W; ++q) {
+                if (q < Wi) {
+                    const uint64_t wq = readlane64(words[q], li);
+                    if ((wq >> lane()) & 1ull) {
+                        const uint64_t slot = pos + (uint64_t)__popcll(wq & lanemask_lt());
+                        out_idx[slot] = parent;
+                        out_pos[slot] = (uint16_t)(q * 64 + lane());
+                    }
+                    pos += (uint64_t)__popcll(wq);
+                }
             }
         }
     }
+    read = wave_sum_u64(read);
+    if (lane() == 0 && read) atomicAdd(&stats[4], (unsigned long long)read);
 }
 
-// fused last level: one thread per level-2 entry
+// fused last level: one thread per level-2 entry (r, S[i], S[j]), i < j:
+// the 4-cliques it extends to are the set bits of row i AND row j (row j
+// only has bits above j, so each is counted once)
 __global__ __launch_bounds__(256) void k_clique_last_masks(int64_t m, const int32_t* __restrict__ idx,
                                                            const uint16_t* __restrict__ pos,
-                                                           const int32_t* __restrict__ vid,
-                                                           const int64_t* __restrict__ rp,
-                                                           const int32_t* __restrict__ src,
-                                                           const uint64_t* __restrict__ moff,
+                                                           const uint64_t* __restrict__ info,
                                                            const uint64_t* __restrict__ M,
                                                            unsigned long long* __restrict__ stats) {
-    uint64_t found = 0, deg_sum = 0;
+    uint64_t found = 0, words = 0;
     for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < m; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t e = idx[x];
-        const int32_t r = src[e];
-        const int64_t b = rp[r];
-        const int32_t d = (int32_t)(rp[r + 1] - b);
-        const int W = (d + 63) >> 6;
-        const uint64_t* blk = M + moff[r];
-        const uint64_t* r1 = blk + (uint64_t)(e - b) * W;
-        const uint64_t* r2 = blk + (uint64_t)pos[x] * W;
-        for (int q = 0; q < W; ++q) found += (uint64_t)__popcll(r1[q] & r2[q]);
-        const int32_t v = vid[x];
-        deg_sum += (uint64_t)(rp[v + 1] - rp[v]);
+        const uint64_t f = info[idx[x]];
+        const int W = info_w(f);
+        const uint64_t* blk = M + info_base(f);
+        const uint64_t* r1 = blk + (uint64_t)info_i(f) * W;
+        const int j = pos[x];
+        const uint64_t* r2 = blk + (uint64_t)j * W;
+        for (int q = j >> 6; q < W; ++q) found += (uint64_t)__popcll(r1[q] & r2[q]);
+        words += (uint64_t)(W - (j >> 6));
     }
     found = wave_sum_u64(found);
-    deg_sum = wave_sum_u64(deg_sum);
-    if (lane() == 0 && (found | deg_sum)) {
+    words = wave_sum_u64(words);
+    if (lane() == 0 && (found | words)) {
         atomicAdd(&stats[0], (unsigned long long)found);
-        atomicAdd(&stats[2], (unsigned long long)deg_sum);
+        atomicAdd(&stats[2], (unsigned long long)words);
     }
 }
 
@@ -528,16 +564,12 @@ struct MaskArgs {
     int lev;                     // level of the children
     MaskChain ch;
     int64_t x_lo, x_hi;          // children extended (WRITE chunks)
-    const int64_t* rp;
-    const int32_t* col;
-    const int32_t* src;
-    const uint64_t* moff;
+    const uint64_t* info;        // row_info of each level-1 entry
     const uint64_t* M;
     uint32_t* count;             // COUNT: per child
     const uint64_t* start;       // WRITE: grandchildren of child x at start[x] - start_base
     uint64_t start_base;
     int32_t* out_idx;
-    int32_t* out_vid;
     uint16_t* out_pos;
     unsigned long long* stats;
 };
@@ -560,45 +592,57 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
                 apos[na++] = A.ch.pos[l][c];
                 c = A.ch.idx[l][c];
             }
-            const int64_t e = c;                  // level-1 entry
-            const int32_t r = A.src[e];
-            const int64_t rb = A.rp[r];
-            const int32_t d = (int32_t)(A.rp[r + 1] - rb);
-            const int W = (d + 63) >> 6;
-            const uint64_t* blk = A.M + A.moff[r];
+            const uint64_t f = A.info[c];         // c: the level-1 entry
+            const int W = info_w(f);
+            const uint64_t* blk = A.M + info_base(f);
             // S of the parent, one word per lane
             uint64_t sp = 0;
             if (lane() < W) {
-                sp = blk[(uint64_t)(e - rb) * W + lane()];
+                sp = blk[(uint64_t)info_i(f) * W + lane()];
                 for (int a = 0; a < na; ++a) sp &= blk[(uint64_t)apos[a] * W + lane()];
             }
+            uint64_t s[BM_W];
+#pragma unroll
+            for (int q = 0; q < BM_W; ++q) s[q] = q < W ? readlane64(sp, q) : 0ull;
             const int64_t x0 = max<int64_t>(b, A.x_lo), x1 = min<int64_t>(e2, A.x_hi);
             for (int64_t xb = x0; xb < x1; xb += WAVE) {
                 const int64_t x = xb + lane();
                 const bool valid = x < x1;
                 const int32_t px = valid ? A.ch.pos[A.lev][x] : 0;
                 const uint64_t* row = blk + (uint64_t)px * W;
+                uint64_t words[BM_W];
                 uint32_t cnt = 0;
-                uint64_t outp = 0;
-                if (MODE == MODE_WRITE && valid) outp = A.start[x] - A.start_base;
-                for (int q = 0; q < W; ++q) {
-                    const uint64_t s = (uint64_t)__shfl((long long)sp, q, WAVE);
-                    uint64_t bits = valid ? (s & row[q]) : 0;
-                    if (MODE == MODE_WRITE) {
-                        while (bits) {
-                            const int j = q * 64 + __ffsll((unsigned long long)bits) - 1;
-                            bits &= bits - 1;
-                            A.out_idx[outp] = (int32_t)x;
-                            A.out_vid[outp] = A.col[rb + j];
-                            A.out_pos[outp] = (uint16_t)j;
-                            ++outp;
-                        }
-                    } else {
-                        cnt += (uint32_t)__popcll(bits);
-                    }
+#pragma unroll
+                for (int q = 0; q < BM_W; ++q) {
+                    words[q] = (valid && q < W) ? (s[q] & row[q]) : 0ull;
+                    cnt += (uint32_t)__popcll(words[q]);
                 }
                 if (MODE == MODE_COUNT && valid) A.count[x] = cnt;
                 if (MODE == MODE_LAST) acc += cnt;
+                if (MODE == MODE_WRITE) {
+                    // children of the wave's entries, entry by entry, each
+                    // word compacted by a ballot (coalesced stores)
+                    const uint64_t s0 = valid ? A.start[x] - A.start_base : 0;
+                    uint64_t todo = ballot(cnt != 0);
+                    while (todo) {
+                        const int li = __ffsll((unsigned long long)todo) - 1;
+                        todo &= todo - 1;
+                        uint64_t o = readlane64(s0, li);
+                        const int32_t parent = (int32_t)(xb + li);
+#pragma unroll
+                        for (int q = 0; q < BM_W; ++q) {
+                            if (q < W) {
+                                const uint64_t wq = readlane64(words[q], li);
+                                if ((wq >> lane()) & 1ull) {
+                                    const uint64_t slot = o + (uint64_t)__popcll(wq & lanemask_lt());
+                                    A.out_idx[slot] = parent;
+                                    A.out_pos[slot] = (uint16_t)(q * 64 + lane());
+                                }
+                                o += (uint64_t)__popcll(wq);
+                            }
+                        }
+                    }
+                }
             }
         }
     }
@@ -621,10 +665,7 @@ static unsigned grid_threads(int64_t items) {
 }
 
 struct MaskCtx {
-    const int64_t* rp;
-    const int32_t* col;
-    const int32_t* src;
-    const uint64_t* moff;
+    const uint64_t* info;
     const uint64_t* M;
 };
 
@@ -655,10 +696,7 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
     A.ch = ch;
     A.x_lo = 0;
     A.x_hi = m;
-    A.rp = X.rp;
-    A.col = X.col;
-    A.src = X.src;
-    A.moff = X.moff;
+    A.info = X.info;
     A.M = X.M;
     if (lev == R.k - 2) {
         launch_mask<MODE_LAST>(R, A, p_lo, p_hi - p_lo, "clique_last", 0.0);
@@ -677,7 +715,7 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
         return;
     }
     const bool next_last = (lev + 1 == R.k - 2);
-    const uint64_t per = next_last ? 10 : 10 + 4 + 8;
+    const uint64_t per = next_last ? 6 : 6 + 4 + 8;
     const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
     const uint64_t cap = std::max<uint64_t>(room / (per * (next_last ? 1 : 2)), (uint64_t)g->dag.max_out + 1);
     const int64_t nb = (int64_t)((total + cap - 1) / cap);
@@ -705,7 +743,6 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
     uint64_t biggest = 0;
     for (int64_t j = 0; j < nb; ++j) biggest = std::max<uint64_t>(biggest, hs[j + 1] - hs[j]);
     int32_t* n_idx = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
-    int32_t* n_vid = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
     uint16_t* n_pos = push<uint16_t>(ar, std::max<uint64_t>(biggest, 1));
     for (int64_t j = 0; j < nb; ++j) {
         const int64_t c0 = hc[j], c1 = hc[j + 1];
@@ -717,7 +754,6 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
         W.start = start;
         W.start_base = hs[j];
         W.out_idx = n_idx;
-        W.out_vid = n_vid;
         W.out_pos = n_pos;
         const int64_t q_lo = hp[j];
         const int64_t q_hi = (nb == 1 || j + 1 == nb) ? p_hi : hp[j + 1] + 1;
@@ -737,7 +773,7 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     const int64_t E = g->dag.n_edges;
     const int64_t* rp = g->dag.rp.as<int64_t>();
     const int32_t* col = g->dag.col.as<int32_t>();
-    const int32_t* src = g->dag.src.as<int32_t>();
+    PG_REQUIRE(E <= INT32_MAX, PG_EUNSUPPORTED, "level-2 parent indices are 32-bit: too many DAG edges");
     // mask block offsets
     uint64_t* moff = push<uint64_t>(ar, n + 1);
     {
@@ -751,8 +787,10 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     const uint64_t mwords = read_u64(moff + n, s);
     uint64_t* M = push<uint64_t>(ar, std::max<uint64_t>(mwords, 1));
     uint32_t* cnt = push<uint32_t>(ar, E);
+    uint64_t* info = push<uint64_t>(ar, E);
     uint64_t* start = push<uint64_t>(ar, E + 1);
     fill_u32(cnt, E, 0, s);
+    R.mwords = mwords;
     {
         BmArgs A;
         fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, s);
@@ -764,6 +802,7 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
         A.moff = moff;
         A.M = M;
         A.count = cnt;
+        A.info = info;
         A.stats = R.stats;
         ProfScope ps("clique_count", s, (double)E);
         k_clique_count_masks<<<R.blocks, CQ_THREADS, 0, s>>>(A);
@@ -772,9 +811,12 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     scan_u32(cnt, E, start, ar, s);
     const uint64_t total = read_u64(start + E, s);
     if (total == 0) return 0;
-    // edge blocking over level-1 entries: 10 bytes per level-2 entry
+    // edge blocking over level-1 entries: 6 bytes per level-2 entry, and
+    // for k >= 5 its child count and offset (12 B) plus room for a chunk of
+    // the next level
     const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
-    const uint64_t cap = std::max<uint64_t>(room / 10, (uint64_t)g->dag.max_out + 1);
+    const uint64_t per = R.k == 4 ? 6 : 6 + 4 + 8;
+    const uint64_t cap = std::max<uint64_t>(room / (per * (R.k == 4 ? 1 : 2)), (uint64_t)g->dag.max_out + 1);
     const int64_t nb = (int64_t)((total + cap - 1) / cap);
     std::vector<int64_t> hc(nb + 1), hp(nb + 1);
     std::vector<uint64_t> hs(nb + 1);
@@ -796,7 +838,6 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     uint64_t biggest = 0;
     for (int64_t j = 0; j < nb; ++j) biggest = std::max<uint64_t>(biggest, hs[j + 1] - hs[j]);
     int32_t* l2_idx = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
-    int32_t* l2_vid = push<int32_t>(ar, std::max<uint64_t>(biggest, 1));
     uint16_t* l2_pos = push<uint16_t>(ar, std::max<uint64_t>(biggest, 1));
     for (int64_t j = 0; j < nb; ++j) {
         const int64_t c0 = hc[j], c1 = hc[j + 1];
@@ -804,17 +845,17 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
         if (c1 <= c0 || m2 == 0) continue;
         {
             ProfScope ps("clique_write", s, (double)m2);
-            k_clique_write_masks<<<grid_threads(c1 - c0), 256, 0, s>>>(c0, c1, rp, col, src, moff, M, start, hs[j],
-                                                                       l2_idx, l2_vid, l2_pos);
+            k_clique_write_masks<<<grid_threads(c1 - c0), 256, 0, s>>>(c0, c1, info, M, start, hs[j], l2_idx, l2_pos,
+                                                                       R.stats);
             PG_HIP(hipGetLastError());
         }
         if (R.k == 4) {
             ProfScope ps("clique_last", s, 0.0);
-            k_clique_last_masks<<<grid_threads((int64_t)m2), 256, 0, s>>>((int64_t)m2, l2_idx, l2_pos, l2_vid, rp,
-                                                                          src, moff, M, R.stats);
+            k_clique_last_masks<<<grid_threads((int64_t)m2), 256, 0, s>>>((int64_t)m2, l2_idx, l2_pos, info, M,
+                                                                          R.stats);
             PG_HIP(hipGetLastError());
         } else {
-            MaskCtx X{rp, col, src, moff, M};
+            MaskCtx X{info, M};
             MaskChain ch{};
             ch.idx[2] = l2_idx;
             ch.pos[2] = l2_pos;
@@ -846,22 +887,34 @@ uint64_t count_cliques(pg_graph* g, int k) {
     R.stats = reinterpret_cast<unsigned long long*>(small);
     R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
     fill_u64(small, 8, 0, s);
-    if (k >= 4 && g->dag.max_out <= BM_MAXD && !g->force_generic) {
+    const bool masks = k >= 4 && g->dag.max_out <= BM_MAXD && !g->force_generic;
+    if (masks) {
         count_cliques4_masks(g, R);
     } else {
         // level L1: entries = DAG edges, parents = vertices (segment = out-list)
         extend_level(R, 1, g->dag.rp.as<int64_t>(), 0, 0, g->n, g->dag.col.as<int32_t>(), 0, g->dag.n_edges);
     }
-    uint64_t st[4] = {0, 0, 0, 0};
+    uint64_t st[5] = {0, 0, 0, 0, 0};
     PG_HIP(hipMemcpyAsync(st, small, sizeof(st), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (prof_on()) {
-        // algorithmic bytes: the last level reads per input entry its SoA
-        // entry and two row pointers (16 B) and streams the out-list of its
-        // newest vertex (4 B per entry); the sibling-mask count pass reads
-        // per level-1 entry 24 B and streams the out-list of its vertex
-        ProfScope ps("clique_last_work", s, 16.0 * (double)st[1] + 4.0 * (double)st[2]);
-        if (st[3]) ProfScope pc("clique_count_work", s, 24.0 * (double)g->dag.n_edges + 4.0 * (double)st[3]);
+        // algorithmic bytes of one call, per kernel
+        const double E = (double)g->dag.n_edges;
+        if (!masks) {
+            // last level: per input entry its SoA entry and a row-pointer
+            // pair (16 B), and the out-list of its newest vertex (4 B each)
+            ProfScope ps("clique_last_work", s, 16.0 * (double)st[1] + 4.0 * (double)st[2]);
+        } else {
+            // count pass: per level-1 entry its vertex, row-pointer pair,
+            // count and row info (32 B) and its mask row; 4 B per streamed
+            // out-list element
+            ProfScope pc("clique_count_work", s, 32.0 * E + 8.0 * (double)R.mwords + 4.0 * (double)st[3]);
+            // write pass: a start pair per level-1 entry, info and row of
+            // every entry with children, 6 B per level-2 entry written
+            ProfScope pw("clique_write_work", s, 16.0 * E + (double)st[4] + 6.0 * (double)st[1]);
+            if (k == 4)   // last level: 6 B SoA + 8 B info per entry, 16 B per pair of row words
+                ProfScope pl("clique_last_work", s, 14.0 * (double)st[1] + 16.0 * (double)st[2]);
+        }
     }
     return st[0];
 }

@@ -36,6 +36,18 @@ __device__ __forceinline__ int64_t bcast64(int64_t v, int src) {
     return (int64_t)__shfl((long long)v, src, WAVE);
 }
 
+// Value of v in lane l, for a wave-uniform l (a scalar read of the lane's
+// register, no LDS traffic).
+__device__ __forceinline__ int32_t readlane(int32_t v, int l) {
+    return __builtin_amdgcn_readlane(v, l);
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Inclusive prefix sum across the wave.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 #pragma unroll

@@ -375,7 +375,7 @@ __global__ void k_fsm_l2(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, u
 template <bool BITS>
 __global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, const int32_t* __restrict__ e2s,
                          uint32_t* __restrict__ counts, Bits Bt, unsigned long long* __restrict__ n_emb) {
-    uint64_t local = 0;
+    uint64_t local = 0, scanned = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t e1 = e1s[i], e2 = e2s[i];
         const int32_t a = C.esrc[e1], b = C.edst[e1], c = C.esrc[e2], d = C.edst[e2];
@@ -383,6 +383,7 @@ __global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, c
         const int32_t s = (a == c || a == d) ? a : b;
         const int32_t o = (s == a) ? b : a;
         const int32_t t = (s == c) ? d : c;
+        if (!BITS) scanned += (uint64_t)(C.rp[s + 1] - C.rp[s] + C.rp[o + 1] - C.rp[o] + C.rp[t + 1] - C.rp[t]);
         // edges at s: new leaf w (adjacent to e1 -> e > e2): star
         for (int64_t j = C.rp[s]; j < C.rp[s + 1]; ++j) {
             const int32_t w = C.col[j];
@@ -413,7 +414,9 @@ __global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, c
     }
     if (!BITS) {
         local = wave_sum_u64(local);
-        if (lane() == 0 && local) atomicAdd(n_emb, (unsigned long long)local);
+        scanned = wave_sum_u64(scanned);
+        if (lane() == 0 && local) atomicAdd(&n_emb[0], (unsigned long long)local);
+        if (lane() == 0 && scanned) atomicAdd(&n_emb[1], (unsigned long long)scanned);
     }
 }
 
@@ -561,7 +564,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
     unsigned long long* n_emb = reinterpret_cast<unsigned long long*>(push<uint64_t>(ar, 4));
     fill_u64(reinterpret_cast<uint64_t*>(n_emb), 4, 0, s);
 
-    int64_t n2_total = 0;
+    int64_t n2_total = 0, m2_total = 0, l3_passes = 0;
     // ---------------- level 1: every edge; Reduce; Filter
     int32_t* pid1 = push<int32_t>(ar, std::max<int64_t>(E, 1));
     {
@@ -622,6 +625,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
             PG_HIP(hipGetLastError());
             scan_u32(keep2, n2, kpos2, ar, s);
             const int64_t m2 = (int64_t)read_u64(kpos2 + n2, s);
+            m2_total = m2;
             int32_t* fa = push<int32_t>(ar, std::max<int64_t>(m2, 1));
             int32_t* fb = push<int32_t>(ar, std::max<int64_t>(m2, 1));
             k_compact2<<<grid1(n2), 256, 0, s>>>(n2, keep2, kpos2, a2, b2, fa, fb);
@@ -637,19 +641,29 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
                     ProfScope ps("fsm_l3_bits", s, (double)m2);
                     k_fsm_l3<true><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bt, nullptr);
                     PG_HIP(hipGetLastError());
+                    ++l3_passes;   // one per group of candidate patterns
                 }
             });
         }
     }
     std::vector<uint64_t> h((size_t)np);
-    uint64_t n3 = 0;
+    uint64_t n3s[2] = {0, 0};
     PG_HIP(hipMemcpyAsync(h.data(), sup_pat, sizeof(uint64_t) * np, hipMemcpyDeviceToHost, s));
-    PG_HIP(hipMemcpyAsync(&n3, n_emb, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(n3s, n_emb, sizeof(n3s), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
+    const uint64_t n3 = n3s[0];
     if (prof_on()) {
         // embeddings generated at every level (levels 2 and 3 from the
         // filtered parents)
         ProfScope ps("fsm_embeddings", s, (double)E + (double)n2_total + (double)n3);
+        // algorithmic bytes of one domain-bit pass over level 3: per
+        // parent its two edge ids, their four endpoints and three
+        // row-pointer pairs (72 B); per scanned list element its vertex and
+        // edge id (8 B); per embedding the new vertex's label (4 B) and a
+        // read-modify-write of one domain word per vertex (4 x 8 B)
+        if (l3_passes > 0)
+            ProfScope pw("fsm_l3_bits_work", s,
+                         (double)l3_passes * (72.0 * (double)m2_total + 8.0 * (double)n3s[1] + 36.0 * (double)n3));
     }
     size_t nf = 0;
     for (int64_t p = 0; p < np; ++p) {

@@ -143,25 +143,25 @@ def test_clique_rmat_config_k4(torch):
 
 @pytest.mark.slow
 def test_clique_rmat_config_edge_blocking(torch):
-    """The scale-21 4-clique count with the level memory bounded to 1 GiB
-    (several level-2 chunks)."""
+    """The scale-21 4-clique count with the level memory bounded to 1.5 GiB
+    (the 3.6 GB triangle level goes in about a dozen chunks)."""
     g = synth.clique_rmat()
     want = golden("full_configs.json")["clique_rmat_s21"]
     with binding.Graph.from_csr(g) as G:
-        G.set_memory_budget(1 << 30)
+        G.set_memory_budget(3 << 29)
         assert G.cliques(4) == want["k4"]
 
 
 @pytest.mark.slow
 def test_clique_rmat_config_k5(torch):
-    """R-MAT scale 21: the 5-clique count at full size, on the mask levels
-    and with the general kernels under a 4 GiB level budget (chunked)."""
+    """R-MAT scale 21: the 5-clique count at full size on the mask levels,
+    with the default level budget and with 8 GiB (the 4-clique level, 143 GB,
+    then goes in about twenty chunks)."""
     g = synth.clique_rmat()
     want = golden("full_configs.json")["clique_rmat_s21_k5"]
     with binding.Graph.from_csr(g) as G:
         say("scale-21 k=5, sibling masks")
         assert G.cliques(5) == want["k5"]
-        G.set_option(binding.PG_OPT_CLIQUE_MASKS, 0)
-        G.set_memory_budget(4 << 30)
-        say("scale-21 k=5, general kernels, 4 GiB")
+        G.set_memory_budget(8 << 30)
+        say("scale-21 k=5, sibling masks, 8 GiB")
         assert G.cliques(5) == want["k5"]
