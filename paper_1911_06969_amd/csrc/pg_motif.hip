@@ -342,20 +342,33 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_l1(MotifArgs A) {
 struct L4Lds {
     int32_t A0[MO_WAVES][MO_STAGE];
     int32_t A1[MO_WAVES][MO_STAGE];
+    int32_t A2[MO_WAVES][MO_STAGE];  // the current child's list, when staged
     int32_t C[MO_WAVES][MO_CMAX];
-    uint32_t pre[MO_WAVES][WAVE];
-    int64_t lo2[MO_WAVES][WAVE];
-    int64_t base2[MO_WAVES][WAVE];   // row start of v2
-    int32_t len2[MO_WAVES][WAVE];    // degree of v2
-    int32_t v2[MO_WAVES][WAVE];
-    int32_t opt[MO_WAVES][WAVE];
-    int32_t hb2[MO_WAVES][WAVE];     // dense row of v2, or -1
-    uint32_t cnt[MO_WAVES][WAVE][6]; // I02 lo/hi, I12 lo/hi, I012 lo/hi
 };
+
+// Adds the hits of one 64-candidate step to the six counters: [0, 1] u ~ v0
+// and v2, [2, 3] u ~ v1 and v2, [4, 5] all three, each split into (v0, v2]
+// and above v2.  Ballots make the counts wave-uniform.
+__device__ __forceinline__ void tally(uint32_t (&c)[6], bool in02, bool in12, bool in012, bool hi) {
+    c[0] += (uint32_t)popc64(ballot(in02 && !hi));
+    c[1] += (uint32_t)popc64(ballot(in02 && hi));
+    c[2] += (uint32_t)popc64(ballot(in12 && !hi));
+    c[3] += (uint32_t)popc64(ballot(in12 && hi));
+    c[4] += (uint32_t)popc64(ballot(in012 && !hi));
+    c[5] += (uint32_t)popc64(ballot(in012 && hi));
+}
 
 // Children of one L1 entry (v0, v1).  A0/A1: the two adjacency lists (LDS or
 // global) with their dense rows h0/h1 when they have one, C: A0 and A1
 // above v0 intersected (sorted, LDS or scratch).
+//
+// The lanes first read 64 children's parameters and pick, per child, the
+// cheaper way to get its counts: stream A2' (v2's list above v0) probing A0
+// and A1, or stream A0' and A1' probing A2 (through v2's dense row, or a
+// copy staged in LDS).  Then the wave takes the children one at a time:
+// every lane probes one candidate of the child's stream, all lanes follow
+// the same strategy, binary searches run the same number of steps in every
+// lane, and the counts are ballot popcounts.
 template <class P0, class P1, class PC>
 __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L, int w, int32_t v0, int32_t v1,
                                                     P0 A0, int32_t d0, P1 A1, int32_t d1, PC C, int32_t nc,
@@ -366,10 +379,10 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
     const int32_t a1lo = (int32_t)upper_bound(A1, 0, d1, v0);
     const int32_t d0p = d0 - a0lo, d1p = d1 - a1lo;
     const int32_t pc0 = probe_cost(cheap0, d0), pc1 = probe_cost(cheap1, d1);
+    int32_t* S2 = &L.A2[w][0];
     for (int32_t xc = 0; xc < s; xc += WAVE) {
         const int32_t x = xc + lane();
-        uint32_t work = 0;
-        int32_t v2 = 0, code = 0;
+        int32_t v2 = 0, code = 0, hb2 = -1, opt = 0;
         int64_t s0 = 0, s1 = 0, lo2 = 0;
         if (x < s) {
             v2 = A.vid2[b + x];
@@ -377,72 +390,65 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
             s0 = A.rp[v2];
             s1 = A.rp[v2 + 1];
             lo2 = upper_bound(A.col, s0, s1, v0);
-            const int32_t d2p = (int32_t)(s1 - lo2);
-            const int32_t hb2 = A.hub_id[v2];
-            const int32_t pc2 = probe_cost(hb2 >= 0, (int32_t)(s1 - s0));
-            // iterate A2' probing A0 and A1, or iterate A0' (probing A2 and A1)
-            // and A1' (probing A2): the cheaper total
+            const int32_t d2 = (int32_t)(s1 - s0), d2p = (int32_t)(s1 - lo2);
+            hb2 = A.hub_id[v2];
+            const bool stage2 = hb2 < 0 && d2 <= MO_STAGE;
+            const int32_t pc2 = probe_cost(hb2 >= 0 || stage2, d2);
             const int64_t cost0 = (int64_t)d2p * (pc0 + pc1);
-            const int64_t cost1 = (int64_t)d0p * (pc2 + pc1) + (int64_t)d1p * pc2;
-            const int opt = (cost0 <= cost1) ? 0 : 1;
-            work = (uint32_t)(opt == 0 ? d2p : d0p + d1p);
-            L.lo2[w][lane()] = lo2;
-            L.base2[w][lane()] = s0;
-            L.len2[w][lane()] = (int32_t)(s1 - s0);
-            L.v2[w][lane()] = v2;
-            L.opt[w][lane()] = opt;
-            L.hb2[w][lane()] = hb2;
+            const int64_t cost1 = (int64_t)d0p * (pc2 + pc1) + (int64_t)d1p * pc2 + (stage2 ? d2 : 0);
+            opt = (cost0 <= cost1) ? 0 : 1;
+            items += (uint64_t)(opt == 0 ? d2p : d0p + d1p);
         }
-#pragma unroll
-        for (int c = 0; c < 6; ++c) L.cnt[w][lane()][c] = 0;
-        const uint32_t inc = wave_incl_scan(work);
-        const uint32_t W = bcast(inc, WAVE - 1);
-        L.pre[w][lane()] = inc - work;
-        items += work;
-        wave_sync();
+        uint32_t cnt[6] = {0, 0, 0, 0, 0, 0};   // lane x: its child's counters
         const int nx = min(WAVE, s - xc);
-        for (uint32_t t0 = 0; t0 < W; t0 += WAVE) {
-            const uint32_t t = t0 + lane();
-            if (t < W) {
-                int xi = 0;
-                {
-                    int n_i = nx;
-                    while (n_i > 1) {
-                        const int half = n_i >> 1;
-                        if (L.pre[w][xi + half] <= t) xi += half;
-                        n_i -= half;
-                    }
+        for (int xi = 0; xi < nx; ++xi) {
+            const int32_t cv2 = readlane(v2, xi);
+            uint32_t c6[6] = {0, 0, 0, 0, 0, 0};
+            if (readlane(opt, xi) == 0) {
+                const int64_t l = (int64_t)readlane64((uint64_t)lo2, xi);
+                const int64_t h = (int64_t)readlane64((uint64_t)s1, xi);
+                for (int64_t t0 = l; t0 < h; t0 += 2 * WAVE) {
+                    const int64_t ta = t0 + lane(), tb = ta + WAVE;
+                    const bool va = ta < h, vb = tb < h;
+                    const int32_t ua = va ? A.col[ta] : 0;
+                    const int32_t ub = vb ? A.col[tb] : 0;
+                    const bool a0 = va && adj_has(h0, A0, d0, ua);
+                    const bool b0 = vb && adj_has(h0, A0, d0, ub);
+                    const bool a1 = va && adj_has(h1, A1, d1, ua);
+                    const bool b1 = vb && adj_has(h1, A1, d1, ub);
+                    tally(c6, a0, a1, a0 && a1, ua > cv2);
+                    tally(c6, b0, b1, b0 && b1, ub > cv2);
                 }
-                const uint32_t j = t - L.pre[w][xi];
-                const int32_t cv2 = L.v2[w][xi];
-                if (L.opt[w][xi] == 0) {
-                    const int32_t u = A.col[L.lo2[w][xi] + j];
-                    const bool b0 = adj_has(h0, A0, d0, u);
-                    const bool b1 = adj_has(h1, A1, d1, u);
-                    const int r = u > cv2;
-                    if (b0) atomicAdd(&L.cnt[w][xi][0 + r], 1u);
-                    if (b1) atomicAdd(&L.cnt[w][xi][2 + r], 1u);
-                    if (b0 && b1) atomicAdd(&L.cnt[w][xi][4 + r], 1u);
-                } else {
-                    const int32_t hb2 = L.hb2[w][xi];
-                    const uint32_t* h2 = hb2 >= 0 ? A.hub_bits + (int64_t)hb2 * A.hub_words : nullptr;
-                    const int32_t* g2 = A.col + L.base2[w][xi];
-                    const int32_t len2 = L.len2[w][xi];
-                    if ((int32_t)j < d0p) {
-                        const int32_t u = A0[a0lo + (int32_t)j];
-                        if (adj_has(h2, g2, len2, u)) {
-                            const int r = u > cv2;
-                            atomicAdd(&L.cnt[w][xi][0 + r], 1u);
-                            if (adj_has(h1, A1, d1, u)) atomicAdd(&L.cnt[w][xi][4 + r], 1u);
-                        }
-                    } else {
-                        const int32_t u = A1[a1lo + (int32_t)j - d0p];
-                        if (adj_has(h2, g2, len2, u)) atomicAdd(&L.cnt[w][xi][2 + (u > cv2)], 1u);
+            } else {
+                const int32_t hb = readlane(hb2, xi);
+                const int64_t base = (int64_t)readlane64((uint64_t)s0, xi);
+                const int32_t len2 = (int32_t)((int64_t)readlane64((uint64_t)s1, xi) - base);
+                const uint32_t* h2 = hb >= 0 ? A.hub_bits + (int64_t)hb * A.hub_words : nullptr;
+                const bool staged = h2 == nullptr && len2 <= MO_STAGE;
+                if (staged) {
+                    wave_sync();   // the previous child's probes are done
+                    for (int k = lane(); k < len2; k += WAVE) S2[k] = A.col[base + k];
+                    wave_sync();
+                }
+                const int32_t tot = d0p + d1p;
+                for (int32_t t0 = 0; t0 < tot; t0 += WAVE) {
+                    const int32_t t = t0 + lane();
+                    const bool from0 = t < d0p;
+                    bool in2 = false, in1 = false;
+                    int32_t u = 0;
+                    if (t < tot) {
+                        u = from0 ? A0[a0lo + t] : A1[a1lo + (t - d0p)];
+                        in2 = staged ? member(S2, len2, u) : adj_has(h2, A.col + base, len2, u);
+                        in1 = from0 && in2 && adj_has(h1, A1, d1, u);
                     }
+                    tally(c6, from0 && in2, !from0 && in2, in1, u > cv2);
                 }
             }
+            if (lane() == xi) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) cnt[c] = c6[c];
+            }
         }
-        wave_sync();
         if (x < s) {
             const int a02 = code & 1, a12 = (code >> 1) & 1;
             const int p = a02 ? 0 : 1;
@@ -458,8 +464,8 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
             int64_t N[2][8];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int64_t i02 = L.cnt[w][lane()][0 + r], i12 = L.cnt[w][lane()][2 + r];
-                const int64_t i012 = L.cnt[w][lane()][4 + r];
+                const int64_t i02 = cnt[0 + r], i12 = cnt[2 + r];
+                const int64_t i012 = cnt[4 + r];
                 N[r][0] = 0;
                 N[r][7] = i012;
                 N[r][3] = I01[r] - i012;
@@ -469,9 +475,14 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
                 N[r][2] = I1[r] - I01[r] - i12 + i012;
                 N[r][4] = I2[r] - i02 - i12 + i012;
             }
-            // the embedding's own vertices are not candidates
-            N[v1 > v2 ? 1 : 0][1 | (a12 ? 4 : 0)] -= 1;   // v1: adjacent to v0, to v2 iff a12
-            N[0][a02 | (a12 << 1)] -= 1;                   // v2: adjacent to v0 iff a02, to v1 iff a12
+            // the embedding's own vertices are not candidates: v1 (adjacent
+            // to v0, to v2 iff a12) and v2 (adjacent to v0 iff a02, to v1 iff
+            // a12); constant indices keep N and acc in registers
+            const int r1 = v1 > v2 ? 1 : 0, m1 = 1 | (a12 ? 4 : 0), m2 = a02 | (a12 << 1);
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int m = 0; m < 8; ++m) N[r][m] -= (int64_t)((r == r1 && m == m1) + (r == 0 && m == m2));
             const int ebits = 1 | (a02 << 1) | (a12 << 2);
 #pragma unroll
             for (int m = 1; m < 8; ++m) {
@@ -479,7 +490,8 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
                 if (sbit < p) continue;
                 const int64_t c = (sbit == p) ? N[1][m] : N[0][m] + N[1][m];
                 const int pid = c_lut4.v[ebits | (m << 3)];
-                if (pid >= 0) acc[pid] += (uint64_t)c;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) acc[q] += (pid == q) ? (uint64_t)c : 0ull;
             }
         }
         wave_sync();
