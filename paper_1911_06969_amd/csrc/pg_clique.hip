@@ -352,7 +352,7 @@ static void extend_level(CliqueRun& R, int lev, const int64_t* seg, int64_t seg_
 
 constexpr int BM_MAXD = 768;             // roots with out-degree up to this use masks
 constexpr int BM_W = BM_MAXD / 64;       // 64-bit words per mask row
-constexpr int BM_UNROLL = 4;             // out-list elements per lane in flight
+constexpr int BM_UNROLL = 3;             // out-list elements per lane per step (double-buffered)
 
 // Level-1 entry e = (r, S[i]) is described by one word: the first mask word
 // of r's block, i, and the row width W (words):  base << 14 | i << 4 | W.
@@ -369,7 +369,8 @@ struct BmLds {
 };
 
 struct BmArgs {
-    XcdQueue Q;                 // items: roots, heaviest (highest rank) first
+    XcdQueue Q;                 // over items[]: (root, round of 64 level-1 entries), highest ranks first
+    const uint64_t* items;
     const int64_t* rp;          // DAG
     const int32_t* col;
     const uint64_t* moff;       // first mask word of each root
@@ -379,8 +380,9 @@ struct BmArgs {
     unsigned long long* stats;  // [3] += out-list entries streamed
 };
 
-// count pass: one wave per root r, out(r) staged in LDS.  The wave walks
-// r's level-1 entries in order; for entry i (vertex v = S[i]) all 64 lanes
+// count pass: a work item is one round of 64 level-1 entries of a root r
+// (so no wave holds a heavy root for long), with out(r) staged in LDS.  The
+// wave walks the round's entries in order; for entry i (vertex v = S[i]) all 64 lanes
 // stream out(v) together, BM_UNROLL coalesced loads per lane in flight,
 // and look each candidate up in S[i+1, d) with a branch-free binary search
 // whose trip count is the same for every lane.  Hits set bits of row i in
@@ -395,18 +397,21 @@ __global__ __launch_bounds__(CQ_THREADS, 8) void k_clique_count_masks(BmArgs A) 
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
-        for (int64_t item = it; item < it_end; ++item) {
-            const int64_t r = A.Q.n_items - 1 - item;
+        for (int64_t j = it; j < it_end; ++j) {
+            const uint64_t item = A.items[A.Q.n_items - 1 - j];
+            const int64_t r = item_seg(item);
             const int64_t b = A.rp[r];
             const int32_t d = (int32_t)(A.rp[r + 1] - b);
             if (d < 2) continue;   // counts are pre-zeroed; rows and infos are never read
             const int W = (d + 63) >> 6;
+            wave_sync();           // the previous item's reads of S are done
             for (int k = lane(); k < d; k += WAVE) S[k] = A.col[b + k];
             wave_sync();
             const int32_t s_last = S[d - 1];
             const uint64_t base = A.moff[r];
             uint64_t* Mr = A.M + base;
-            for (int32_t xc = 0; xc < d; xc += WAVE) {
+            {
+                const int32_t xc = (int32_t)item_round(item) * WAVE;
                 // out-list bounds of the round's entries, one per lane
                 const int32_t xl = xc + lane();
                 int64_t lo = 0, hi = 0;
@@ -424,31 +429,51 @@ __global__ __launch_bounds__(CQ_THREADS, 8) void k_clique_count_masks(BmArgs A) 
                     if (lane() < W) row[lane()] = 0ull;
                     wave_sync();
                     const int32_t len = d - x - 1;   // >= 1 whenever l < h
-                    for (int64_t t0 = l; t0 < h; t0 += WAVE * BM_UNROLL) {
-                        int32_t u[BM_UNROLL], p[BM_UNROLL];
+                    uint32_t c = 0;                  // hits = children of x (wave-uniform)
+                    if (l < h) {
+                        // double-buffered: the next chunk is loaded while this one is searched
+                        int32_t u[BM_UNROLL];
 #pragma unroll
                         for (int q = 0; q < BM_UNROLL; ++q) {
-                            const int64_t t = t0 + q * WAVE + lane();
+                            const int64_t t = l + q * WAVE + lane();
                             u[q] = t < h ? A.col[t] : 0x7fffffff;
-                            p[q] = x + 1;
                         }
-                        // invariant: the answer lies in [p, p + n) within [x + 1, d)
-                        for (int32_t n = len; n > 1;) {
-                            const int32_t half = n >> 1;
+                        for (int64_t t0 = l;;) {
+                            const int64_t tn = t0 + WAVE * BM_UNROLL;
+                            // stop once the list passes the root's last out-neighbour
+                            const bool more = tn < h && readlane(u[BM_UNROLL - 1], WAVE - 1) <= s_last;
+                            int32_t un[BM_UNROLL];
 #pragma unroll
-                            for (int q = 0; q < BM_UNROLL; ++q) p[q] = (S[p[q] + half] <= u[q]) ? p[q] + half : p[q];
-                            n -= half;
+                            for (int q = 0; q < BM_UNROLL; ++q) {
+                                const int64_t t = tn + q * WAVE + lane();
+                                un[q] = (more && t < h) ? A.col[t] : 0x7fffffff;
+                            }
+                            int32_t p[BM_UNROLL];
+#pragma unroll
+                            for (int q = 0; q < BM_UNROLL; ++q) p[q] = x + 1;
+                            // invariant: the answer lies in [p, p + n) within [x + 1, d)
+                            for (int32_t n = len; n > 1;) {
+                                const int32_t half = n >> 1;
+#pragma unroll
+                                for (int q = 0; q < BM_UNROLL; ++q) p[q] = (S[p[q] + half] <= u[q]) ? p[q] + half : p[q];
+                                n -= half;
+                            }
+#pragma unroll
+                            for (int q = 0; q < BM_UNROLL; ++q) {
+                                const bool f = S[p[q]] == u[q];
+                                if (f) atomicOr(&row[p[q] >> 6], 1ull << (p[q] & 63));
+                                c += (uint32_t)popc64(ballot(f));
+                            }
+                            streamed += (uint64_t)min<int64_t>(h - t0, WAVE * BM_UNROLL);
+                            if (!more) break;
+#pragma unroll
+                            for (int q = 0; q < BM_UNROLL; ++q) u[q] = un[q];
+                            t0 = tn;
                         }
-#pragma unroll
-                        for (int q = 0; q < BM_UNROLL; ++q)
-                            if (S[p[q]] == u[q]) atomicOr(&row[p[q] >> 6], 1ull << (p[q] & 63));
-                        streamed += (uint64_t)min<int64_t>(h - t0, WAVE * BM_UNROLL);
-                        if (readlane(u[BM_UNROLL - 1], WAVE - 1) > s_last) break;
                     }
                     wave_sync();
                     const unsigned long long word = lane() < W ? row[lane()] : 0ull;
                     if (lane() < W) Mr[(uint64_t)x * W + lane()] = word;
-                    const uint32_t c = wave_sum_u32((uint32_t)__popcll(word));
                     if (lane() == xi) mine = c;
                     wave_sync();
                 }
@@ -557,7 +582,7 @@ struct MaskChain {
 };
 
 struct MaskArgs {
-    XcdQueue Q;
+    XcdQueue Q;                  // over parents: a parent has at most BM_MAXD children
     int64_t p_lo;                // parents (level lev-1 entries)
     const uint64_t* seg;         // children of parent p: seg[p] - seg_base .. seg[p+1] - seg_base
     uint64_t seg_base;
@@ -583,7 +608,9 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
         for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
             const int64_t b = (int64_t)(A.seg[p] - A.seg_base);
             const int64_t e2 = (int64_t)(A.seg[p + 1] - A.seg_base);
-            if (e2 <= b || e2 <= A.x_lo || b >= A.x_hi) continue;
+            // the parent's children within the launch's window [x_lo, x_hi)
+            const int64_t x0 = max<int64_t>(b, A.x_lo), x1 = min<int64_t>(e2, A.x_hi);
+            if (x0 >= x1) continue;
             // the parent's ancestry: positions of its vertices after the root
             int32_t apos[PG_KMAX];
             int na = 0;
@@ -604,7 +631,6 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
             uint64_t s[BM_W];
 #pragma unroll
             for (int q = 0; q < BM_W; ++q) s[q] = q < W ? readlane64(sp, q) : 0ull;
-            const int64_t x0 = max<int64_t>(b, A.x_lo), x1 = min<int64_t>(e2, A.x_hi);
             for (int64_t xb = x0; xb < x1; xb += WAVE) {
                 const int64_t x = xb + lane();
                 const bool valid = x < x1;
@@ -793,10 +819,14 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     R.mwords = mwords;
     {
         BmArgs A;
+        const size_t mk = ar.mark();
+        uint64_t* items = nullptr;
+        const int64_t n_items = round_items(rp, 0, n, WAVE, ar, s, &items);
         fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, s);
         A.Q.next = R.qctr;
-        A.Q.n_items = n;
-        A.Q.chunk = n >= R.waves * 64 ? 16 : 1;
+        A.Q.n_items = n_items;
+        A.Q.chunk = n_items >= R.waves * 64 ? 4 : 1;
+        A.items = items;
         A.rp = rp;
         A.col = col;
         A.moff = moff;
@@ -804,9 +834,12 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
         A.count = cnt;
         A.info = info;
         A.stats = R.stats;
-        ProfScope ps("clique_count", s, (double)E);
-        k_clique_count_masks<<<R.blocks, CQ_THREADS, 0, s>>>(A);
-        PG_HIP(hipGetLastError());
+        if (n_items > 0) {
+            ProfScope ps("clique_count", s, (double)E);
+            k_clique_count_masks<<<R.blocks, CQ_THREADS, 0, s>>>(A);
+            PG_HIP(hipGetLastError());
+        }
+        ar.reset(mk);
     }
     scan_u32(cnt, E, start, ar, s);
     const uint64_t total = read_u64(start + E, s);

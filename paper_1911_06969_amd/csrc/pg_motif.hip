@@ -86,8 +86,8 @@ __host__ __device__ constexpr Lut4 make_lut4() {
 __constant__ Lut4 c_lut4 = make_lut4();
 
 struct MotifArgs {
-    XcdQueue Q;
-    int64_t p_lo;               // first item (segment) id
+    XcdQueue Q;                 // over items[]: (segment, round of 64 children)
+    const uint64_t* items;
     const int64_t* rp;          // undirected CSR
     const int32_t* col;
     // level-1 segments: vertex v0 owns L1 entries l1_seg[v0] .. l1_seg[v0+1]-1
@@ -159,15 +159,14 @@ struct L1Lds {
     uint32_t c_hi[MO_WAVES][WAVE];
 };
 
+// L1 entries [xc, x1) of vertex v0 (at most 64: one work item)
 template <int MODE, class P0>
 __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, int w, int32_t v0, P0 A0,
-                                                 int32_t d0, int64_t r0, int64_t b, int32_t s,
+                                                 int32_t d0, int64_t r0, int64_t b, int32_t xc, int32_t x1,
                                                  uint64_t (&acc)[6], const uint32_t* h0, bool a0_cheap) {
     // A0' = A0 above v0, at positions [a0lo, d0)
     const int32_t a0lo = (int32_t)upper_bound(A0, 0, d0, v0);
-    const int32_t x0 = (int32_t)max<int64_t>(0, A.x_lo - b);
-    const int32_t x1 = (int32_t)min<int64_t>(s, A.x_hi - b);
-    for (int32_t xc = x0; xc < x1; xc += WAVE) {
+    {
         const int32_t x = xc + lane();
         uint32_t work = 0;
         if (x < x1) {
@@ -310,20 +309,25 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_l1(MotifArgs A) {
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
-        for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
+        for (int64_t j = it; j < it_end; ++j) {
+            const uint64_t item = A.items[j];
+            const int64_t p = item_seg(item);
             const int32_t v0 = (int32_t)p;
             const int64_t b = A.l1_seg[p], e = A.l1_seg[p + 1];
             const int32_t s = (int32_t)(e - b);
-            if (s <= 0 || e <= A.x_lo || b >= A.x_hi) continue;
+            // this item's entries, within the launch's window [x_lo, x_hi)
+            const int32_t xa = (int32_t)max<int64_t>(item_round(item) * WAVE, A.x_lo - b);
+            const int32_t xb = (int32_t)min<int64_t>(min<int64_t>(item_round(item) * WAVE + WAVE, s), A.x_hi - b);
+            if (xa >= xb) continue;
             const int64_t r0 = A.rp[v0], r1 = A.rp[v0 + 1];
             const int32_t d0 = (int32_t)(r1 - r0);
             if (d0 <= MO_STAGE) {
                 for (int i = lane(); i < d0; i += WAVE) L.A0[w][i] = A.col[r0 + i];
                 wave_sync();
-                motif_l1_segment<MODE>(A, L, w, v0, &L.A0[w][0], d0, r0, b, s, acc, nullptr, true);
+                motif_l1_segment<MODE>(A, L, w, v0, &L.A0[w][0], d0, r0, b, xa, xb, acc, nullptr, true);
             } else {
                 const uint32_t* h0 = hub_row(A, v0);
-                motif_l1_segment<MODE>(A, L, w, v0, A.col + r0, d0, r0, b, s, acc, h0, h0 != nullptr);
+                motif_l1_segment<MODE>(A, L, w, v0, A.col + r0, d0, r0, b, xa, xb, acc, h0, h0 != nullptr);
             }
             wave_sync();
         }
@@ -358,7 +362,7 @@ __device__ __forceinline__ void tally(uint32_t (&c)[6], bool in02, bool in12, bo
     c[5] += (uint32_t)popc64(ballot(in012 && hi));
 }
 
-// Children of one L1 entry (v0, v1).  A0/A1: the two adjacency lists (LDS or
+// Children [xc, xc + 64) of one L1 entry (v0, v1).  A0/A1: the two adjacency lists (LDS or
 // global) with their dense rows h0/h1 when they have one, C: A0 and A1
 // above v0 intersected (sorted, LDS or scratch).
 //
@@ -372,7 +376,7 @@ __device__ __forceinline__ void tally(uint32_t (&c)[6], bool in02, bool in12, bo
 template <class P0, class P1, class PC>
 __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L, int w, int32_t v0, int32_t v1,
                                                     P0 A0, int32_t d0, P1 A1, int32_t d1, PC C, int32_t nc,
-                                                    int64_t b, int32_t s, uint64_t (&acc)[6],
+                                                    int64_t b, int32_t xc, int32_t s, uint64_t (&acc)[6],
                                                     uint64_t& items, const uint32_t* h0, const uint32_t* h1,
                                                     bool cheap0, bool cheap1) {
     const int32_t a0lo = (int32_t)upper_bound(A0, 0, d0, v0);
@@ -380,7 +384,7 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
     const int32_t d0p = d0 - a0lo, d1p = d1 - a1lo;
     const int32_t pc0 = probe_cost(cheap0, d0), pc1 = probe_cost(cheap1, d1);
     int32_t* S2 = &L.A2[w][0];
-    for (int32_t xc = 0; xc < s; xc += WAVE) {
+    {   // children [xc, min(xc + 64, s)): one work item
         const int32_t x = xc + lane();
         int32_t v2 = 0, code = 0, hb2 = -1, opt = 0;
         int64_t s0 = 0, s1 = 0, lo2 = 0;
@@ -508,15 +512,19 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
-        for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
+        for (int64_t j = it; j < it_end; ++j) {
+            const uint64_t item = A.items[j];
+            const int64_t p = item_seg(item);
+            const int32_t xc = (int32_t)item_round(item) * WAVE;
             const int64_t b = (int64_t)(A.seg2[p] - A.seg2_base);
             const int32_t s = (int32_t)(A.seg2[p + 1] - A.seg2[p]);
-            if (s <= 0) continue;
+            if (xc >= s) continue;
             const int32_t v0 = A.l1_src[p], v1 = A.l1_dst[p];
             const int64_t r0 = A.rp[v0], q0 = A.rp[v1];
             const int32_t d0 = (int32_t)(A.rp[v0 + 1] - r0), d1 = (int32_t)(A.rp[v1 + 1] - q0);
-            n_in += (lane() == 0) ? (uint64_t)s : 0;
-            deg_sum += (lane() == 0) ? (uint64_t)s * (uint64_t)(d0 + d1) : 0;
+            const uint64_t n_here = (uint64_t)(min(xc + WAVE, s) - xc);
+            n_in += (lane() == 0) ? n_here : 0;
+            deg_sum += (lane() == 0) ? n_here * (uint64_t)(d0 + d1) : 0;
             const bool st0 = d0 <= MO_STAGE, st1 = d1 <= MO_STAGE;
             if (st0) for (int i = lane(); i < d0; i += WAVE) L.A0[w][i] = A.col[r0 + i];
             if (st1) for (int i = lane(); i < d1; i += WAVE) L.A1[w][i] = A.col[q0 + i];
@@ -558,17 +566,17 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
             const bool ch0 = st0 || h0 != nullptr, ch1 = st1 || h1 != nullptr;
             const int32_t* sc = scratch;
             if (st0 && st1) {
-                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, s, acc, items, h0, h1, ch0, ch1);
-                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, sc, nc, b, s, acc, items, h0, h1, ch0, ch1);
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, xc, s, acc, items, h0, h1, ch0, ch1);
+                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, &L.A1[w][0], d1, sc, nc, b, xc, s, acc, items, h0, h1, ch0, ch1);
             } else if (st0) {
-                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, &L.C[w][0], nc, b, s, acc, items, h0, h1, ch0, ch1);
-                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, sc, nc, b, s, acc, items, h0, h1, ch0, ch1);
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, &L.C[w][0], nc, b, xc, s, acc, items, h0, h1, ch0, ch1);
+                else motif_last4_segment(A, L, w, v0, v1, &L.A0[w][0], d0, gA1, d1, sc, nc, b, xc, s, acc, items, h0, h1, ch0, ch1);
             } else if (st1) {
-                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, s, acc, items, h0, h1, ch0, ch1);
-                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, sc, nc, b, s, acc, items, h0, h1, ch0, ch1);
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, &L.C[w][0], nc, b, xc, s, acc, items, h0, h1, ch0, ch1);
+                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, &L.A1[w][0], d1, sc, nc, b, xc, s, acc, items, h0, h1, ch0, ch1);
             } else {
-                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, &L.C[w][0], nc, b, s, acc, items, h0, h1, ch0, ch1);
-                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, sc, nc, b, s, acc, items, h0, h1, ch0, ch1);
+                if (c_in_lds) motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, &L.C[w][0], nc, b, xc, s, acc, items, h0, h1, ch0, ch1);
+                else motif_last4_segment(A, L, w, v0, v1, gA0, d0, gA1, d1, sc, nc, b, xc, s, acc, items, h0, h1, ch0, ch1);
             }
             wave_sync();
         }
@@ -668,22 +676,30 @@ static void build_hubs(pg_graph* g) {
     L.hubs_built = true;
 }
 
-static void set_queue(MotifRun& R, MotifArgs& A, int64_t p_lo, int64_t n_items) {
+static void set_queue(MotifRun& R, MotifArgs& A, const uint64_t* items, int64_t n_items) {
     fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, R.s);
     A.Q.next = R.qctr;
     A.Q.n_items = n_items;
-    A.Q.chunk = n_items >= R.waves * 64 ? 16 : (n_items >= R.waves * 8 ? 4 : 1);
-    A.p_lo = p_lo;
+    A.Q.chunk = n_items >= R.waves * 64 ? 4 : 1;
+    A.items = items;
     A.out = R.out;
 }
 
+// a level-1 pass over the vertices [v_lo, v_hi), in items of 64 L1 entries
 template <int MODE>
 static void launch_l1(MotifRun& R, MotifArgs A, int64_t v_lo, int64_t v_hi, const char* name, double units) {
     if (v_hi <= v_lo) return;
-    set_queue(R, A, v_lo, v_hi - v_lo);
-    ProfScope ps(name, R.s, units);
-    k_motif_l1<MODE><<<R.blocks, MO_THREADS, 0, R.s>>>(A);
-    PG_HIP(hipGetLastError());
+    Arena& ar = R.g->arena;
+    const size_t mk = ar.mark();
+    uint64_t* items = nullptr;
+    const int64_t m = round_items(A.l1_seg, v_lo, v_hi - v_lo, WAVE, ar, R.s, &items);
+    if (m > 0) {
+        set_queue(R, A, items, m);
+        ProfScope ps(name, R.s, units);
+        k_motif_l1<MODE><<<R.blocks, MO_THREADS, 0, R.s>>>(A);
+        PG_HIP(hipGetLastError());
+    }
+    ar.reset(mk);
 }
 
 // first vertex whose L1 segment holds entry x: largest v with l1_seg[v] <= x
@@ -798,10 +814,16 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
             L.code2 = code2;
             L.scratch = scratch;
             L.scratch_per_wave = scratch_per_wave;
-            set_queue(R, L, c0, c1 - c0);
-            ProfScope ps("motif_last", s, 0.0);
-            k_motif_last4<<<R.blocks, MO_THREADS, 0, s>>>(L);
-            PG_HIP(hipGetLastError());
+            const size_t mk = ar.mark();
+            uint64_t* items = nullptr;
+            const int64_t m = round_items(start, c0, c1 - c0, WAVE, ar, s, &items);
+            if (m > 0) {
+                set_queue(R, L, items, m);
+                ProfScope ps("motif_last", s, 0.0);
+                k_motif_last4<<<R.blocks, MO_THREADS, 0, s>>>(L);
+                PG_HIP(hipGetLastError());
+            }
+            ar.reset(mk);
         }
     }
     uint64_t h[16];

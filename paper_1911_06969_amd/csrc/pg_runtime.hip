@@ -229,6 +229,68 @@ void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
     PG_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------------------ round items
+
+template <class T>
+__global__ void k_round_counts(const T* __restrict__ seg, int64_t p_lo, int64_t n_seg, int per,
+                               uint32_t* __restrict__ rounds) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_seg;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = (int64_t)(seg[p_lo + i + 1] - seg[p_lo + i]);
+        rounds[i] = (uint32_t)((c + per - 1) / per);
+    }
+}
+
+__global__ void k_round_emit(int64_t p_lo, int64_t n_seg, const uint64_t* __restrict__ pos,
+                             uint64_t* __restrict__ items) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_seg;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = pos[i], e = pos[i + 1];
+        const uint64_t p = (uint64_t)(p_lo + i) << ROUND_BITS;
+        for (uint64_t k = b; k < e; ++k) items[k] = p | (k - b);
+    }
+}
+
+template <class T>
+static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
+                                uint64_t** items) {
+    *items = nullptr;
+    if (n_seg <= 0) return 0;
+    PG_REQUIRE((uint64_t)(p_lo + n_seg) < (1ull << (64 - ROUND_BITS)), PG_EOVERFLOW, "too many segments");
+    const size_t mk = a.mark();
+    uint32_t* rounds = push<uint32_t>(a, n_seg);
+    uint64_t* pos = push<uint64_t>(a, n_seg + 1);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n_seg + 255) / 256, 8192);
+    k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds);
+    PG_HIP(hipGetLastError());
+    scan_u32(rounds, n_seg, pos, a, s);
+    const int64_t m = (int64_t)read_u64(pos + n_seg, s);
+    // the items go below the temporaries' mark so that those can be dropped
+    a.reset(mk);
+    uint64_t* out = push<uint64_t>(a, std::max<int64_t>(m, 1));
+    const size_t mk2 = a.mark();
+    uint32_t* rounds2 = push<uint32_t>(a, n_seg);
+    uint64_t* pos2 = push<uint64_t>(a, n_seg + 1);
+    k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds2);
+    PG_HIP(hipGetLastError());
+    scan_u32(rounds2, n_seg, pos2, a, s);
+    k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos2, out);
+    PG_HIP(hipGetLastError());
+    a.reset(mk2);
+    *items = out;
+    return m;
+}
+
+int64_t round_items(const int64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
+                    uint64_t** items) {
+    return round_items_impl(seg, p_lo, n_seg, per, a, s, items);
+}
+
+int64_t round_items(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
+                    uint64_t** items) {
+    return round_items_impl(seg, p_lo, n_seg, per, a, s, items);
+}
+
 uint64_t read_u64(const uint64_t* dev, hipStream_t s) {
     uint64_t h = 0;
     PG_HIP(hipMemcpyAsync(&h, dev, sizeof(h), hipMemcpyDeviceToHost, s));
