@@ -368,6 +368,26 @@ struct BmLds {
     unsigned long long row[CQ_WAVES][BM_W];
 };
 
+// Search of BM_UNROLL keys in S[x+1, d), x and d wave-uniform and
+// LG = floor(log2(len)), len = d - x - 1 >= 1: for each key u the last
+// element P of S[x, d) with P = S + x or *P <= u.  With m = 2^LG, one probe
+// at x + m decides whether the answer lies among the first m positions or
+// the last m; strides m/2 .. 1 finish it (Shar's method).  Every probe stays
+// inside S[x+1, d); all strides are immediates (LDS offsets) and the chain
+// is straight-line code, so a step costs one add, compare and select.
+template <int LG>
+__device__ __forceinline__ void bs_find(const int32_t* S, int32_t x, int32_t d, const int32_t* (&P)[BM_UNROLL],
+                                        const int32_t (&u)[BM_UNROLL]) {
+    constexpr int32_t m = 1 << LG;
+    const int32_t pivot = S[x + m];
+#pragma unroll
+    for (int q = 0; q < BM_UNROLL; ++q) P[q] = (pivot <= u[q]) ? S + (d - m) : S + x;
+#pragma unroll
+    for (int st = m / 2; st >= 1; st >>= 1)
+#pragma unroll
+        for (int q = 0; q < BM_UNROLL; ++q) P[q] = (P[q][st] <= u[q]) ? P[q] + st : P[q];
+}
+
 struct BmArgs {
     XcdQueue Q;                 // over items[]: (root, round of 64 level-1 entries), highest ranks first
     const uint64_t* items;
@@ -388,7 +408,62 @@ struct BmArgs {
 // whose trip count is the same for every lane.  Hits set bits of row i in
 // LDS; the finished row goes to HBM and its popcount is i's child count.
 // The stream stops once it passes the root's last out-neighbour.
-__global__ __launch_bounds__(CQ_THREADS, 8) void k_clique_count_masks(BmArgs A) {
+// Streams out(v) of level-1 entry x (n_cand > 0 elements from cp) against
+// S[x+1, d): BM_UNROLL loads per lane per step, double-buffered (the next
+// step's loads fly during this step's search, the two buffers alternate),
+// hits set bits of the LDS row.  Stops once the list passes s_last.
+// Returns the number of hits (wave-uniform).  No element of out(v) equals
+// S[x] = v, so a search ending at S + x is a miss.
+template <int LG>
+__device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left, const int32_t* S, int32_t x,
+                                                 int32_t d, int32_t s_last, unsigned long long* row,
+                                                 uint64_t& streamed) {
+    constexpr int STEP = WAVE * BM_UNROLL;
+    uint32_t c = 0;
+    int32_t ua[BM_UNROLL], ub[BM_UNROLL];
+    auto load = [&](int32_t (&u)[BM_UNROLL], const int32_t* p, int32_t lim) {
+#pragma unroll
+        for (int q = 0; q < BM_UNROLL; ++q) {
+            const int32_t o = q * WAVE + lane();
+            u[q] = o < lim ? p[o] : 0x7fffffff;
+        }
+    };
+    auto search = [&](const int32_t (&u)[BM_UNROLL]) {
+        const int32_t* P[BM_UNROLL];
+        bs_find<LG>(S, x, d, P, u);
+#pragma unroll
+        for (int q = 0; q < BM_UNROLL; ++q) {
+            const bool f = *P[q] == u[q];
+            if (f) {
+                const int32_t pos = (int32_t)(P[q] - S);
+                atomicOr(&row[pos >> 6], 1ull << (pos & 63));
+            }
+            c += (uint32_t)popc64(ballot(f));
+        }
+    };
+    load(ua, cp, (int32_t)min<int64_t>(left, STEP));
+    while (true) {
+        // ua holds the current step; ub gets the next one
+        bool more = left > STEP && readlane(ua[BM_UNROLL - 1], WAVE - 1) <= s_last;
+        if (more) load(ub, cp + STEP, (int32_t)min<int64_t>(left - STEP, STEP));
+        search(ua);
+        streamed += (uint64_t)min<int64_t>(left, STEP);
+        if (!more) break;
+        cp += STEP;
+        left -= STEP;
+        // ub holds the current step; ua gets the next one
+        more = left > STEP && readlane(ub[BM_UNROLL - 1], WAVE - 1) <= s_last;
+        if (more) load(ua, cp + STEP, (int32_t)min<int64_t>(left - STEP, STEP));
+        search(ub);
+        streamed += (uint64_t)min<int64_t>(left, STEP);
+        if (!more) break;
+        cp += STEP;
+        left -= STEP;
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(CQ_THREADS, 7) void k_clique_count_masks(BmArgs A) {
     __shared__ BmLds L;
     const int w = threadIdx.x / WAVE;
     int32_t* S = L.S[w];
@@ -398,89 +473,63 @@ __global__ __launch_bounds__(CQ_THREADS, 8) void k_clique_count_masks(BmArgs A) 
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
         for (int64_t j = it; j < it_end; ++j) {
-            const uint64_t item = A.items[A.Q.n_items - 1 - j];
+            // everything per item and per entry is wave-uniform: keep it scalar
+            const uint64_t item = (uint64_t)uniform64((int64_t)A.items[A.Q.n_items - 1 - j]);
             const int64_t r = item_seg(item);
-            const int64_t b = A.rp[r];
-            const int32_t d = (int32_t)(A.rp[r + 1] - b);
+            const int64_t b = uniform64(A.rp[r]);
+            const int32_t d = uniform((int32_t)(A.rp[r + 1] - b));
             if (d < 2) continue;   // counts are pre-zeroed; rows and infos are never read
             const int W = (d + 63) >> 6;
             wave_sync();           // the previous item's reads of S are done
             for (int k = lane(); k < d; k += WAVE) S[k] = A.col[b + k];
             wave_sync();
-            const int32_t s_last = S[d - 1];
-            const uint64_t base = A.moff[r];
+            const int32_t s_last = uniform(S[d - 1]);
+            const uint64_t base = (uint64_t)uniform64((int64_t)A.moff[r]);
             uint64_t* Mr = A.M + base;
-            {
-                const int32_t xc = (int32_t)item_round(item) * WAVE;
-                // out-list bounds of the round's entries, one per lane
-                const int32_t xl = xc + lane();
-                int64_t lo = 0, hi = 0;
-                if (xl < d - 1) {
-                    const int32_t v = S[xl];
-                    lo = A.rp[v];
-                    hi = A.rp[v + 1];
-                }
-                uint32_t mine = 0;
-                const int nx = min(WAVE, d - xc);
-                for (int xi = 0; xi < nx; ++xi) {
-                    const int32_t x = xc + xi;
-                    const int64_t l = (int64_t)readlane64((uint64_t)lo, xi);
-                    const int64_t h = (int64_t)readlane64((uint64_t)hi, xi);
-                    if (lane() < W) row[lane()] = 0ull;
-                    wave_sync();
-                    const int32_t len = d - x - 1;   // >= 1 whenever l < h
-                    uint32_t c = 0;                  // hits = children of x (wave-uniform)
-                    if (l < h) {
-                        // double-buffered: the next chunk is loaded while this one is searched
-                        int32_t u[BM_UNROLL];
-#pragma unroll
-                        for (int q = 0; q < BM_UNROLL; ++q) {
-                            const int64_t t = l + q * WAVE + lane();
-                            u[q] = t < h ? A.col[t] : 0x7fffffff;
-                        }
-                        for (int64_t t0 = l;;) {
-                            const int64_t tn = t0 + WAVE * BM_UNROLL;
-                            // stop once the list passes the root's last out-neighbour
-                            const bool more = tn < h && readlane(u[BM_UNROLL - 1], WAVE - 1) <= s_last;
-                            int32_t un[BM_UNROLL];
-#pragma unroll
-                            for (int q = 0; q < BM_UNROLL; ++q) {
-                                const int64_t t = tn + q * WAVE + lane();
-                                un[q] = (more && t < h) ? A.col[t] : 0x7fffffff;
-                            }
-                            int32_t p[BM_UNROLL];
-#pragma unroll
-                            for (int q = 0; q < BM_UNROLL; ++q) p[q] = x + 1;
-                            // invariant: the answer lies in [p, p + n) within [x + 1, d)
-                            for (int32_t n = len; n > 1;) {
-                                const int32_t half = n >> 1;
-#pragma unroll
-                                for (int q = 0; q < BM_UNROLL; ++q) p[q] = (S[p[q] + half] <= u[q]) ? p[q] + half : p[q];
-                                n -= half;
-                            }
-#pragma unroll
-                            for (int q = 0; q < BM_UNROLL; ++q) {
-                                const bool f = S[p[q]] == u[q];
-                                if (f) atomicOr(&row[p[q] >> 6], 1ull << (p[q] & 63));
-                                c += (uint32_t)popc64(ballot(f));
-                            }
-                            streamed += (uint64_t)min<int64_t>(h - t0, WAVE * BM_UNROLL);
-                            if (!more) break;
-#pragma unroll
-                            for (int q = 0; q < BM_UNROLL; ++q) u[q] = un[q];
-                            t0 = tn;
-                        }
+            const int32_t xc = (int32_t)item_round(item) * WAVE;
+            // out-list bounds of the round's entries, one per lane
+            const int32_t xl = xc + lane();
+            int64_t lo = 0, hi = 0;
+            if (xl < d - 1) {
+                const int32_t v = S[xl];
+                lo = A.rp[v];
+                hi = A.rp[v + 1];
+            }
+            uint32_t mine = 0;
+            const int nx = min(WAVE, d - xc);
+            for (int xi = 0; xi < nx; ++xi) {
+                const int32_t x = xc + xi;
+                const int64_t l = (int64_t)readlane64((uint64_t)lo, xi);
+                const int64_t n_cand = (int64_t)readlane64((uint64_t)hi, xi) - l;
+                if (lane() < W) row[lane()] = 0ull;
+                wave_sync();
+                uint32_t c = 0;   // hits = children of x (wave-uniform)
+                // n_cand > 0 only when x < d - 1, so S[x+1, d) is non-empty
+                if (n_cand > 0) {
+                    static_assert(BM_MAXD <= 1024, "depths below cover len < 1024");
+                    const int lg = 31 - __clz(d - x - 1);
+                    switch (lg) {
+                        case 0: c = stream_entry<0>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        case 1: c = stream_entry<1>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        case 2: c = stream_entry<2>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        case 3: c = stream_entry<3>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        case 4: c = stream_entry<4>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        case 5: c = stream_entry<5>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        case 6: c = stream_entry<6>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        case 7: c = stream_entry<7>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        case 8: c = stream_entry<8>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                        default: c = stream_entry<9>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
                     }
-                    wave_sync();
-                    const unsigned long long word = lane() < W ? row[lane()] : 0ull;
-                    if (lane() < W) Mr[(uint64_t)x * W + lane()] = word;
-                    if (lane() == xi) mine = c;
-                    wave_sync();
                 }
-                if (xl < d) {
-                    A.count[b + xl] = mine;
-                    A.info[b + xl] = row_info(base, xl, W);
-                }
+                wave_sync();
+                const unsigned long long word = lane() < W ? row[lane()] : 0ull;
+                if (lane() < W) Mr[(uint64_t)x * W + lane()] = word;
+                if (lane() == xi) mine = c;
+                wave_sync();
+            }
+            if (xl < d) {
+                A.count[b + xl] = mine;
+                A.info[b + xl] = row_info(base, xl, W);
             }
         }
     }
