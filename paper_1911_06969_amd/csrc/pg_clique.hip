@@ -72,8 +72,8 @@ template <int MODE, class SPtr>
 __device__ __forceinline__ void clique_segment(const CliqueArgs& A, CliqueLds& L, int w, SPtr S, int32_t s,
                                                int64_t b, CliqueAcc& acc) {
     const int32_t s_last = S[s - 1];
-    const int32_t x0 = (int32_t)max<int64_t>(0, A.x_lo - b);
-    const int32_t x1 = (int32_t)min<int64_t>(s, A.x_hi - b);
+    const int32_t x0 = (int32_t)max64(0, A.x_lo - b);
+    const int32_t x1 = (int32_t)min64(s, A.x_hi - b);
     for (int32_t xc = x0; xc < x1; xc += WAVE) {
         const int32_t x = xc + lane();
         int64_t lo = 0;
@@ -441,21 +441,21 @@ __device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left
             c += (uint32_t)popc64(ballot(f));
         }
     };
-    load(ua, cp, (int32_t)min<int64_t>(left, STEP));
+    load(ua, cp, (int32_t)min64(left, STEP));
     while (true) {
         // ua holds the current step; ub gets the next one
         bool more = left > STEP && readlane(ua[BM_UNROLL - 1], WAVE - 1) <= s_last;
-        if (more) load(ub, cp + STEP, (int32_t)min<int64_t>(left - STEP, STEP));
+        if (more) load(ub, cp + STEP, (int32_t)min64(left - STEP, STEP));
         search(ua);
-        streamed += (uint64_t)min<int64_t>(left, STEP);
+        streamed += (uint64_t)min64(left, STEP);
         if (!more) break;
         cp += STEP;
         left -= STEP;
         // ub holds the current step; ua gets the next one
         more = left > STEP && readlane(ub[BM_UNROLL - 1], WAVE - 1) <= s_last;
-        if (more) load(ua, cp + STEP, (int32_t)min<int64_t>(left - STEP, STEP));
+        if (more) load(ua, cp + STEP, (int32_t)min64(left - STEP, STEP));
         search(ub);
-        streamed += (uint64_t)min<int64_t>(left, STEP);
+        streamed += (uint64_t)min64(left, STEP);
         if (!more) break;
         cp += STEP;
         left -= STEP;
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
             const int64_t b = (int64_t)(A.seg[p] - A.seg_base);
             const int64_t e2 = (int64_t)(A.seg[p + 1] - A.seg_base);
             // the parent's children within the launch's window [x_lo, x_hi)
-            const int64_t x0 = max<int64_t>(b, A.x_lo), x1 = min<int64_t>(e2, A.x_hi);
+            const int64_t x0 = max64(b, A.x_lo), x1 = min64(e2, A.x_hi);
             if (x0 >= x1) continue;
             // the parent's ancestry: positions of its vertices after the root
             int32_t apos[PG_KMAX];

@@ -36,6 +36,11 @@ __device__ __forceinline__ int64_t bcast64(int64_t v, int src) {
     return (int64_t)__shfl((long long)v, src, WAVE);
 }
 
+// 64-bit integer min / max by compare and select (HIP's generic min/max on
+// 64-bit integers goes through double precision).
+__host__ __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+__host__ __device__ __forceinline__ int64_t max64(int64_t a, int64_t b) { return a > b ? a : b; }
+
 // Value of v in lane l, for a wave-uniform l (a scalar read of the lane's
 // register, no LDS traffic).
 __device__ __forceinline__ int32_t readlane(int32_t v, int l) {
@@ -112,6 +117,39 @@ __device__ __forceinline__ bool contains(P a, int32_t len, int32_t key) {
         n -= half;
     }
     return a[base] == key;
+}
+
+// Membership of key in the sorted a[0, n) for n >= 1, LG = floor(log2(n)):
+// Shar's search.  With m = 2^LG, one probe at m - 1 decides whether the
+// last element <= key lies among the first m - 1 positions or the last m;
+// strides m/2 .. 1 finish it.  Probes stay inside a[0, n), strides are
+// immediates and the chain is straight-line code.
+template <int LG, class P>
+__device__ __forceinline__ bool member_shar(P a, int32_t n, int32_t key) {
+    constexpr int32_t m = 1 << LG;
+    P q = (a[m - 1] <= key) ? a + (n - m) : a - 1;   // last element <= key, or a - 1
+#pragma unroll
+    for (int st = m / 2; st >= 1; st >>= 1) q = (q[st] <= key) ? q + st : q;
+    return q >= a && *(q >= a ? q : a) == key;
+}
+
+// Membership for a wave-uniform n (the depth switch is a scalar branch).
+template <class P>
+__device__ __forceinline__ bool member_u(P a, int32_t n, int32_t key) {
+    if (n <= 0) return false;
+    switch (31 - __clz(n)) {
+        case 0: return member_shar<0>(a, n, key);
+        case 1: return member_shar<1>(a, n, key);
+        case 2: return member_shar<2>(a, n, key);
+        case 3: return member_shar<3>(a, n, key);
+        case 4: return member_shar<4>(a, n, key);
+        case 5: return member_shar<5>(a, n, key);
+        case 6: return member_shar<6>(a, n, key);
+        case 7: return member_shar<7>(a, n, key);
+        case 8: return member_shar<8>(a, n, key);
+        case 9: return member_shar<9>(a, n, key);
+        default: return contains(a, n, key);
+    }
 }
 
 // ---------------------------------------------------------- work queues

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, int64_t nnz, const 
             if (j > r0 && col[j - 1] >= u) bad |= BAD_ORDER;
             const int64_t q0 = rp[u], q1 = rp[u + 1];
             if (q0 < 0 || q1 < q0 || q1 > nnz) continue;   // reported by u's own wave
-            if (!contains(col + q0, (int32_t)min<int64_t>(q1 - q0, INT32_MAX), (int32_t)v))
+            if (!contains(col + q0, (int32_t)min64(q1 - q0, INT32_MAX), (int32_t)v))
                 bad |= BAD_SYMMETRY;
         }
     }

@@ -138,6 +138,12 @@ __device__ __forceinline__ bool adj_has(const uint32_t* row, P a, int32_t len, i
     return row ? bit_has(row, u) : member(a, len, u);
 }
 
+// the same for a wave-uniform len (unrolled search)
+template <class P>
+__device__ __forceinline__ bool adj_has_u(const uint32_t* row, P a, int32_t len, int32_t u) {
+    return row ? bit_has(row, u) : member_u(a, len, u);
+}
+
 // relative cost of one membership test: 1 through LDS or a dense row,
 // otherwise the depth of a binary search in global memory
 __device__ __forceinline__ int32_t probe_cost(bool cheap, int32_t len) {
@@ -316,8 +322,8 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_l1(MotifArgs A) {
             const int64_t b = A.l1_seg[p], e = A.l1_seg[p + 1];
             const int32_t s = (int32_t)(e - b);
             // this item's entries, within the launch's window [x_lo, x_hi)
-            const int32_t xa = (int32_t)max<int64_t>(item_round(item) * WAVE, A.x_lo - b);
-            const int32_t xb = (int32_t)min<int64_t>(min<int64_t>(item_round(item) * WAVE + WAVE, s), A.x_hi - b);
+            const int32_t xa = (int32_t)max64(item_round(item) * WAVE, A.x_lo - b);
+            const int32_t xb = (int32_t)min64(min64(item_round(item) * WAVE + WAVE, s), A.x_hi - b);
             if (xa >= xb) continue;
             const int64_t r0 = A.rp[v0], r1 = A.rp[v0 + 1];
             const int32_t d0 = (int32_t)(r1 - r0);
@@ -416,10 +422,10 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
                     const bool va = ta < h, vb = tb < h;
                     const int32_t ua = va ? A.col[ta] : 0;
                     const int32_t ub = vb ? A.col[tb] : 0;
-                    const bool a0 = va && adj_has(h0, A0, d0, ua);
-                    const bool b0 = vb && adj_has(h0, A0, d0, ub);
-                    const bool a1 = va && adj_has(h1, A1, d1, ua);
-                    const bool b1 = vb && adj_has(h1, A1, d1, ub);
+                    const bool a0 = va && adj_has_u(h0, A0, d0, ua);
+                    const bool b0 = vb && adj_has_u(h0, A0, d0, ub);
+                    const bool a1 = va && adj_has_u(h1, A1, d1, ua);
+                    const bool b1 = vb && adj_has_u(h1, A1, d1, ub);
                     tally(c6, a0, a1, a0 && a1, ua > cv2);
                     tally(c6, b0, b1, b0 && b1, ub > cv2);
                 }
@@ -442,8 +448,8 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
                     int32_t u = 0;
                     if (t < tot) {
                         u = from0 ? A0[a0lo + t] : A1[a1lo + (t - d0p)];
-                        in2 = staged ? member(S2, len2, u) : adj_has(h2, A.col + base, len2, u);
-                        in1 = from0 && in2 && adj_has(h1, A1, d1, u);
+                        in2 = staged ? member_u(S2, len2, u) : adj_has_u(h2, A.col + base, len2, u);
+                        in1 = from0 && in2 && adj_has_u(h1, A1, d1, u);
                     }
                     tally(c6, from0 && in2, !from0 && in2, in1, u > cv2);
                 }
@@ -513,15 +519,16 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
         for (int64_t j = it; j < it_end; ++j) {
-            const uint64_t item = A.items[j];
+            // per item everything is wave-uniform: keep it in scalar registers
+            const uint64_t item = (uint64_t)uniform64((int64_t)A.items[j]);
             const int64_t p = item_seg(item);
             const int32_t xc = (int32_t)item_round(item) * WAVE;
-            const int64_t b = (int64_t)(A.seg2[p] - A.seg2_base);
-            const int32_t s = (int32_t)(A.seg2[p + 1] - A.seg2[p]);
+            const int64_t b = uniform64((int64_t)(A.seg2[p] - A.seg2_base));
+            const int32_t s = uniform((int32_t)(A.seg2[p + 1] - A.seg2[p]));
             if (xc >= s) continue;
-            const int32_t v0 = A.l1_src[p], v1 = A.l1_dst[p];
-            const int64_t r0 = A.rp[v0], q0 = A.rp[v1];
-            const int32_t d0 = (int32_t)(A.rp[v0 + 1] - r0), d1 = (int32_t)(A.rp[v1 + 1] - q0);
+            const int32_t v0 = uniform(A.l1_src[p]), v1 = uniform(A.l1_dst[p]);
+            const int64_t r0 = uniform64(A.rp[v0]), q0 = uniform64(A.rp[v1]);
+            const int32_t d0 = uniform((int32_t)(A.rp[v0 + 1] - r0)), d1 = uniform((int32_t)(A.rp[v1 + 1] - q0));
             const uint64_t n_here = (uint64_t)(min(xc + WAVE, s) - xc);
             n_in += (lane() == 0) ? n_here : 0;
             deg_sum += (lane() == 0) ? n_here * (uint64_t)(d0 + d1) : 0;
@@ -545,10 +552,10 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
                 if (j < di) {
                     if (it0) {
                         u = st0 ? L.A0[w][j] : gA0[j];
-                        f = u > v0 && (st1 ? member(&L.A1[w][0], d1, u) : adj_has(h1, gA1, d1, u));
+                        f = u > v0 && (st1 ? member_u(&L.A1[w][0], d1, u) : adj_has_u(h1, gA1, d1, u));
                     } else {
                         u = st1 ? L.A1[w][j] : gA1[j];
-                        f = u > v0 && (st0 ? member(&L.A0[w][0], d0, u) : adj_has(h0, gA0, d0, u));
+                        f = u > v0 && (st0 ? member_u(&L.A0[w][0], d0, u) : adj_has_u(h0, gA0, d0, u));
                     }
                 }
                 const uint64_t F = ballot(f);
