@@ -566,8 +566,19 @@ __global__ __launch_bounds__(256) void k_clique_write_masks(int64_t e_lo, int64_
             const uint64_t f = has ? info[e] : 0;
             Wl = info_w(f);
             const uint64_t* rowp = M + info_base(f) + (uint64_t)info_i(f) * Wl;
+            // in 16-byte pairs (half the scattered load instructions)
+            static_assert(BM_W % 2 == 0, "rows are read in word pairs");
 #pragma unroll
-            for (int q = 0; q < BM_W; ++q) words[q] = q < Wl ? rowp[q] : 0ull;
+            for (int q = 0; q < BM_W; q += 2) {
+                if (q + 1 < Wl) {
+                    const ulonglong2 pr = *reinterpret_cast<const ulonglong2*>(rowp + q);
+                    words[q] = pr.x;
+                    words[q + 1] = pr.y;
+                } else {
+                    words[q] = q < Wl ? rowp[q] : 0ull;
+                    words[q + 1] = 0ull;
+                }
+            }
             if (has) read += 8u + 8u * (uint64_t)Wl;
         }
         uint64_t todo = ballot(has);
@@ -611,7 +622,14 @@ __global__ __launch_bounds__(256) void k_clique_last_masks(int64_t m, const int3
         const uint64_t* r1 = blk + (uint64_t)info_i(f) * W;
         const int j = pos[x];
         const uint64_t* r2 = blk + (uint64_t)j * W;
-        for (int q = j >> 6; q < W; ++q) found += (uint64_t)__popcll(r1[q] & r2[q]);
+        // row words in 16-byte pairs: half the (scattered) load instructions
+        int q = j >> 6;
+        for (; q + 1 < W; q += 2) {
+            const ulonglong2 a = *reinterpret_cast<const ulonglong2*>(r1 + q);
+            const ulonglong2 c = *reinterpret_cast<const ulonglong2*>(r2 + q);
+            found += (uint64_t)(__popcll(a.x & c.x) + __popcll(a.y & c.y));
+        }
+        if (q < W) found += (uint64_t)__popcll(r1[q] & r2[q]);
         words += (uint64_t)(W - (j >> 6));
     }
     found = wave_sum_u64(found);
