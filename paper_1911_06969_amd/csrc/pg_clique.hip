@@ -703,12 +703,28 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
                 const bool valid = x < x1;
                 const int32_t px = valid ? A.ch.pos[A.lev][x] : 0;
                 const uint64_t* row = blk + (uint64_t)px * W;
-                uint64_t words[BM_W];
+                // only the words where the parent's set is non-empty (a
+                // wave-uniform test) are read, in 16-byte pairs
+                uint64_t words[MODE == MODE_WRITE ? BM_W : 1];
                 uint32_t cnt = 0;
 #pragma unroll
-                for (int q = 0; q < BM_W; ++q) {
-                    words[q] = (valid && q < W) ? (s[q] & row[q]) : 0ull;
-                    cnt += (uint32_t)__popcll(words[q]);
+                for (int q = 0; q < BM_W; q += 2) {
+                    const uint64_t s0 = q < W ? s[q] : 0ull, s1 = q + 1 < W ? s[q + 1] : 0ull;
+                    uint64_t w0 = 0ull, w1 = 0ull;
+                    if ((s0 | s1) != 0ull && valid) {
+                        if (q + 1 < W) {
+                            const ulonglong2 pr = *reinterpret_cast<const ulonglong2*>(row + q);
+                            w0 = s0 & pr.x;
+                            w1 = s1 & pr.y;
+                        } else {
+                            w0 = s0 & row[q];
+                        }
+                    }
+                    cnt += (uint32_t)(__popcll(w0) + __popcll(w1));
+                    if constexpr (MODE == MODE_WRITE) {
+                        words[q] = w0;
+                        words[q + 1] = w1;
+                    }
                 }
                 if (MODE == MODE_COUNT && valid) A.count[x] = cnt;
                 if (MODE == MODE_LAST) acc += cnt;
