@@ -672,32 +672,55 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
-        for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
+        // set-up of up to 64 parents side by side: lane l walks the ancestry
+        // of parent it + l and forms its set S (the AND of the rows of its
+        // vertices after the root), word q in sp[q]
+        const int64_t p = A.p_lo + it + lane();
+        int64_t px0 = 0, px1 = 0;
+        int Wl = 0;
+        uint64_t bl = 0;
+        uint64_t sp[BM_W];
+#pragma unroll
+        for (int q = 0; q < BM_W; ++q) sp[q] = 0ull;
+        if (it + lane() < it_end) {
             const int64_t b = (int64_t)(A.seg[p] - A.seg_base);
             const int64_t e2 = (int64_t)(A.seg[p + 1] - A.seg_base);
             // the parent's children within the launch's window [x_lo, x_hi)
-            const int64_t x0 = max64(b, A.x_lo), x1 = min64(e2, A.x_hi);
-            if (x0 >= x1) continue;
-            // the parent's ancestry: positions of its vertices after the root
-            int32_t apos[PG_KMAX];
-            int na = 0;
-            int64_t c = p;
-            for (int l = A.lev - 1; l >= 2; --l) {
-                apos[na++] = A.ch.pos[l][c];
-                c = A.ch.idx[l][c];
+            px0 = max64(b, A.x_lo);
+            px1 = min64(e2, A.x_hi);
+            if (px0 < px1) {
+                int32_t apos[PG_KMAX];
+                int na = 0;
+                int64_t c = p;
+                for (int l = A.lev - 1; l >= 2; --l) {
+                    apos[na++] = A.ch.pos[l][c];
+                    c = A.ch.idx[l][c];
+                }
+                const uint64_t f = A.info[c];         // c: the level-1 entry
+                Wl = info_w(f);
+                bl = info_base(f);
+                const uint64_t* blk = A.M + bl;
+#pragma unroll
+                for (int q = 0; q < BM_W; ++q) {
+                    if (q < Wl) {
+                        uint64_t v = blk[(uint64_t)info_i(f) * Wl + q];
+                        for (int a2 = 0; a2 < na; ++a2) v &= blk[(uint64_t)apos[a2] * Wl + q];
+                        sp[q] = v;
+                    }
+                }
             }
-            const uint64_t f = A.info[c];         // c: the level-1 entry
-            const int W = info_w(f);
-            const uint64_t* blk = A.M + info_base(f);
-            // S of the parent, one word per lane
-            uint64_t sp = 0;
-            if (lane() < W) {
-                sp = blk[(uint64_t)info_i(f) * W + lane()];
-                for (int a = 0; a < na; ++a) sp &= blk[(uint64_t)apos[a] * W + lane()];
-            }
+        }
+        uint64_t todo_p = ballot(px0 < px1);
+        while (todo_p) {
+            const int pi = __ffsll((unsigned long long)todo_p) - 1;
+            todo_p &= todo_p - 1;
+            const int W = readlane(Wl, pi);
+            const uint64_t* blk = A.M + readlane64(bl, pi);
             uint64_t s[BM_W];
 #pragma unroll
-            for (int q = 0; q < BM_W; ++q) s[q] = q < W ? readlane64(sp, q) : 0ull;
+            for (int q = 0; q < BM_W; ++q) s[q] = q < W ? readlane64(sp[q], pi) : 0ull;
+            const int64_t x0 = (int64_t)readlane64((uint64_t)px0, pi);
+            const int64_t x1 = (int64_t)readlane64((uint64_t)px1, pi);
             for (int64_t xb = x0; xb < x1; xb += WAVE) {
                 const int64_t x = xb + lane();
                 const bool valid = x < x1;
@@ -784,7 +807,8 @@ static void launch_mask(CliqueRun& R, MaskArgs A, int64_t p_lo, int64_t n_par, c
     fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, R.s);
     A.Q.next = R.qctr;
     A.Q.n_items = n_par;
-    A.Q.chunk = n_par >= R.waves * 64 ? 16 : (n_par >= R.waves * 8 ? 4 : 1);
+    // a wave sets up at most 64 parents at once (one per lane)
+    A.Q.chunk = n_par >= R.waves * 64 ? WAVE : (n_par >= R.waves * 8 ? 8 : 1);
     A.p_lo = p_lo;
     A.stats = R.stats;
     ProfScope ps(name, R.s, units);
