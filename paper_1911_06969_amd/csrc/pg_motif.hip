@@ -467,15 +467,16 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
             const int32_t u1 = (int32_t)upper_bound(A1, a1lo, d1, v2);
             const int64_t u2 = upper_bound(A.col, lo2, s1, v2);
             const int32_t uc = (int32_t)upper_bound(C, 0, nc, v2);
-            int64_t I0[2] = {u0 - a0lo, d0 - u0};
-            int64_t I1[2] = {u1 - a1lo, d1 - u1};
-            int64_t I2[2] = {u2 - lo2, s1 - u2};
-            int64_t I01[2] = {uc, nc - uc};
-            int64_t N[2][8];
+            // per-child counts are bounded by a degree: 32-bit (fewer registers)
+            const int32_t I0[2] = {u0 - a0lo, d0 - u0};
+            const int32_t I1[2] = {u1 - a1lo, d1 - u1};
+            const int32_t I2[2] = {(int32_t)(u2 - lo2), (int32_t)(s1 - u2)};
+            const int32_t I01[2] = {uc, nc - uc};
+            int32_t N[2][8];
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int64_t i02 = cnt[0 + r], i12 = cnt[2 + r];
-                const int64_t i012 = cnt[4 + r];
+                const int32_t i02 = (int32_t)cnt[0 + r], i12 = (int32_t)cnt[2 + r];
+                const int32_t i012 = (int32_t)cnt[4 + r];
                 N[r][0] = 0;
                 N[r][7] = i012;
                 N[r][3] = I01[r] - i012;
@@ -492,13 +493,13 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int m = 0; m < 8; ++m) N[r][m] -= (int64_t)((r == r1 && m == m1) + (r == 0 && m == m2));
+                for (int m = 0; m < 8; ++m) N[r][m] -= (int32_t)((r == r1 && m == m1) + (r == 0 && m == m2));
             const int ebits = 1 | (a02 << 1) | (a12 << 2);
 #pragma unroll
             for (int m = 1; m < 8; ++m) {
                 const int sbit = (m & 1) ? 0 : ((m & 2) ? 1 : 2);   // first adjacent position
                 if (sbit < p) continue;
-                const int64_t c = (sbit == p) ? N[1][m] : N[0][m] + N[1][m];
+                const int64_t c = (sbit == p) ? (int64_t)N[1][m] : (int64_t)N[0][m] + N[1][m];
                 const int pid = c_lut4.v[ebits | (m << 3)];
 #pragma unroll
                 for (int q = 0; q < 6; ++q) acc[q] += (pid == q) ? (uint64_t)c : 0ull;
