@@ -37,9 +37,15 @@ typedef int64_t i64;
 typedef int32_t i32;
 typedef uint64_t u64;
 
-static void set_threads(int nthreads) {
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-}
+/* The thread count asked for one call (0 = all), restored when it ends so
+ * that a call on a tiny graph does not leave later calls single-threaded. */
+struct ThreadScope {
+    int prev;
+    explicit ThreadScope(int nthreads) : prev(omp_get_max_threads()) {
+        if (nthreads > 0) omp_set_num_threads(nthreads);
+    }
+    ~ThreadScope() { omp_set_num_threads(prev); }
+};
 
 extern "C" int or_max_threads(void) { return omp_get_max_threads(); }
 
@@ -77,7 +83,7 @@ static std::vector<std::vector<i32>> degree_order_out(i64 n, const i64* rp, cons
 }
 
 extern "C" u64 or_clique_count(i64 n, const i64* rp, const i32* col, int k, int nthreads) {
-    set_threads(nthreads);
+    ThreadScope threads(nthreads);
     if (k <= 0) return 0;
     if (k == 1) return (u64)n;
     auto out = degree_order_out(n, rp, col);
@@ -91,7 +97,7 @@ extern "C" u64 or_clique_count(i64 n, const i64* rp, const i32* col, int k, int 
  * one of roots[0..nr); per-root counts go to per_root[]. */
 extern "C" u64 or_clique_count_roots(i64 n, const i64* rp, const i32* col, int k,
                                      const i64* roots, i64 nr, u64* per_root, int nthreads) {
-    set_threads(nthreads);
+    ThreadScope threads(nthreads);
     auto out = degree_order_out(n, rp, col);
     u64 total = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
@@ -165,7 +171,7 @@ static void esu_rec(const Esu& E, std::vector<i32>& sub, std::vector<i32> ext) {
 
 /* counts[] receives 2 (k=3) or 6 (k=4) values. */
 extern "C" void or_motif_esu(i64 n, const i64* rp, const i32* col, int k, u64* counts, int nthreads) {
-    set_threads(nthreads);
+    ThreadScope threads(nthreads);
     const int np = (k == 3) ? 2 : 6;
     for (int p = 0; p < np; ++p) counts[p] = 0;
 #pragma omp parallel
@@ -189,7 +195,7 @@ extern "C" void or_motif_esu(i64 n, const i64* rp, const i32* col, int k, u64* c
 extern "C" void or_motif_esu_roots(i64 n, const i64* rp, const i32* col, int k, const i64* roots,
                                    i64 nr, u64* counts, int nthreads) {
     (void)n;
-    set_threads(nthreads);
+    ThreadScope threads(nthreads);
     const int np = (k == 3) ? 2 : 6;
     for (int p = 0; p < np; ++p) counts[p] = 0;
 #pragma omp parallel
@@ -221,7 +227,7 @@ extern "C" void or_motif_esu_roots(i64 n, const i64* rp, const i32* col, int k, 
  * where t_uv = common neighbours of an edge, t_v = triangles at v and
  * c(u,w) = common neighbours of a vertex pair. */
 extern "C" void or_motif_parts(i64 n, const i64* rp, const i32* col, u64* parts, int nthreads) {
-    set_threads(nthreads);
+    ThreadScope threads(nthreads);
     u64 wedges = 0, star = 0, p4raw = 0, tri3 = 0, dia = 0;
     std::vector<u64> tv((size_t)n, 0);
     /* per-edge triangles by merging the two sorted lists */
@@ -493,7 +499,7 @@ static void fsm_esu(const FsmCtx& C, std::vector<i64>& sub, std::vector<i64> ext
  * emb_count[j] = number of (j+1)-edge embeddings. */
 extern "C" int or_fsm_supports(i64 n, const i64* rp, const i32* col, const i32* labels, int L,
                                int max_edges, u64* supports, u64* emb_count, int nthreads) {
-    set_threads(nthreads);
+    ThreadScope threads(nthreads);
     if (max_edges < 1 || max_edges > 3) return -1;
     std::vector<i32> eu, ev;
     for (i64 u = 0; u < n; ++u)
