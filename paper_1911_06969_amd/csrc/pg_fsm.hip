@@ -302,14 +302,17 @@ struct Bits {
     int64_t words;         // words per bitmap
     const int32_t* slot;   // pattern -> slot or -1
     int32_t s_lo, s_hi;    // slots of this group
+    const int32_t* lrank;  // vertex -> its rank among the vertices of its label
 };
 
 __device__ __forceinline__ void set_bits(const Bits& Bt, const Emb& E) {
     const int32_t sl = Bt.slot[E.pid];
     if (sl < Bt.s_lo || sl >= Bt.s_hi) return;
     uint32_t* base = Bt.bm + (int64_t)(sl - Bt.s_lo) * 4 * Bt.words;
+    // every vertex of an orbit has the orbit's label, so its bit is indexed
+    // by its rank within that label (bitmaps of max-label-count bits)
     for (int i = 0; i < E.nv; ++i) {
-        const uint32_t v = (uint32_t)E.v[i];
+        const uint32_t v = (uint32_t)Bt.lrank[E.v[i]];
         atomicOr(base + E.orb[i] * Bt.words + (v >> 5), 1u << (v & 31));
     }
 }
@@ -474,8 +477,9 @@ static unsigned grid1(int64_t items) {
 // Reduce over one level: supports of its patterns [p_lo, p_hi) (dense
 // index), frequent flags, and the host copy of the supports.
 template <class SetBits>
-static void reduce_level(pg_graph* g, FsmCtx& C, int64_t p_lo, int64_t p_hi, const uint32_t* counts,
-                         uint64_t sigma, uint8_t* freq, uint64_t* sup_pat, SetBits&& set_bits_pass) {
+static void reduce_level(pg_graph* g, FsmCtx& C, const int32_t* lrank, int64_t label_max, int64_t p_lo,
+                         int64_t p_hi, const uint32_t* counts, uint64_t sigma, uint8_t* freq, uint64_t* sup_pat,
+                         SetBits&& set_bits_pass) {
     hipStream_t s = g->stream;
     Arena& ar = g->arena;
     const int64_t np = p_hi - p_lo;
@@ -493,7 +497,7 @@ static void reduce_level(pg_graph* g, FsmCtx& C, int64_t p_lo, int64_t p_hi, con
     PG_HIP(hipGetLastError());
     uint64_t* sup_slot = push<uint64_t>(ar, std::max<int64_t>(ns, 1));
     if (ns > 0) {
-        const int64_t words = (g->n + 31) / 32;
+        const int64_t words = (label_max + 31) / 32;
         const uint64_t per_slot = (uint64_t)words * 4 * sizeof(uint32_t);
         const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
         const int64_t group = std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(room / std::max<uint64_t>(per_slot, 1))));
@@ -501,7 +505,7 @@ static void reduce_level(pg_graph* g, FsmCtx& C, int64_t p_lo, int64_t p_hi, con
         for (int64_t g0 = 0; g0 < ns; g0 += group) {
             const int64_t g1 = std::min(ns, g0 + group);
             fill_u32(bm, (g1 - g0) * 4 * words, 0, s);
-            Bits Bt{bm, words, slot, (int32_t)g0, (int32_t)g1};
+            Bits Bt{bm, words, slot, (int32_t)g0, (int32_t)g1, lrank};
             set_bits_pass(Bt);
             ProfScope ps("fsm_support", s, (double)(g1 - g0));
             k_supports<<<(unsigned)(g1 - g0), 256, 0, s>>>(bm, words, (int32_t)g0, (int32_t)g1, sup_slot);
@@ -512,6 +516,52 @@ static void reduce_level(pg_graph* g, FsmCtx& C, int64_t p_lo, int64_t p_hi, con
     k_frequent<<<grid1(np), 256, 0, s>>>(np, slot + p_lo, sup_slot, sigma, sup_pat + p_lo, freq + p_lo);
     PG_HIP(hipGetLastError());
     ar.reset(mk);
+}
+
+__global__ void k_label_keys(int64_t n, const int32_t* __restrict__ lab, uint64_t* __restrict__ keys,
+                             uint32_t* __restrict__ hist) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        keys[v] = ((uint64_t)(uint32_t)lab[v] << 32) | (uint64_t)v;
+        atomicAdd(&hist[lab[v]], 1u);
+    }
+}
+
+__global__ void k_label_ranks(int64_t n, const uint64_t* __restrict__ sorted, const uint64_t* __restrict__ first,
+                              int32_t* __restrict__ lrank) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = sorted[i];
+        lrank[(uint32_t)k] = (int32_t)((uint64_t)i - first[k >> 32]);
+    }
+}
+
+// Rank of every vertex among the vertices of its label (stable by id);
+// returns the largest label class.
+static int64_t label_ranks(pg_graph* g, int32_t* lrank) {
+    hipStream_t s = g->stream;
+    Arena& ar = g->arena;
+    const int64_t n = g->n, L = g->n_labels;
+    if (n == 0) return 0;
+    const size_t mk = ar.mark();
+    uint64_t* keys = push<uint64_t>(ar, n);
+    uint64_t* tmp = push<uint64_t>(ar, n);
+    uint32_t* hist = push<uint32_t>(ar, L);
+    uint64_t* first = push<uint64_t>(ar, L + 1);
+    fill_u32(hist, L, 0, s);
+    k_label_keys<<<grid1(n), 256, 0, s>>>(n, g->labels.as<int32_t>(), keys, hist);
+    PG_HIP(hipGetLastError());
+    int lb = 1;
+    while ((int64_t(1) << lb) < L) ++lb;
+    radix_sort_u64(keys, tmp, n, 0, 32 + lb, ar, s);
+    scan_u32(hist, L, first, ar, s);
+    k_label_ranks<<<grid1(n), 256, 0, s>>>(n, keys, first, lrank);
+    PG_HIP(hipGetLastError());
+    std::vector<uint32_t> h((size_t)L);
+    PG_HIP(hipMemcpyAsync(h.data(), hist, sizeof(uint32_t) * L, hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    ar.reset(mk);
+    int64_t mx = 0;
+    for (uint32_t c : h) mx = std::max<int64_t>(mx, c);
+    return mx;
 }
 
 void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports, size_t len, size_t* n_frequent) {
@@ -555,6 +605,8 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
         ar.reset(mk);
     }
     C.path_rank = prank;
+    int32_t* lrank = push<int32_t>(ar, std::max<int64_t>(g->n, 1));
+    const int64_t label_max = label_ranks(g, lrank);
     uint32_t* counts = push<uint32_t>(ar, np);
     uint8_t* freq = push<uint8_t>(ar, np);
     uint64_t* sup_pat = push<uint64_t>(ar, np);
@@ -574,7 +626,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
         k_hist<<<grid1(E), 256, 0, s>>>(E, pid1, counts);
         PG_HIP(hipGetLastError());
     }
-    reduce_level(g, C, C.B.edge, C.B.wedge, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
+    reduce_level(g, C, lrank, label_max, C.B.edge, C.B.wedge, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
         k_fsm_l1<true><<<grid1(E), 256, 0, s>>>(C, E, nullptr, Bt);
         PG_HIP(hipGetLastError());
     });
@@ -611,7 +663,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
             k_hist<<<grid1(n2), 256, 0, s>>>(n2, p2, counts);
             PG_HIP(hipGetLastError());
         }
-        reduce_level(g, C, C.B.wedge, C.B.tri, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
+        reduce_level(g, C, lrank, label_max, C.B.wedge, C.B.tri, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
             if (n2 > 0) {
                 k_fsm_l2_bits<<<grid1(n2), 256, 0, s>>>(C, n2, a2, b2, Bt);
                 PG_HIP(hipGetLastError());
@@ -636,7 +688,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
                 k_fsm_l3<false><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, counts, Bits{}, n_emb);
                 PG_HIP(hipGetLastError());
             }
-            reduce_level(g, C, C.B.tri, C.B.total, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
+            reduce_level(g, C, lrank, label_max, C.B.tri, C.B.total, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
                 if (m2 > 0) {
                     ProfScope ps("fsm_l3_bits", s, (double)m2);
                     k_fsm_l3<true><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bt, nullptr);
