@@ -236,7 +236,7 @@ def main():
             with open(args.traffic) as f:
                 t = json.load(f)
             entry = t.get(w)
-            if entry and entry.get("kernel_source_sha") == kernel_source_sha():
+            if entry and entry.get("kernel_source_sha") == kernel_source_sha(w):
                 traffic = entry["bytes_per_launch"]
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -376,14 +376,22 @@ def measure_batch_and_serve(args):
     return out
 
 
-def kernel_source_sha() -> str:
+# the sources that define each workload's kernels (its pipeline file plus the
+# shared device helpers and runtime), for keying stored counter readings
+KERNEL_FILES = {
+    "clique4": ["pg_clique.hip"], "clique5": ["pg_clique.hip"], "tc": ["pg_clique.hip"],
+    "motif4": ["pg_motif.hip"], "motif3": ["pg_motif.hip"], "fsm": ["pg_fsm.hip"],
+}
+COMMON_FILES = ["pg_device.h", "pg_internal.h", "pg_runtime.hip"]
+
+
+def kernel_source_sha(workload: str = "clique4") -> str:
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1911_06969_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_FILES.get(workload, []) + COMMON_FILES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
