@@ -39,6 +39,16 @@ def test_complete_graphs(torch):
         assert gpu_cliques(g, range(1, 9)) == [comb(n, k) for k in range(1, 9)]
 
 
+def test_mask_row_width_limit(torch):
+    """K_769: the lowest-ranked vertex has DAG out-degree 768, the most the
+    sibling masks take (12-word rows, the deepest search of the count pass);
+    K_770 (out-degree 769) goes to the general kernels.  K_130 takes 3-word
+    rows through the deeper mask levels.  Every count against C(n, k)."""
+    for n, ks in ((769, (3, 4)), (770, (3, 4)), (130, (3, 4, 5, 6))):
+        say("K", n)
+        assert gpu_cliques(synth.complete(n), ks) == [comb(n, k) for k in ks]
+
+
 def test_empty_and_edge_cases(torch):
     assert gpu_cliques(synth.empty(5), [1, 2, 3, 4]) == [5, 0, 0, 0]
     assert gpu_cliques(synth.empty(0), [1, 3]) == [0, 0]

@@ -57,6 +57,15 @@ def test_er_against_oracle(torch, n, p, L, sigma):
         assert np.array_equal(got, want)
 
 
+def test_largest_label_alphabet(torch):
+    """64 labels, the most a graph may carry: 11.5 million pattern slots
+    for up to 3 edges, label ranks up to ~60 per class."""
+    g = synth.erdos_renyi(3000, 0.004, seed=47, n_labels=64)
+    for K in (1, 2, 3):
+        for sigma in (1, 3):
+            assert np.array_equal(gpu_fsm(g, K, sigma), oracle.fsm(g, K, sigma)), (K, sigma)
+
+
 def test_power_law_labelled(torch):
     g = synth.rmat(11, 8, seed=43)
     g = synth.CSR(g.row_ptr, g.col, synth.random_labels(g.n, 5, 44), 5)
