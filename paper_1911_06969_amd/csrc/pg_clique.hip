@@ -225,7 +225,7 @@ struct CliqueRun {
     int k;
     hipStream_t s;
     unsigned long long* stats;
-    unsigned long long* qctr;   // N_XCD counters
+    unsigned long long* qctr;   // Q_WORDS words of queue counters
     int64_t waves;
     int blocks;
     uint64_t mwords = 0;        // mask path: words of all mask rows
@@ -234,7 +234,7 @@ struct CliqueRun {
 template <int MODE>
 static void launch(CliqueRun& R, CliqueArgs A, int64_t p_lo, int64_t n_seg, const char* name, double units) {
     if (n_seg <= 0) return;
-    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, R.s);
+    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, R.s);
     A.Q.next = R.qctr;
     A.Q.n_items = n_seg;
     A.Q.chunk = n_seg >= R.waves * 64 ? 16 : (n_seg >= R.waves * 8 ? 4 : 1);
@@ -363,29 +363,53 @@ __device__ __forceinline__ int info_w(uint64_t info) { return (int)(info & 15); 
 __device__ __forceinline__ int info_i(uint64_t info) { return (int)((info >> 4) & 1023); }
 __device__ __forceinline__ uint64_t info_base(uint64_t info) { return info >> 14; }
 
+constexpr int BM_CHUNK = 8;              // most count-pass items a wave takes at once
+
 struct BmLds {
     int32_t S[CQ_WAVES][BM_MAXD];
     unsigned long long row[CQ_WAVES][BM_W];
+    uint4 item[CQ_WAVES][BM_CHUNK];      // b, d | round << 16, mask base (low, high)
 };
 
-// Search of BM_UNROLL keys in S[x+1, d), x and d wave-uniform and
+// Search of NK <= BM_UNROLL keys in S[x+1, d), x and d wave-uniform and
 // LG = floor(log2(len)), len = d - x - 1 >= 1: for each key u the last
 // element P of S[x, d) with P = S + x or *P <= u.  With m = 2^LG, one probe
 // at x + m decides whether the answer lies among the first m positions or
 // the last m; strides m/2 .. 1 finish it (Shar's method).  Every probe stays
 // inside S[x+1, d); all strides are immediates (LDS offsets) and the chain
 // is straight-line code, so a step costs one add, compare and select.
-template <int LG>
+template <int LG, int NK>
 __device__ __forceinline__ void bs_find(const int32_t* S, int32_t x, int32_t d, const int32_t* (&P)[BM_UNROLL],
                                         const int32_t (&u)[BM_UNROLL]) {
     constexpr int32_t m = 1 << LG;
     const int32_t pivot = S[x + m];
 #pragma unroll
-    for (int q = 0; q < BM_UNROLL; ++q) P[q] = (pivot <= u[q]) ? S + (d - m) : S + x;
+    for (int q = 0; q < NK; ++q) P[q] = (pivot <= u[q]) ? S + (d - m) : S + x;
 #pragma unroll
     for (int st = m / 2; st >= 1; st >>= 1)
 #pragma unroll
-        for (int q = 0; q < BM_UNROLL; ++q) P[q] = (P[q][st] <= u[q]) ? P[q] + st : P[q];
+        for (int q = 0; q < NK; ++q) P[q] = (P[q][st] <= u[q]) ? P[q] + st : P[q];
+}
+
+// Looks up keys u[0, NK) in S[x+1, d) (LG as for bs_find); hits set bits of
+// the LDS row.  Returns the number of hits (wave-uniform).  No key equals
+// S[x], so a search ending at S + x is a miss.
+template <int LG, int NK>
+__device__ __forceinline__ uint32_t search_keys(const int32_t* S, int32_t x, int32_t d,
+                                                const int32_t (&u)[BM_UNROLL], unsigned long long* row) {
+    const int32_t* P[BM_UNROLL];
+    bs_find<LG, NK>(S, x, d, P, u);
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        const bool f = *P[q] == u[q];
+        if (f) {
+            const int32_t pos = (int32_t)(P[q] - S);
+            atomicOr(&row[pos >> 6], 1ull << (pos & 63));
+        }
+        c += (uint32_t)popc64(ballot(f));
+    }
+    return c;
 }
 
 struct BmArgs {
@@ -412,8 +436,12 @@ struct BmArgs {
 // S[x+1, d): BM_UNROLL loads per lane per step, double-buffered (the next
 // step's loads fly during this step's search, the two buffers alternate),
 // hits set bits of the LDS row.  Stops once the list passes s_last.
-// Returns the number of hits (wave-uniform).  No element of out(v) equals
-// S[x] = v, so a search ending at S + x is a miss.
+// Returns the number of hits (wave-uniform).
+//
+// Every step issues its loads unconditionally (past the end of the list a
+// lane loads the last element and discards it; after the final step the
+// loads repeat the current one), so the number of loads in flight is known
+// at compile time and the search waits for its own step's data only.
 template <int LG>
 __device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left, const int32_t* S, int32_t x,
                                                  int32_t d, int32_t s_last, unsigned long long* row,
@@ -421,31 +449,32 @@ __device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left
     constexpr int STEP = WAVE * BM_UNROLL;
     uint32_t c = 0;
     int32_t ua[BM_UNROLL], ub[BM_UNROLL];
+    // lim >= 1 elements valid from p
     auto load = [&](int32_t (&u)[BM_UNROLL], const int32_t* p, int32_t lim) {
 #pragma unroll
         for (int q = 0; q < BM_UNROLL; ++q) {
             const int32_t o = q * WAVE + lane();
-            u[q] = o < lim ? p[o] : 0x7fffffff;
+            const int32_t val = p[min(o, lim - 1)];
+            u[q] = o < lim ? val : 0x7fffffff;
         }
     };
+    // A step is sorted: once the first key of a row of 64 exceeds s_last,
+    // neither it nor any later key can hit, and those rows are not searched.
+    static_assert(BM_UNROLL == 3, "the row cases below are written out for three rows");
     auto search = [&](const int32_t (&u)[BM_UNROLL]) {
-        const int32_t* P[BM_UNROLL];
-        bs_find<LG>(S, x, d, P, u);
-#pragma unroll
-        for (int q = 0; q < BM_UNROLL; ++q) {
-            const bool f = *P[q] == u[q];
-            if (f) {
-                const int32_t pos = (int32_t)(P[q] - S);
-                atomicOr(&row[pos >> 6], 1ull << (pos & 63));
-            }
-            c += (uint32_t)popc64(ballot(f));
-        }
+        if (readlane(u[2], 0) <= s_last) c += search_keys<LG, 3>(S, x, d, u, row);
+        else if (readlane(u[1], 0) <= s_last) c += search_keys<LG, 2>(S, x, d, u, row);
+        else if (readlane(u[0], 0) <= s_last) c += search_keys<LG, 1>(S, x, d, u, row);
+    };
+    // the next step's loads: of cp + STEP if there is one, else of cp again
+    auto next = [&](int32_t (&u)[BM_UNROLL], bool more) {
+        load(u, more ? cp + STEP : cp, more ? (int32_t)min64(left - STEP, STEP) : 1);
     };
     load(ua, cp, (int32_t)min64(left, STEP));
     while (true) {
         // ua holds the current step; ub gets the next one
         bool more = left > STEP && readlane(ua[BM_UNROLL - 1], WAVE - 1) <= s_last;
-        if (more) load(ub, cp + STEP, (int32_t)min64(left - STEP, STEP));
+        next(ub, more);
         search(ua);
         streamed += (uint64_t)min64(left, STEP);
         if (!more) break;
@@ -453,7 +482,7 @@ __device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left
         left -= STEP;
         // ub holds the current step; ua gets the next one
         more = left > STEP && readlane(ub[BM_UNROLL - 1], WAVE - 1) <= s_last;
-        if (more) load(ua, cp + STEP, (int32_t)min64(left - STEP, STEP));
+        next(ua, more);
         search(ub);
         streamed += (uint64_t)min64(left, STEP);
         if (!more) break;
@@ -468,64 +497,86 @@ __global__ __launch_bounds__(CQ_THREADS, 7) void k_clique_count_masks(BmArgs A) 
     const int w = threadIdx.x / WAVE;
     int32_t* S = L.S[w];
     unsigned long long* row = L.row[w];
+    if (lane() < BM_W) row[lane()] = 0ull;   // every entry leaves it zero again
     uint64_t streamed = 0;   // wave-uniform
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
-        for (int64_t j = it; j < it_end; ++j) {
-            // everything per item and per entry is wave-uniform: keep it scalar
-            const uint64_t item = (uint64_t)uniform64((int64_t)A.items[A.Q.n_items - 1 - j]);
+        // the chunk's item descriptors, loaded side by side (one item per
+        // lane) and kept in LDS.  The DAG has at most 2^31 - 1 edges and
+        // out-degrees of at most BM_MAXD here, so b fits 32 bits and d and
+        // the round share a word.
+        const int nj = (int)(it_end - it);   // <= BM_CHUNK
+        wave_sync();                         // the previous chunk's reads are done
+        if (lane() < nj) {
+            const uint64_t item = A.items[A.Q.n_items - 1 - (it + lane())];
             const int64_t r = item_seg(item);
-            const int64_t b = uniform64(A.rp[r]);
-            const int32_t d = uniform((int32_t)(A.rp[r + 1] - b));
+            const int64_t b0 = A.rp[r];
+            const uint64_t mb = A.moff[r];
+            L.item[w][lane()] = make_uint4((uint32_t)b0,
+                                           (uint32_t)(A.rp[r + 1] - b0) | ((uint32_t)item_round(item) << 16),
+                                           (uint32_t)mb, (uint32_t)(mb >> 32));
+        }
+        wave_sync();
+        for (int jj = 0; jj < nj; ++jj) {
+            // everything per item and per entry is wave-uniform: keep it scalar
+            const uint4 desc = L.item[w][jj];
+            const int64_t b = uniform((int32_t)desc.x);
+            const int32_t dr = uniform((int32_t)desc.y);
+            const int32_t d = dr & 0xffff;
             if (d < 2) continue;   // counts are pre-zeroed; rows and infos are never read
             const int W = (d + 63) >> 6;
+            const int32_t xc = (dr >> 16) * WAVE;
+            // out-list bounds of the round's entries, one per lane; the
+            // entry's vertex comes from HBM, so these loads fly with the staging
+            const int32_t xl = xc + lane();
+            int64_t lo = 0;
+            int32_t nl = 0;   // out-degree (the DAG has fewer than 2^31 edges)
+            if (xl < d - 1) {
+                const int32_t v = A.col[b + xl];
+                lo = A.rp[v];
+                nl = (int32_t)(A.rp[v + 1] - lo);
+            }
             wave_sync();           // the previous item's reads of S are done
             for (int k = lane(); k < d; k += WAVE) S[k] = A.col[b + k];
             wave_sync();
             const int32_t s_last = uniform(S[d - 1]);
-            const uint64_t base = (uint64_t)uniform64((int64_t)A.moff[r]);
+            const uint64_t base = ((uint64_t)(uint32_t)uniform((int32_t)desc.w) << 32) | (uint32_t)uniform((int32_t)desc.z);
             uint64_t* Mr = A.M + base;
-            const int32_t xc = (int32_t)item_round(item) * WAVE;
-            // out-list bounds of the round's entries, one per lane
-            const int32_t xl = xc + lane();
-            int64_t lo = 0, hi = 0;
-            if (xl < d - 1) {
-                const int32_t v = S[xl];
-                lo = A.rp[v];
-                hi = A.rp[v + 1];
-            }
             uint32_t mine = 0;
             const int nx = min(WAVE, d - xc);
             for (int xi = 0; xi < nx; ++xi) {
                 const int32_t x = xc + xi;
                 const int64_t l = (int64_t)readlane64((uint64_t)lo, xi);
-                const int64_t n_cand = (int64_t)readlane64((uint64_t)hi, xi) - l;
-                if (lane() < W) row[lane()] = 0ull;
-                wave_sync();
+                const int64_t n_cand = readlane(nl, xi);
                 uint32_t c = 0;   // hits = children of x (wave-uniform)
-                // n_cand > 0 only when x < d - 1, so S[x+1, d) is non-empty
-                if (n_cand > 0) {
-                    static_assert(BM_MAXD <= 1024, "depths below cover len < 1024");
-                    const int lg = 31 - __clz(d - x - 1);
-                    switch (lg) {
-                        case 0: c = stream_entry<0>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        case 1: c = stream_entry<1>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        case 2: c = stream_entry<2>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        case 3: c = stream_entry<3>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        case 4: c = stream_entry<4>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        case 5: c = stream_entry<5>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        case 6: c = stream_entry<6>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        case 7: c = stream_entry<7>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        case 8: c = stream_entry<8>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                        default: c = stream_entry<9>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
-                    }
+                // the row is all zero here; with no candidates it stays so
+                if (n_cand <= 0) {
+                    if (lane() < W) Mr[(uint64_t)x * W + lane()] = 0ull;
+                    continue;
                 }
-                wave_sync();
-                const unsigned long long word = lane() < W ? row[lane()] : 0ull;
-                if (lane() < W) Mr[(uint64_t)x * W + lane()] = word;
+                // n_cand > 0 only when x < d - 1, so S[x+1, d) is non-empty
+                static_assert(BM_MAXD <= 1024, "depths below cover len < 1024");
+                const int lg = 31 - __clz(d - x - 1);
+                switch (lg) {
+                    case 0: c = stream_entry<0>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    case 1: c = stream_entry<1>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    case 2: c = stream_entry<2>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    case 3: c = stream_entry<3>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    case 4: c = stream_entry<4>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    case 5: c = stream_entry<5>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    case 6: c = stream_entry<6>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    case 7: c = stream_entry<7>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    case 8: c = stream_entry<8>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                    default: c = stream_entry<9>(A.col + l, n_cand, S, x, d, s_last, row, streamed); break;
+                }
+                wave_sync();      // every lane's hits are in the row
+                if (lane() < W) {
+                    Mr[(uint64_t)x * W + lane()] = row[lane()];
+                    row[lane()] = 0ull;
+                }
                 if (lane() == xi) mine = c;
-                wave_sync();
+                wave_sync();      // cleared before the next entry's hits
             }
             if (xl < d) {
                 A.count[b + xl] = mine;
@@ -804,7 +855,7 @@ struct MaskCtx {
 template <int MODE>
 static void launch_mask(CliqueRun& R, MaskArgs A, int64_t p_lo, int64_t n_par, const char* name, double units) {
     if (n_par <= 0) return;
-    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, R.s);
+    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, R.s);
     A.Q.next = R.qctr;
     A.Q.n_items = n_par;
     // a wave sets up at most 64 parents at once (one per lane)
@@ -929,10 +980,10 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
         const size_t mk = ar.mark();
         uint64_t* items = nullptr;
         const int64_t n_items = round_items(rp, 0, n, WAVE, ar, s, &items);
-        fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, s);
+        fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, s);
         A.Q.next = R.qctr;
         A.Q.n_items = n_items;
-        A.Q.chunk = n_items >= R.waves * 64 ? 4 : 1;
+        A.Q.chunk = n_items >= R.waves * 64 ? 4 : 1;   // at most BM_CHUNK
         A.items = items;
         A.rp = rp;
         A.col = col;
@@ -1023,7 +1074,7 @@ uint64_t count_cliques(pg_graph* g, int k) {
     R.s = s;
     R.waves = grid_waves(32);
     R.blocks = (int)(R.waves / CQ_WAVES);
-    uint64_t* small = push<uint64_t>(ar, 16);
+    uint64_t* small = push<uint64_t>(ar, 8 + Q_WORDS);
     R.stats = reinterpret_cast<unsigned long long*>(small);
     R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
     fill_u64(small, 8, 0, s);

@@ -685,7 +685,7 @@ static void build_hubs(pg_graph* g) {
 }
 
 static void set_queue(MotifRun& R, MotifArgs& A, const uint64_t* items, int64_t n_items) {
-    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), N_XCD, 0, R.s);
+    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, R.s);
     A.Q.next = R.qctr;
     A.Q.n_items = n_items;
     A.Q.chunk = n_items >= R.waves * 64 ? 4 : 1;
@@ -757,7 +757,7 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
     R.s = s;
     R.waves = grid_waves(16);
     R.blocks = (int)(R.waves / MO_WAVES);
-    uint64_t* small = push<uint64_t>(ar, 32);
+    uint64_t* small = push<uint64_t>(ar, 16 + Q_WORDS);
     R.out = reinterpret_cast<unsigned long long*>(small);
     R.qctr = reinterpret_cast<unsigned long long*>(small + 16);
     fill_u64(small, 16, 0, s);
