@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "pg_device.h"
@@ -403,11 +404,12 @@ __device__ __forceinline__ uint32_t search_keys(const int32_t* S, int32_t x, int
 #pragma unroll
     for (int q = 0; q < NK; ++q) {
         const bool f = *P[q] == u[q];
-        if (f) {
-            const int32_t pos = (int32_t)(P[q] - S);
-            atomicOr(&row[pos >> 6], 1ull << (pos & 63));
-        }
         c += (uint32_t)popc64(ballot(f));
+        if (f) {
+            // byte offset in S: LDS addresses are 32-bit
+            const uint32_t off = (uint32_t)(reinterpret_cast<uintptr_t>(P[q]) - reinterpret_cast<uintptr_t>(S));
+            atomicOr(&row[off >> 8], 1ull << ((off >> 2) & 63));
+        }
     }
     return c;
 }
@@ -589,17 +591,28 @@ __global__ __launch_bounds__(CQ_THREADS, 7) void k_clique_count_masks(BmArgs A) 
 
 // write pass: a wave takes 64 consecutive level-1 entries (one per lane,
 // which loads its row), then, entry by entry, compacts the set bits of the
-// row a word at a time with a ballot: lane j handles bit j, so consecutive
-// children go to consecutive slots and the stores coalesce.  A level-2
-// entry is (parent level-1 entry, position in the root's out-list); its
-// vertex is the root's out-neighbour at that position.
-__global__ __launch_bounds__(256) void k_clique_write_masks(int64_t e_lo, int64_t e_hi,
-                                                            const uint64_t* __restrict__ info,
-                                                            const uint64_t* __restrict__ M,
-                                                            const uint64_t* __restrict__ start, uint64_t start_base,
-                                                            int32_t* __restrict__ out_idx,
-                                                            uint16_t* __restrict__ out_pos,
-                                                            unsigned long long* __restrict__ stats) {
+// row a word at a time with a ballot (lane j handles bit j; words that are
+// zero, such as all those below the entry's own position, are skipped with a
+// scalar branch).  The children of the wave's entries fill one contiguous
+// output range, so they gather in a buffer in LDS and leave in full 64-lane
+// coalesced stores.  A level-2 entry is (parent level-1 entry, position in
+// the root's out-list); its vertex is the root's out-neighbour at that
+// position.
+constexpr int WR_THREADS = 256;
+
+__global__ __launch_bounds__(WR_THREADS) void k_clique_write_masks(int64_t e_lo, int64_t e_hi,
+                                                                   const uint64_t* __restrict__ info,
+                                                                   const uint64_t* __restrict__ M,
+                                                                   const uint64_t* __restrict__ start,
+                                                                   uint64_t start_base,
+                                                                   int32_t* __restrict__ out_idx,
+                                                                   uint16_t* __restrict__ out_pos,
+                                                                   unsigned long long* __restrict__ stats) {
+    // fill < 64 before a word adds at most 64 children
+    __shared__ int32_t buf_idx[WR_THREADS / WAVE][2 * WAVE];
+    __shared__ uint16_t buf_pos[WR_THREADS / WAVE][2 * WAVE];
+    int32_t* bi = buf_idx[threadIdx.x / WAVE];
+    uint16_t* bp = buf_pos[threadIdx.x / WAVE];
     uint64_t read = 0;   // info and row bytes of the entries with children
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
@@ -632,56 +645,200 @@ __global__ __launch_bounds__(256) void k_clique_write_masks(int64_t e_lo, int64_
             }
             if (has) read += 8u + 8u * (uint64_t)Wl;
         }
+        // lane 0's entry e0 < e_hi opens the wave's output range
+        uint64_t out_at = readlane64(s0, 0);
+        int fill = 0;   // children in the buffer (wave-uniform)
+        // the words of entry li's row, for a row of NW words (unrolled)
+        auto emit = [&](auto nw, int li, int32_t parent) {
+            constexpr int NW = decltype(nw)::value;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const uint64_t wq = readlane64(words[q], li);
+                if (wq == 0) continue;
+                if ((wq >> lane()) & 1ull) {
+                    const int slot = fill + __popcll(wq & lanemask_lt());
+                    bi[slot] = parent;
+                    bp[slot] = (uint16_t)(q * 64 + lane());
+                }
+                fill += __popcll(wq);
+                if (fill >= WAVE) {
+                    wave_sync();
+                    out_idx[out_at + lane()] = bi[lane()];
+                    out_pos[out_at + lane()] = bp[lane()];
+                    const int32_t ti = bi[WAVE + lane()];
+                    const uint16_t tp = bp[WAVE + lane()];
+                    wave_sync();
+                    bi[lane()] = ti;
+                    bp[lane()] = tp;
+                    fill -= WAVE;
+                    out_at += WAVE;
+                }
+            }
+        };
+        static_assert(BM_W == 12, "the row widths below run to 12 words");
         uint64_t todo = ballot(has);
         while (todo) {
             const int li = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
-            uint64_t pos = readlane64(s0, li);
-            const int Wi = readlane(Wl, li);
             const int32_t parent = (int32_t)(e0 + li);
-#pragma unroll
-            for (int q = 0; q < BM_W; ++q) {
-                if (q < Wi) {
-                    const uint64_t wq = readlane64(words[q], li);
-                    if ((wq >> lane()) & 1ull) {
-                        const uint64_t slot = pos + (uint64_t)__popcll(wq & lanemask_lt());
-                        out_idx[slot] = parent;
-                        out_pos[slot] = (uint16_t)(q * 64 + lane());
-                    }
-                    pos += (uint64_t)__popcll(wq);
-                }
+            switch (readlane(Wl, li)) {
+                case 1: emit(std::integral_constant<int, 1>{}, li, parent); break;
+                case 2: emit(std::integral_constant<int, 2>{}, li, parent); break;
+                case 3: emit(std::integral_constant<int, 3>{}, li, parent); break;
+                case 4: emit(std::integral_constant<int, 4>{}, li, parent); break;
+                case 5: emit(std::integral_constant<int, 5>{}, li, parent); break;
+                case 6: emit(std::integral_constant<int, 6>{}, li, parent); break;
+                case 7: emit(std::integral_constant<int, 7>{}, li, parent); break;
+                case 8: emit(std::integral_constant<int, 8>{}, li, parent); break;
+                case 9: emit(std::integral_constant<int, 9>{}, li, parent); break;
+                case 10: emit(std::integral_constant<int, 10>{}, li, parent); break;
+                case 11: emit(std::integral_constant<int, 11>{}, li, parent); break;
+                default: emit(std::integral_constant<int, 12>{}, li, parent); break;
             }
         }
+        wave_sync();
+        if (lane() < fill) {
+            out_idx[out_at + lane()] = bi[lane()];
+            out_pos[out_at + lane()] = bp[lane()];
+        }
+        wave_sync();   // the buffer is refilled by the next batch
     }
     read = wave_sum_u64(read);
     if (lane() == 0 && read) atomicAdd(&stats[4], (unsigned long long)read);
 }
 
-// fused last level: one thread per level-2 entry (r, S[i], S[j]), i < j:
-// the 4-cliques it extends to are the set bits of row i AND row j (row j
-// only has bits above j, so each is counted once)
-__global__ __launch_bounds__(256) void k_clique_last_masks(int64_t m, const int32_t* __restrict__ idx,
-                                                           const uint16_t* __restrict__ pos,
-                                                           const uint64_t* __restrict__ info,
-                                                           const uint64_t* __restrict__ M,
-                                                           unsigned long long* __restrict__ stats) {
-    uint64_t found = 0, words = 0;
-    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < m; x += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t f = info[idx[x]];
-        const int W = info_w(f);
-        const uint64_t* blk = M + info_base(f);
-        const uint64_t* r1 = blk + (uint64_t)info_i(f) * W;
-        const int j = pos[x];
-        const uint64_t* r2 = blk + (uint64_t)j * W;
-        // row words in 16-byte pairs: half the (scattered) load instructions
-        int q = j >> 6;
-        for (; q + 1 < W; q += 2) {
-            const ulonglong2 a = *reinterpret_cast<const ulonglong2*>(r1 + q);
-            const ulonglong2 c = *reinterpret_cast<const ulonglong2*>(r2 + q);
-            found += (uint64_t)(__popcll(a.x & c.x) + __popcll(a.y & c.y));
+// fused last level: a level-2 entry (r, S[i], S[j]), i < j, extends to the
+// 4-cliques given by the set bits of row i AND row j (row j only has bits
+// above j, so each is counted once); a thread takes one entry at a time.
+// The mask rows are read from LDS.  The mask blocks of consecutive roots are
+// consecutive in M, so a run of roots (a window) is one word range of M.  A root whose block has LW_BIG words or more is a
+// window of its own; the others are grouped while their blocks start in the
+// same LW_SPAN-word stretch of M.  A window then spans fewer than
+// LW_SPAN + LW_BIG words, or one block (at most BM_MAXD * BM_W words).  A
+// work item is a round of at most LW_PER of a window's level-2 entries
+// (those of the current chunk of level-1 entries); a workgroup stages the
+// window's words in LDS, in 16-byte pieces, and counts its entries from
+// there.  Items are taken from a counter, one workgroup at a time.
+constexpr int LW_THREADS = 512;
+constexpr int LW_BIG = 3072;
+constexpr int LW_SPAN = 6144;
+constexpr int LW_CAP = BM_MAXD * BM_W + 2;   // +1 word when the range starts at an odd word, even
+constexpr int LW_PER = 1 << 15;
+static_assert(LW_SPAN + LW_BIG <= BM_MAXD * BM_W, "a window of small roots fits the LDS buffer");
+
+// window starts: mark[r] = 1 if root r opens a window
+__global__ void k_last_marks(int64_t n, const uint64_t* __restrict__ moff, uint32_t* __restrict__ mark) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t m0 = moff[r];
+        bool st = r == 0 || moff[r + 1] - m0 >= (uint64_t)LW_BIG;
+        if (!st) {
+            const uint64_t pm = moff[r - 1];
+            st = m0 - pm >= (uint64_t)LW_BIG || m0 / LW_SPAN != pm / LW_SPAN;
         }
-        if (q < W) found += (uint64_t)__popcll(r1[q] & r2[q]);
-        words += (uint64_t)(W - (j >> 6));
+        mark[r] = st ? 1u : 0u;
+    }
+}
+
+// first root of each window (woff = exclusive scan of mark); first[nw] = n
+__global__ void k_last_first(int64_t n, const uint32_t* __restrict__ mark, const uint64_t* __restrict__ woff,
+                             int64_t* __restrict__ first) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        if (mark[r]) first[woff[r]] = r;
+        if (r == n - 1) first[woff[n]] = n;
+    }
+}
+
+// level-2 entries of each window within the chunk of level-1 entries
+// [c0, c1): seg[w] .. seg[w + 1], counted from the chunk's first entry
+__global__ void k_last_segs(int64_t nw, const int64_t* __restrict__ first, const int64_t* __restrict__ rp,
+                            const uint64_t* __restrict__ start, int64_t c0, int64_t c1, uint64_t* __restrict__ seg) {
+    for (int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; w <= nw; w += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = min64(max64(rp[first[w]], c0), c1);
+        seg[w] = start[e] - start[c0];
+    }
+}
+
+// Entries e0 + threadIdx.x, ... < e1 (e0 < e1), LW_B at a time per thread:
+// their loads are clamped into [e0, e1) and issued together, so a thread
+// waits for one round trip per LW_B entries.
+constexpr int LW_B = 8;
+
+template <bool LDS>
+__device__ __forceinline__ void last_count(const uint64_t* base, uint64_t m_al, uint64_t e0, uint64_t e1,
+                                           const int32_t* __restrict__ idx, const uint16_t* __restrict__ pos,
+                                           const uint64_t* __restrict__ info, uint64_t& found, uint64_t& words) {
+    for (uint64_t x0 = e0 + threadIdx.x; x0 < e1; x0 += LW_B * LW_THREADS) {
+        int32_t p[LW_B];
+        int j[LW_B];
+#pragma unroll
+        for (int u = 0; u < LW_B; ++u) {
+            const uint64_t x = x0 + (uint64_t)u * LW_THREADS;
+            const uint64_t xc = x < e1 ? x : e1 - 1;
+            p[u] = idx[xc];
+            j[u] = pos[xc];
+        }
+        uint64_t f[LW_B];
+#pragma unroll
+        for (int u = 0; u < LW_B; ++u) f[u] = info[p[u]];
+#pragma unroll
+        for (int u = 0; u < LW_B; ++u) {
+            if (x0 + (uint64_t)u * LW_THREADS >= e1) break;
+            const int W = info_w(f[u]);
+            const uint64_t* blk = base + (info_base(f[u]) - m_al);
+            const uint64_t* r1 = blk + (uint64_t)info_i(f[u]) * W;
+            const uint64_t* r2 = blk + (uint64_t)j[u] * W;
+            for (int q = j[u] >> 6; q < W; ++q) found += (uint64_t)__popcll(r1[q] & r2[q]);
+            words += (uint64_t)(W - (j[u] >> 6));
+        }
+    }
+}
+
+__global__ __launch_bounds__(LW_THREADS) void k_clique_last_lds(const uint64_t* __restrict__ items, int64_t n_items,
+                                                                const uint64_t* __restrict__ seg,
+                                                                const int64_t* __restrict__ first,
+                                                                const uint64_t* __restrict__ moff,
+                                                                const int32_t* __restrict__ idx,
+                                                                const uint16_t* __restrict__ pos,
+                                                                const uint64_t* __restrict__ info,
+                                                                const uint64_t* __restrict__ M,
+                                                                unsigned long long* __restrict__ next,
+                                                                unsigned long long* __restrict__ stats) {
+    __shared__ __align__(16) uint64_t R[LW_CAP];
+    __shared__ int64_t s_item;
+    uint64_t found = 0, words = 0;
+    while (true) {
+        // every thread is done with the previous item's words here
+        if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(next, 1ull);
+        __syncthreads();
+        const int64_t it = s_item;
+        if (it >= n_items) break;
+        const uint64_t item = items[it];
+        const int64_t w = item_seg(item);
+        const uint64_t e0 = seg[w] + item_round(item) * (uint64_t)LW_PER;
+        const uint64_t e1 = e0 + LW_PER < seg[w + 1] ? e0 + LW_PER : seg[w + 1];
+        const uint64_t m_al = moff[first[w]] & ~1ull;   // M is 16-byte aligned
+        const uint64_t span = moff[first[w + 1]] - m_al;
+        if (span <= (uint64_t)LW_CAP) {
+            const int64_t np = (int64_t)(span / 2);
+            const ulonglong2* src = reinterpret_cast<const ulonglong2*>(M + m_al);
+            ulonglong2* dst = reinterpret_cast<ulonglong2*>(R);
+            // three 16-byte loads in flight per thread
+            for (int64_t k = threadIdx.x; k < np; k += 3 * LW_THREADS) {
+                const int64_t kb = k + LW_THREADS, kc = k + 2 * LW_THREADS;
+                const ulonglong2 va = src[k];
+                const ulonglong2 vb = kb < np ? src[kb] : va;
+                const ulonglong2 vc = kc < np ? src[kc] : va;
+                dst[k] = va;
+                if (kb < np) dst[kb] = vb;
+                if (kc < np) dst[kc] = vc;
+            }
+            if ((span & 1) && threadIdx.x == 0) R[span - 1] = M[m_al + span - 1];
+            __syncthreads();
+            last_count<true>(R, m_al, e0, e1, idx, pos, info, found, words);
+        } else {
+            // not reached for blocks laid out as above; kept for safety
+            last_count<false>(M + m_al, m_al, e0, e1, idx, pos, info, found, words);
+        }
     }
     found = wave_sum_u64(found);
     words = wave_sum_u64(words);
@@ -975,6 +1132,22 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     uint64_t* start = push<uint64_t>(ar, E + 1);
     fill_u32(cnt, E, 0, s);
     R.mwords = mwords;
+    // k = 4: windows of roots for the fused last level (first root of each)
+    int64_t nw = 0;
+    int64_t* wfirst = nullptr;
+    if (R.k == 4) {
+        wfirst = push<int64_t>(ar, n + 1);
+        const size_t mk = ar.mark();
+        uint32_t* mark = push<uint32_t>(ar, n);
+        uint64_t* woff = push<uint64_t>(ar, n + 1);
+        k_last_marks<<<grid_threads(n), 256, 0, s>>>(n, moff, mark);
+        PG_HIP(hipGetLastError());
+        scan_u32(mark, n, woff, ar, s);
+        k_last_first<<<grid_threads(n), 256, 0, s>>>(n, mark, woff, wfirst);
+        PG_HIP(hipGetLastError());
+        nw = (int64_t)read_u64(woff + n, s);
+        ar.reset(mk);
+    }
     {
         BmArgs A;
         const size_t mk = ar.mark();
@@ -1036,15 +1209,25 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
         if (c1 <= c0 || m2 == 0) continue;
         {
             ProfScope ps("clique_write", s, (double)m2);
-            k_clique_write_masks<<<grid_threads(c1 - c0), 256, 0, s>>>(c0, c1, info, M, start, hs[j], l2_idx, l2_pos,
+            k_clique_write_masks<<<grid_threads(c1 - c0), WR_THREADS, 0, s>>>(c0, c1, info, M, start, hs[j], l2_idx, l2_pos,
                                                                        R.stats);
             PG_HIP(hipGetLastError());
         }
         if (R.k == 4) {
-            ProfScope ps("clique_last", s, 0.0);
-            k_clique_last_masks<<<grid_threads((int64_t)m2), 256, 0, s>>>((int64_t)m2, l2_idx, l2_pos, info, M,
-                                                                          R.stats);
+            const size_t mk = ar.mark();
+            uint64_t* wseg = push<uint64_t>(ar, nw + 1);
+            k_last_segs<<<grid_threads(nw + 1), 256, 0, s>>>(nw, wfirst, rp, start, c0, c1, wseg);
             PG_HIP(hipGetLastError());
+            uint64_t* items = nullptr;
+            const int64_t n_items = round_items(wseg, 0, nw, LW_PER, ar, s, &items);
+            fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, s);
+            {
+                ProfScope ps("clique_last", s, 0.0);
+                k_clique_last_lds<<<(unsigned)(2 * device_info().n_cu), LW_THREADS, 0, s>>>(
+                    items, n_items, wseg, wfirst, moff, l2_idx, l2_pos, info, M, R.qctr, R.stats);
+                PG_HIP(hipGetLastError());
+            }
+            ar.reset(mk);
         } else {
             MaskCtx X{info, M};
             MaskChain ch{};
