@@ -440,10 +440,14 @@ struct BmArgs {
 // hits set bits of the LDS row.  Stops once the list passes s_last.
 // Returns the number of hits (wave-uniform).
 //
-// Every step issues its loads unconditionally (past the end of the list a
-// lane loads the last element and discards it; after the final step the
-// loads repeat the current one), so the number of loads in flight is known
-// at compile time and the search waits for its own step's data only.
+// A step is read through a buffer descriptor over its valid elements: the
+// address arithmetic is scalar, and lanes past the end read 0, which is
+// never in S (out(r) holds ranks above r, so its elements are at least 1).
+// Every step issues its loads (after the final step they repeat its first
+// element), so the number of loads in flight is known at compile time and
+// the search waits for its own step's data only.
+constexpr int BUF_WORD3 = 0x00020000;    // raw 32-bit buffer access, gfx9 family
+
 template <int LG>
 __device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left, const int32_t* S, int32_t x,
                                                  int32_t d, int32_t s_last, unsigned long long* row,
@@ -451,41 +455,44 @@ __device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left
     constexpr int STEP = WAVE * BM_UNROLL;
     uint32_t c = 0;
     int32_t ua[BM_UNROLL], ub[BM_UNROLL];
+    int32_t la = 0, lb = 0;   // valid elements of each buffer (wave-uniform)
     // lim >= 1 elements valid from p
     auto load = [&](int32_t (&u)[BM_UNROLL], const int32_t* p, int32_t lim) {
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(p), (short)0, lim * 4, BUF_WORD3);
 #pragma unroll
-        for (int q = 0; q < BM_UNROLL; ++q) {
-            const int32_t o = q * WAVE + lane();
-            const int32_t val = p[min(o, lim - 1)];
-            u[q] = o < lim ? val : 0x7fffffff;
-        }
+        for (int q = 0; q < BM_UNROLL; ++q)
+            u[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, (q * WAVE + lane()) * 4, 0, 0);
     };
-    // A step is sorted: once the first key of a row of 64 exceeds s_last,
-    // neither it nor any later key can hit, and those rows are not searched.
+    // A step is sorted: once the first key of a row of 64 exceeds s_last
+    // (or the row is past the list), no key of it or of a later row hits.
     static_assert(BM_UNROLL == 3, "the row cases below are written out for three rows");
-    auto search = [&](const int32_t (&u)[BM_UNROLL]) {
-        if (readlane(u[2], 0) <= s_last) c += search_keys<LG, 3>(S, x, d, u, row);
-        else if (readlane(u[1], 0) <= s_last) c += search_keys<LG, 2>(S, x, d, u, row);
-        else if (readlane(u[0], 0) <= s_last) c += search_keys<LG, 1>(S, x, d, u, row);
+    auto search = [&](const int32_t (&u)[BM_UNROLL], int32_t lim) {
+        auto live = [&](int q) { return q * WAVE < lim && readlane(u[q], 0) <= s_last; };
+        if (live(2)) c += search_keys<LG, 3>(S, x, d, u, row);
+        else if (live(1)) c += search_keys<LG, 2>(S, x, d, u, row);
+        else if (live(0)) c += search_keys<LG, 1>(S, x, d, u, row);
     };
     // the next step's loads: of cp + STEP if there is one, else of cp again
-    auto next = [&](int32_t (&u)[BM_UNROLL], bool more) {
-        load(u, more ? cp + STEP : cp, more ? (int32_t)min64(left - STEP, STEP) : 1);
+    auto next = [&](int32_t (&u)[BM_UNROLL], int32_t& lim, bool more) {
+        lim = more ? (int32_t)min64(left - STEP, STEP) : 1;
+        load(u, more ? cp + STEP : cp, lim);
     };
-    load(ua, cp, (int32_t)min64(left, STEP));
+    la = (int32_t)min64(left, STEP);
+    load(ua, cp, la);
     while (true) {
         // ua holds the current step; ub gets the next one
         bool more = left > STEP && readlane(ua[BM_UNROLL - 1], WAVE - 1) <= s_last;
-        next(ub, more);
-        search(ua);
+        next(ub, lb, more);
+        search(ua, la);
         streamed += (uint64_t)min64(left, STEP);
         if (!more) break;
         cp += STEP;
         left -= STEP;
         // ub holds the current step; ua gets the next one
         more = left > STEP && readlane(ub[BM_UNROLL - 1], WAVE - 1) <= s_last;
-        next(ua, more);
-        search(ub);
+        next(ua, la, more);
+        search(ub, lb);
         streamed += (uint64_t)min64(left, STEP);
         if (!more) break;
         cp += STEP;
