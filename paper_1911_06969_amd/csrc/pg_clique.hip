@@ -623,18 +623,29 @@ __global__ __launch_bounds__(WR_THREADS) void k_clique_write_masks(int64_t e_lo,
     uint64_t read = 0;   // info and row bytes of the entries with children
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    for (int64_t e0 = e_lo + wave_id * WAVE; e0 < e_hi; e0 += n_waves * WAVE) {
-        const int64_t e = e0 + lane();
-        uint64_t s0 = 0, s1 = 0;
-        if (e < e_hi) {
-            s0 = start[e] - start_base;
-            s1 = start[e + 1] - start_base;
-        }
+    // A batch's starts and row infos are loaded together (lanes past e_hi
+    // load the last entry's and drop them), one batch ahead: the next
+    // batch's loads fly while this one is compacted.
+    const int64_t stride = n_waves * WAVE;
+    uint64_t ns0 = 0, ns1 = 0, nf = 0;
+    auto meta = [&](int64_t b0) {
+        const int64_t e = b0 + lane();
+        const int64_t ec = e < e_hi ? e : e_hi - 1;
+        ns0 = start[ec];
+        ns1 = start[ec + 1];
+        nf = info[ec];
+        if (e >= e_hi) ns1 = ns0;
+    };
+    int64_t e0 = e_lo + wave_id * WAVE;
+    if (e0 < e_hi) meta(e0);
+    for (; e0 < e_hi; e0 += stride) {
+        const uint64_t s0 = ns0 - start_base, s1 = ns1 - start_base;
+        const uint64_t fcur = nf;
         const bool has = s1 > s0;
         int Wl = 0;
         uint64_t words[BM_W];
         {
-            const uint64_t f = has ? info[e] : 0;
+            const uint64_t f = has ? fcur : 0;
             Wl = info_w(f);
             const uint64_t* rowp = M + info_base(f) + (uint64_t)info_i(f) * Wl;
             // in 16-byte pairs (half the scattered load instructions)
@@ -652,6 +663,7 @@ __global__ __launch_bounds__(WR_THREADS) void k_clique_write_masks(int64_t e_lo,
             }
             if (has) read += 8u + 8u * (uint64_t)Wl;
         }
+        meta(e0 + stride < e_hi ? e0 + stride : e0);
         // lane 0's entry e0 < e_hi opens the wave's output range
         uint64_t out_at = readlane64(s0, 0);
         int fill = 0;   // children in the buffer (wave-uniform)
@@ -768,7 +780,7 @@ __global__ void k_last_segs(int64_t nw, const int64_t* __restrict__ first, const
 // Entries e0 + threadIdx.x, ... < e1 (e0 < e1), LW_B at a time per thread:
 // their loads are clamped into [e0, e1) and issued together, so a thread
 // waits for one round trip per LW_B entries.
-constexpr int LW_B = 8;
+constexpr int LW_B = 16;
 
 template <bool LDS>
 __device__ __forceinline__ void last_count(const uint64_t* base, uint64_t m_al, uint64_t e0, uint64_t e1,
