@@ -1171,7 +1171,7 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
         BmArgs A;
         const size_t mk = ar.mark();
         uint64_t* items = nullptr;
-        const int64_t n_items = round_items(rp, 0, n, WAVE, ar, s, &items);
+        const int64_t n_items = round_items(rp, 0, n, WAVE, ar, s, &items, E);
         fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, s);
         A.Q.next = R.qctr;
         A.Q.n_items = n_items;
@@ -1238,7 +1238,7 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
             k_last_segs<<<grid_threads(nw + 1), 256, 0, s>>>(nw, wfirst, rp, start, c0, c1, wseg);
             PG_HIP(hipGetLastError());
             uint64_t* items = nullptr;
-            const int64_t n_items = round_items(wseg, 0, nw, LW_PER, ar, s, &items);
+            const int64_t n_items = round_items(wseg, 0, nw, LW_PER, ar, s, &items, (int64_t)m2);
             fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, s);
             {
                 ProfScope ps("clique_last", s, 0.0);

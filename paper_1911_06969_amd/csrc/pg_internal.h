@@ -171,14 +171,16 @@ uint64_t read_u64(const uint64_t* dev, hipStream_t s);   // synchronous
 // Work items for load balance: segment p in [p_lo, p_lo + n_seg), whose
 // children are seg[p] .. seg[p+1] (any offset base), is cut into rounds of
 // `per` children; item = (p << ROUND_BITS) | round, in segment order.
-// Returns the number of items; the array comes from the arena.
+// Returns the number of items; the array comes from the arena.  A caller
+// that knows the children in all (total = seg[p_lo + n_seg] - seg[p_lo])
+// passes it: the array is then sized by a bound and filled in one pass.
 constexpr int ROUND_BITS = 24;
 __host__ __device__ inline int64_t item_seg(uint64_t it) { return (int64_t)(it >> ROUND_BITS); }
 __host__ __device__ inline int64_t item_round(uint64_t it) { return (int64_t)(it & ((1ull << ROUND_BITS) - 1)); }
 int64_t round_items(const int64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                    uint64_t** items);
+                    uint64_t** items, int64_t total = -1);
 int64_t round_items(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                    uint64_t** items);
+                    uint64_t** items, int64_t total = -1);
 
 // ------------------------------------------------------------- pipelines
 

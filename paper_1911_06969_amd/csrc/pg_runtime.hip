@@ -242,25 +242,44 @@ __global__ void k_round_counts(const T* __restrict__ seg, int64_t p_lo, int64_t 
 }
 
 __global__ void k_round_emit(int64_t p_lo, int64_t n_seg, const uint64_t* __restrict__ pos,
-                             uint64_t* __restrict__ items) {
+                             uint64_t* __restrict__ items, uint64_t cap) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_seg;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t b = pos[i], e = pos[i + 1];
+        const uint64_t b = pos[i], e = pos[i + 1] < cap ? pos[i + 1] : cap;
         const uint64_t p = (uint64_t)(p_lo + i) << ROUND_BITS;
         for (uint64_t k = b; k < e; ++k) items[k] = p | (k - b);
     }
 }
 
 template <class T>
-static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                                uint64_t** items) {
+static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int per, int64_t total, Arena& a,
+                                hipStream_t s, uint64_t** items) {
     *items = nullptr;
     if (n_seg <= 0) return 0;
     PG_REQUIRE((uint64_t)(p_lo + n_seg) < (1ull << (64 - ROUND_BITS)), PG_EOVERFLOW, "too many segments");
+    const unsigned blocks = (unsigned)std::min<int64_t>((n_seg + 255) / 256, 8192);
+    if (total >= 0) {
+        // sum of ceil(c / per) <= total / per + n_seg: the items go first,
+        // at that bound, and one pass fills them
+        const int64_t cap = total / per + n_seg + 1;
+        uint64_t* out = push<uint64_t>(a, cap);
+        const size_t mk = a.mark();
+        uint32_t* rounds = push<uint32_t>(a, n_seg);
+        uint64_t* pos = push<uint64_t>(a, n_seg + 1);
+        k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds);
+        PG_HIP(hipGetLastError());
+        scan_u32(rounds, n_seg, pos, a, s);
+        k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos, out, (uint64_t)cap);
+        PG_HIP(hipGetLastError());
+        const int64_t m = (int64_t)read_u64(pos + n_seg, s);
+        a.reset(mk);
+        PG_REQUIRE(m <= cap, PG_EOVERFLOW, "work items exceed their bound: segment sizes disagree with the total");
+        *items = out;
+        return m;
+    }
     const size_t mk = a.mark();
     uint32_t* rounds = push<uint32_t>(a, n_seg);
     uint64_t* pos = push<uint64_t>(a, n_seg + 1);
-    const unsigned blocks = (unsigned)std::min<int64_t>((n_seg + 255) / 256, 8192);
     k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds);
     PG_HIP(hipGetLastError());
     scan_u32(rounds, n_seg, pos, a, s);
@@ -274,7 +293,7 @@ static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int p
     k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds2);
     PG_HIP(hipGetLastError());
     scan_u32(rounds2, n_seg, pos2, a, s);
-    k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos2, out);
+    k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos2, out, (uint64_t)m);
     PG_HIP(hipGetLastError());
     a.reset(mk2);
     *items = out;
@@ -282,13 +301,13 @@ static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int p
 }
 
 int64_t round_items(const int64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                    uint64_t** items) {
-    return round_items_impl(seg, p_lo, n_seg, per, a, s, items);
+                    uint64_t** items, int64_t total) {
+    return round_items_impl(seg, p_lo, n_seg, per, total, a, s, items);
 }
 
 int64_t round_items(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                    uint64_t** items) {
-    return round_items_impl(seg, p_lo, n_seg, per, a, s, items);
+                    uint64_t** items, int64_t total) {
+    return round_items_impl(seg, p_lo, n_seg, per, total, a, s, items);
 }
 
 uint64_t read_u64(const uint64_t* dev, hipStream_t s) {
@@ -303,7 +322,9 @@ uint64_t read_u64(const uint64_t* dev, hipStream_t s) {
 // Three phases (inspection-execution's prefix sum, section 5.3):
 // per-tile sums, an exclusive scan of the tile sums (recursively), then a
 // per-tile exclusive scan offset by the tile's base.  A tile is 256 threads
-// x 8 consecutive items.
+// x 8 consecutive items.  With few tiles each block adds up the sums of the
+// tiles before it itself, and the scan takes two launches (one for a single
+// tile).
 
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
@@ -328,12 +349,23 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_sums(const Tin* __re
     }
 }
 
-template <class Tin>
+// LOCAL: the tile's base is the sum of sums[0, blockIdx.x), added up by
+// the block itself (for few tiles); else tile_base[blockIdx.x].
+template <class Tin, bool LOCAL>
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const Tin* __restrict__ in, int64_t m,
                                                              const uint64_t* __restrict__ tile_base,
                                                              uint64_t* __restrict__ out) {
     __shared__ uint64_t wave_tot[SCAN_THREADS / WAVE];
+    __shared__ uint64_t wave_pre[SCAN_THREADS / WAVE];
     const int64_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    const int w = threadIdx.x / WAVE;
+    uint64_t before = 0;
+    if (LOCAL) {
+        uint64_t acc = 0;
+        for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += SCAN_THREADS) acc += tile_base[i];
+        acc = wave_sum_u64(acc);
+        if (lane() == 0) wave_pre[w] = acc;
+    }
     uint64_t v[SCAN_ITEMS];
     uint64_t s = 0;
 #pragma unroll
@@ -348,10 +380,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const Tin* __restri
         uint64_t t = (uint64_t)__shfl_up((unsigned long long)inc, d, WAVE);
         if (lane() >= d) inc += t;
     }
-    const int w = threadIdx.x / WAVE;
     if (lane() == WAVE - 1) wave_tot[w] = inc;
     __syncthreads();
-    uint64_t before = tile_base[blockIdx.x];
+    if (LOCAL) {
+        for (int j = 0; j < SCAN_THREADS / WAVE; ++j) before += wave_pre[j];
+    } else {
+        before = tile_base[blockIdx.x];
+    }
     for (int j = 0; j < w; ++j) before += wave_tot[j];
     uint64_t run = before + inc - s;
 #pragma unroll
@@ -362,6 +397,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(const Tin* __restri
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_THREADS - 1) out[m] = run;
 }
 
+// tiles up to this many add up their own bases (two launches in all)
+constexpr int64_t SCAN_LOCAL_TILES = 2048;
+
 template <class Tin>
 static void scan_impl(const Tin* in, int64_t m, uint64_t* out, Arena& a, hipStream_t s) {
     if (m <= 0) {
@@ -371,17 +409,20 @@ static void scan_impl(const Tin* in, int64_t m, uint64_t* out, Arena& a, hipStre
     const int64_t tiles = (m + SCAN_TILE - 1) / SCAN_TILE;
     size_t mk = a.mark();
     uint64_t* sums = push<uint64_t>(a, tiles);
-    uint64_t* base = push<uint64_t>(a, tiles + 1);
-    {
+    if (tiles > 1) {
         ProfScope ps("scan", s, (double)m);
         k_scan_tile_sums<Tin><<<(unsigned)tiles, SCAN_THREADS, 0, s>>>(in, m, sums);
         PG_HIP(hipGetLastError());
     }
-    if (tiles == 1) fill_u64(base, 1, 0, s);
-    else scan_impl<uint64_t>(sums, tiles, base, a, s);
-    {
+    if (tiles <= SCAN_LOCAL_TILES) {
+        ProfScope ps("scan", s, tiles > 1 ? 0.0 : (double)m);
+        k_scan_tiles<Tin, true><<<(unsigned)tiles, SCAN_THREADS, 0, s>>>(in, m, sums, out);
+        PG_HIP(hipGetLastError());
+    } else {
+        uint64_t* base = push<uint64_t>(a, tiles + 1);
+        scan_impl<uint64_t>(sums, tiles, base, a, s);
         ProfScope ps("scan", s, 0.0);
-        k_scan_tiles<Tin><<<(unsigned)tiles, SCAN_THREADS, 0, s>>>(in, m, base, out);
+        k_scan_tiles<Tin, false><<<(unsigned)tiles, SCAN_THREADS, 0, s>>>(in, m, base, out);
         PG_HIP(hipGetLastError());
     }
     a.reset(mk);
