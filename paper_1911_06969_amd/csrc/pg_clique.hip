@@ -1126,6 +1126,57 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
     ar.reset(mk);
 }
 
+// The mask path's layout and schedule, built once per graph beside the DAG
+// (they depend on its out-degrees only): each root's first mask word, the
+// windows of roots for the fused last level, and the count pass's work
+// items (rounds of 64 level-1 entries).
+static void build_mask_plan(pg_graph* g) {
+    MaskPlan& P = g->dag.plan;
+    if (P.built) return;
+    const int64_t n = g->n;
+    const int64_t E = g->dag.n_edges;
+    const int64_t* rp = g->dag.rp.as<int64_t>();
+    hipStream_t s = g->stream;
+    // temporaries in an arena of their own (the call's arena grows by need),
+    // none released before the end: three uint32[n] counts (28 B per root
+    // with the two uint64[n+1] offset arrays), the items at their bound
+    // (round_items' bound), and the scans' tile sums
+    const int64_t cap = E / WAVE + n + 1;
+    Arena ar;
+    ar.buf.reserve(sizeof(uint64_t) * (size_t)(4 * (n + 1) + cap + 8 * ((n + 2047) / 2048)) + (size_t(1) << 20));
+    P.moff.reserve(sizeof(uint64_t) * (n + 1));
+    uint64_t* moff = P.moff.as<uint64_t>();
+    {
+        uint32_t* words = push<uint32_t>(ar, n);
+        k_mask_words<<<grid_threads(n), 256, 0, s>>>(n, rp, words);
+        PG_HIP(hipGetLastError());
+        scan_u32(words, n, moff, ar, s);
+    }
+    const int64_t words = (int64_t)read_u64(moff + n, s);
+    int64_t nw = 0;
+    {
+        uint32_t* mark = push<uint32_t>(ar, n);
+        uint64_t* woff = push<uint64_t>(ar, n + 1);
+        k_last_marks<<<grid_threads(n), 256, 0, s>>>(n, moff, mark);
+        PG_HIP(hipGetLastError());
+        scan_u32(mark, n, woff, ar, s);
+        nw = (int64_t)read_u64(woff + n, s);
+        P.wfirst.reserve(sizeof(int64_t) * (nw + 1));
+        k_last_first<<<grid_threads(n), 256, 0, s>>>(n, mark, woff, P.wfirst.as<int64_t>());
+        PG_HIP(hipGetLastError());
+    }
+    uint64_t* items = nullptr;
+    const int64_t m = round_items(rp, 0, n, WAVE, ar, s, &items, E);
+    P.item.reserve(sizeof(uint64_t) * std::max<int64_t>(m, 1));
+    if (m > 0)
+        PG_HIP(hipMemcpyAsync(P.item.as<uint64_t>(), items, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
+    PG_HIP(hipStreamSynchronize(s));
+    P.words = words;
+    P.windows = nw;
+    P.items = m;
+    P.built = true;
+}
+
 static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     hipStream_t s = R.s;
     Arena& ar = g->arena;
@@ -1134,17 +1185,10 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     const int64_t* rp = g->dag.rp.as<int64_t>();
     const int32_t* col = g->dag.col.as<int32_t>();
     PG_REQUIRE(E <= INT32_MAX, PG_EUNSUPPORTED, "level-2 parent indices are 32-bit: too many DAG edges");
-    // mask block offsets
-    uint64_t* moff = push<uint64_t>(ar, n + 1);
-    {
-        const size_t mk = ar.mark();
-        uint32_t* words = push<uint32_t>(ar, n);
-        k_mask_words<<<grid_threads(n), 256, 0, s>>>(n, rp, words);
-        PG_HIP(hipGetLastError());
-        scan_u32(words, n, moff, ar, s);
-        ar.reset(mk);
-    }
-    const uint64_t mwords = read_u64(moff + n, s);
+    build_mask_plan(g);
+    const MaskPlan& P = g->dag.plan;
+    const uint64_t* moff = P.moff.as<uint64_t>();
+    const uint64_t mwords = (uint64_t)P.words;
     uint64_t* M = push<uint64_t>(ar, std::max<uint64_t>(mwords, 1));
     uint32_t* cnt = push<uint32_t>(ar, E);
     uint64_t* info = push<uint64_t>(ar, E);
@@ -1152,26 +1196,12 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     fill_u32(cnt, E, 0, s);
     R.mwords = mwords;
     // k = 4: windows of roots for the fused last level (first root of each)
-    int64_t nw = 0;
-    int64_t* wfirst = nullptr;
-    if (R.k == 4) {
-        wfirst = push<int64_t>(ar, n + 1);
-        const size_t mk = ar.mark();
-        uint32_t* mark = push<uint32_t>(ar, n);
-        uint64_t* woff = push<uint64_t>(ar, n + 1);
-        k_last_marks<<<grid_threads(n), 256, 0, s>>>(n, moff, mark);
-        PG_HIP(hipGetLastError());
-        scan_u32(mark, n, woff, ar, s);
-        k_last_first<<<grid_threads(n), 256, 0, s>>>(n, mark, woff, wfirst);
-        PG_HIP(hipGetLastError());
-        nw = (int64_t)read_u64(woff + n, s);
-        ar.reset(mk);
-    }
+    const int64_t nw = P.windows;
+    const int64_t* wfirst = P.wfirst.as<int64_t>();
     {
         BmArgs A;
-        const size_t mk = ar.mark();
-        uint64_t* items = nullptr;
-        const int64_t n_items = round_items(rp, 0, n, WAVE, ar, s, &items, E);
+        const uint64_t* items = P.item.as<uint64_t>();
+        const int64_t n_items = P.items;
         fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, s);
         A.Q.next = R.qctr;
         A.Q.n_items = n_items;
@@ -1189,7 +1219,6 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
             k_clique_count_masks<<<R.blocks, CQ_THREADS, 0, s>>>(A);
             PG_HIP(hipGetLastError());
         }
-        ar.reset(mk);
     }
     scan_u32(cnt, E, start, ar, s);
     const uint64_t total = read_u64(start + E, s);

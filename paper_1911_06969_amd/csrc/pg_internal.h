@@ -108,6 +108,18 @@ const DeviceInfo& device_info();
 
 // --------------------------------------------------------------- graph
 
+// Layout and schedule of the 4-clique sibling-mask path.  They depend on
+// the DAG's out-degrees only, so they are built once, beside the DAG.
+struct MaskPlan {
+    bool built = false;
+    int64_t words = 0;       // mask words of all roots
+    int64_t items = 0;       // count-pass work items
+    int64_t windows = 0;     // windows of roots for the fused last level
+    DevBuf moff;             // uint64[n+1]: first mask word of each root
+    DevBuf item;             // uint64[items]: (root, round of 64 level-1 entries)
+    DevBuf wfirst;           // int64[windows+1]: first root of each window; wfirst[windows] = n
+};
+
 struct Dag {
     bool built = false;
     int64_t n_edges = 0;     // directed DAG edges (= undirected edges)
@@ -116,6 +128,7 @@ struct Dag {
     DevBuf rp;               // int64[n+1] over ranks
     DevBuf col;              // int32[n_edges], out-neighbours (ranks), ascending
     DevBuf src;              // int32[n_edges], source rank of every DAG edge (level-1 idx)
+    MaskPlan plan;
 };
 
 struct MotifL1 {
