@@ -812,7 +812,8 @@ __device__ __forceinline__ void last_count(const uint64_t* base, uint64_t m_al, 
     }
 }
 
-__global__ __launch_bounds__(LW_THREADS) void k_clique_last_lds(const uint64_t* __restrict__ items, int64_t n_items,
+__global__ __launch_bounds__(LW_THREADS) void k_clique_last_lds(const uint64_t* __restrict__ items,
+                                                                const unsigned long long* __restrict__ n_items_dev,
                                                                 const uint64_t* __restrict__ seg,
                                                                 const int64_t* __restrict__ first,
                                                                 const uint64_t* __restrict__ moff,
@@ -824,6 +825,7 @@ __global__ __launch_bounds__(LW_THREADS) void k_clique_last_lds(const uint64_t* 
                                                                 unsigned long long* __restrict__ stats) {
     __shared__ __align__(16) uint64_t R[LW_CAP];
     __shared__ int64_t s_item;
+    const int64_t n_items = (int64_t)*n_items_dev;
     uint64_t found = 0, words = 0;
     while (true) {
         // every thread is done with the previous item's words here
@@ -1177,6 +1179,7 @@ static void build_mask_plan(pg_graph* g) {
     P.built = true;
 }
 
+// Returns the number of level-2 entries (the last level's inputs for k = 4).
 static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     hipStream_t s = R.s;
     Arena& ar = g->arena;
@@ -1266,13 +1269,14 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
             uint64_t* wseg = push<uint64_t>(ar, nw + 1);
             k_last_segs<<<grid_threads(nw + 1), 256, 0, s>>>(nw, wfirst, rp, start, c0, c1, wseg);
             PG_HIP(hipGetLastError());
+            // the item count stays on the device (stats[7]): no round trip
             uint64_t* items = nullptr;
-            const int64_t n_items = round_items(wseg, 0, nw, LW_PER, ar, s, &items, (int64_t)m2);
+            round_items(wseg, 0, nw, LW_PER, ar, s, &items, (int64_t)m2, reinterpret_cast<uint64_t*>(R.stats + 7));
             fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, s);
             {
                 ProfScope ps("clique_last", s, 0.0);
                 k_clique_last_lds<<<(unsigned)(2 * device_info().n_cu), LW_THREADS, 0, s>>>(
-                    items, n_items, wseg, wfirst, moff, l2_idx, l2_pos, info, M, R.qctr, R.stats);
+                    items, R.stats + 7, wseg, wfirst, moff, l2_idx, l2_pos, info, M, R.qctr, R.stats);
                 PG_HIP(hipGetLastError());
             }
             ar.reset(mk);
@@ -1284,11 +1288,8 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
             mask_levels(R, X, 2, ch, start, hs[j], c0, c1, (int64_t)m2);
         }
     }
-    // input entries of the last level
-    const uint64_t n2 = total;
-    PG_HIP(hipMemcpyAsync(R.stats + 1, &n2, sizeof(n2), hipMemcpyHostToDevice, s));
-    PG_HIP(hipStreamSynchronize(s));
-    return 0;
+    // input entries of the last level (the level-2 entries)
+    return total;
 }
 
 uint64_t count_cliques(pg_graph* g, int k) {
@@ -1310,8 +1311,9 @@ uint64_t count_cliques(pg_graph* g, int k) {
     R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
     fill_u64(small, 8, 0, s);
     const bool masks = k >= 4 && g->dag.max_out <= BM_MAXD && !g->force_generic;
+    uint64_t n2 = 0;
     if (masks) {
-        count_cliques4_masks(g, R);
+        n2 = count_cliques4_masks(g, R);
     } else {
         // level L1: entries = DAG edges, parents = vertices (segment = out-list)
         extend_level(R, 1, g->dag.rp.as<int64_t>(), 0, 0, g->n, g->dag.col.as<int32_t>(), 0, g->dag.n_edges);
@@ -1319,6 +1321,7 @@ uint64_t count_cliques(pg_graph* g, int k) {
     uint64_t st[5] = {0, 0, 0, 0, 0};
     PG_HIP(hipMemcpyAsync(st, small, sizeof(st), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
+    if (masks) st[1] = n2;
     if (prof_on()) {
         // algorithmic bytes of one call, per kernel
         const double E = (double)g->dag.n_edges;

@@ -187,13 +187,15 @@ uint64_t read_u64(const uint64_t* dev, hipStream_t s);   // synchronous
 // Returns the number of items; the array comes from the arena.  A caller
 // that knows the children in all (total = seg[p_lo + n_seg] - seg[p_lo])
 // passes it: the array is then sized by a bound and filled in one pass.
+// With count_dev as well, the number of items is written there (on the
+// stream) instead of being read back, and the bound is returned.
 constexpr int ROUND_BITS = 24;
 __host__ __device__ inline int64_t item_seg(uint64_t it) { return (int64_t)(it >> ROUND_BITS); }
 __host__ __device__ inline int64_t item_round(uint64_t it) { return (int64_t)(it & ((1ull << ROUND_BITS) - 1)); }
 int64_t round_items(const int64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                    uint64_t** items, int64_t total = -1);
+                    uint64_t** items, int64_t total = -1, uint64_t* count_dev = nullptr);
 int64_t round_items(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                    uint64_t** items, int64_t total = -1);
+                    uint64_t** items, int64_t total = -1, uint64_t* count_dev = nullptr);
 
 // ------------------------------------------------------------- pipelines
 

@@ -242,7 +242,8 @@ __global__ void k_round_counts(const T* __restrict__ seg, int64_t p_lo, int64_t 
 }
 
 __global__ void k_round_emit(int64_t p_lo, int64_t n_seg, const uint64_t* __restrict__ pos,
-                             uint64_t* __restrict__ items, uint64_t cap) {
+                             uint64_t* __restrict__ items, uint64_t cap, uint64_t* __restrict__ count_dev) {
+    if (count_dev && blockIdx.x == 0 && threadIdx.x == 0) *count_dev = pos[n_seg] < cap ? pos[n_seg] : cap;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_seg;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t b = pos[i], e = pos[i + 1] < cap ? pos[i + 1] : cap;
@@ -253,9 +254,12 @@ __global__ void k_round_emit(int64_t p_lo, int64_t n_seg, const uint64_t* __rest
 
 template <class T>
 static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int per, int64_t total, Arena& a,
-                                hipStream_t s, uint64_t** items) {
+                                hipStream_t s, uint64_t** items, uint64_t* count_dev) {
     *items = nullptr;
-    if (n_seg <= 0) return 0;
+    if (n_seg <= 0) {
+        if (count_dev) fill_u64(count_dev, 1, 0, s);
+        return 0;
+    }
     PG_REQUIRE((uint64_t)(p_lo + n_seg) < (1ull << (64 - ROUND_BITS)), PG_EOVERFLOW, "too many segments");
     const unsigned blocks = (unsigned)std::min<int64_t>((n_seg + 255) / 256, 8192);
     if (total >= 0) {
@@ -269,8 +273,13 @@ static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int p
         k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds);
         PG_HIP(hipGetLastError());
         scan_u32(rounds, n_seg, pos, a, s);
-        k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos, out, (uint64_t)cap);
+        k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos, out, (uint64_t)cap, count_dev);
         PG_HIP(hipGetLastError());
+        if (count_dev) {
+            a.reset(mk);
+            *items = out;
+            return cap;
+        }
         const int64_t m = (int64_t)read_u64(pos + n_seg, s);
         a.reset(mk);
         PG_REQUIRE(m <= cap, PG_EOVERFLOW, "work items exceed their bound: segment sizes disagree with the total");
@@ -293,7 +302,7 @@ static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int p
     k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds2);
     PG_HIP(hipGetLastError());
     scan_u32(rounds2, n_seg, pos2, a, s);
-    k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos2, out, (uint64_t)m);
+    k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos2, out, (uint64_t)m, count_dev);
     PG_HIP(hipGetLastError());
     a.reset(mk2);
     *items = out;
@@ -301,13 +310,13 @@ static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int p
 }
 
 int64_t round_items(const int64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                    uint64_t** items, int64_t total) {
-    return round_items_impl(seg, p_lo, n_seg, per, total, a, s, items);
+                    uint64_t** items, int64_t total, uint64_t* count_dev) {
+    return round_items_impl(seg, p_lo, n_seg, per, total, a, s, items, count_dev);
 }
 
 int64_t round_items(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
-                    uint64_t** items, int64_t total) {
-    return round_items_impl(seg, p_lo, n_seg, per, total, a, s, items);
+                    uint64_t** items, int64_t total, uint64_t* count_dev) {
+    return round_items_impl(seg, p_lo, n_seg, per, total, a, s, items, count_dev);
 }
 
 uint64_t read_u64(const uint64_t* dev, hipStream_t s) {
