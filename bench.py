@@ -1,6 +1,7 @@
 """Benchmark: k-clique counting on the R-MAT scale-21 graph (one GPU).
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload clique4]
+python bench.py --workload rmat-sweep [--sweep-scales 20,21,22,23,24,25]
 
 One step = one pass of the clique hot path over the resident graph:
 pg_count_cliques(g, 4) = level-1 count pass, scan, write of the triangle
@@ -8,7 +9,9 @@ level, and the fused last level.  The graph and its degree-ordered DAG are
 device resident before timing starts (preprocessing and host-to-device
 copies are excluded, as in the paper's evaluation).
 
-Prints one JSON line.  `roofline` is for the dominant kernel (the one
+Prints one JSON line.  `preprocess` gives the graph load and the first call
+(which also builds the DAG), both outside the timed steps.  `roofline` is for
+the dominant kernel (the one
 with the most time per step among the kernels that record their algorithmic
 bytes), from HIP events recorded around every launch during the timed
 steps; `cpu_baseline` times the CPU oracle on a bounded sample of the same
@@ -39,9 +42,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="clique4", choices=["clique4", "clique5", "motif4", "motif3", "tc", "fsm", "copy", "tune-batch"],
+    ap.add_argument("--workload", default="clique4",
+                    choices=["clique4", "clique5", "motif4", "motif3", "tc", "fsm", "copy", "tune-batch", "rmat-sweep"],
                     help="copy: a plain 1 GiB device-to-device copy, the known-size reference "
-                         "for scaling HBM counters")
+                         "for scaling HBM counters; rmat-sweep: triangles and 4-cliques on R-MAT "
+                         "graphs of 2^20 .. 2^25 vertices, average degree 20 (weak scaling)")
+    ap.add_argument("--sweep-scales", default="20,21,22,23,24,25")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 4-motif, batched and served measurements")
@@ -155,6 +161,9 @@ def main():
         tune.save(out, best, table, "sample: 20,000 of the 100,000 graphs of the motif batch (seed 9)")
         print(json.dumps({"best": best}), flush=True)
         return
+    if w == "rmat-sweep":
+        rmat_sweep(args, binding, synth, stream)
+        return
     if w == "fsm":
         g = synth.fsm_er()
         run = lambda G: G.fsm(3, 1000)[1]  # noqa: E731
@@ -186,11 +195,24 @@ def main():
                                 f"undirected int32 CSR, seed 3", "k": k, "vertices": g.n, "edges": g.n_edges}
 
     note("workload", w, "graph ready:", g.n, "vertices")
-    G = binding.Graph.from_csr(g, stream=stream)
-    result = None
-    for _ in range(args.warmup):
-        result = run(G)
+    # preprocessing, excluded from the timed steps and reported beside them:
+    # the load (host-to-device copy, validation) and the first call, which
+    # also builds the degree-ordered DAG (and, for cliques, the mask plan)
     torch.cuda.synchronize()
+    t_load = time.perf_counter()
+    G = binding.Graph.from_csr(g, stream=stream)
+    torch.cuda.synchronize()
+    t_first = time.perf_counter()
+    result = None
+    for i in range(args.warmup):
+        result = run(G)
+        if i == 0:
+            torch.cuda.synchronize()
+            t_first_end = time.perf_counter()
+    torch.cuda.synchronize()
+    preprocess = {"load_ms": round(1000 * (t_first - t_load), 2)}
+    if args.warmup > 0:
+        preprocess["first_call_ms"] = round(1000 * (t_first_end - t_first), 2)
     note("warm-up done")
 
     binding.pg_profile_reset()
@@ -276,10 +298,45 @@ def main():
         "result": found if isinstance(result, int) else [int(x) for x in result],
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "preprocess": preprocess,
         "kernels": kernels,
         "secondary": secondary or None,
     }
     print(json.dumps(line), flush=True)
+
+
+def rmat_sweep(args, binding, synth, stream):
+    """Weak scaling as in the paper's R-MAT experiment: graphs of 2^s vertices
+    and average degree 20 (edge factor 10, a=0.57 b=0.19 c=0.19, seed 7), and
+    per graph the time of one triangle count and one 4-clique count after a
+    warm-up call, normalised to the smallest graph."""
+    import torch
+    rows = []
+    for sc in [int(x) for x in args.sweep_scales.split(",") if x]:
+        t0 = time.perf_counter()
+        g = synth.rmat(sc, 10, seed=7)
+        note(f"scale {sc}: {g.n} vertices, {g.n_edges} edges, generated in {time.perf_counter() - t0:.1f} s")
+        row = {"scale": sc, "vertices": g.n, "edges": g.n_edges}
+        with binding.Graph.from_csr(g, stream=stream) as G:
+            for k, key in ((3, "tc"), (4, "cf4")):
+                G.cliques(k)   # warm-up (builds the DAG on the first call)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                c = G.cliques(k)
+                torch.cuda.synchronize()
+                ms = 1000 * (time.perf_counter() - t)
+                row[key + "_ms"] = round(ms, 3)
+                row[key + "_count"] = int(c)
+                note(f"scale {sc}: {k}-cliques {c} in {ms:.1f} ms")
+        rows.append(row)
+        del g
+    base = rows[0] if rows else None
+    for r in rows:
+        for key in ("tc", "cf4"):
+            r[key + "_vs_first"] = round(r[key + "_ms"] / base[key + "_ms"], 3) if base[key + "_ms"] > 0 else None
+    print(json.dumps({"workload": "R-MAT weak-scaling sweep: triangles and 4-cliques, edge factor 10 "
+                                  "(average degree 20), a=0.57 b=0.19 c=0.19, seed 7",
+                      "data": "synthetic (seeded R-MAT)", "rows": rows}), flush=True)
 
 
 def measure_motif4(steps: int = 2):

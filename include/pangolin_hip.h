@@ -94,10 +94,11 @@ int pg_set_memory_budget(pg_graph* g, uint64_t bytes);
 
 /*
  * Per-graph switches.
- *   PG_OPT_CLIQUE_MASKS  1 (default): 4-cliques on graphs whose DAG
- *                        out-degree is at most 768 record each level-1
- *                        entry's children as a bitmask over its root's
- *                        out-list and count the last level with popcounts;
+ *   PG_OPT_CLIQUE_MASKS  1 (default): k-cliques with k >= 3 on graphs
+ *                        whose DAG out-degree is at most 768 record each
+ *                        level-1 entry's children (its triangles) as a
+ *                        bitmask over its root's out-list; k = 3 is their
+ *                        number, and deeper levels count with popcounts;
  *                        0: the general level kernels for every k.
  * Unknown options return PG_EINVAL.
  */

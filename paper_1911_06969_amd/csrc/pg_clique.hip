@@ -1013,10 +1013,28 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
     }
 }
 
-__global__ void k_mask_words(int64_t n, const int64_t* __restrict__ rp, uint32_t* __restrict__ words) {
+// Per root: its mask words and its out-degree split by whether the root is
+// light (out-degree at most BM_MAXD: sibling masks) or heavy (the general
+// level kernels).
+__global__ void k_mask_words(int64_t n, const int64_t* __restrict__ rp, uint32_t* __restrict__ words,
+                             uint32_t* __restrict__ light, uint32_t* __restrict__ heavy) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t d = rp[r + 1] - rp[r];
-        words[r] = (uint32_t)(d * ((d + 63) >> 6));
+        const bool lt = d <= BM_MAXD;
+        words[r] = lt ? (uint32_t)(d * ((d + 63) >> 6)) : 0u;
+        light[r] = lt ? (uint32_t)d : 0u;
+        heavy[r] = lt ? 0u : (uint32_t)d;
+    }
+}
+
+// The heavy roots' out-lists, packed: hcol[hrp[r] ..) = col[rp[r] ..) when
+// root r is heavy (hrp[r + 1] > hrp[r]).  One wave per root.
+__global__ void k_heavy_lists(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                              const uint64_t* __restrict__ hrp, int32_t* __restrict__ hcol) {
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; r < n; r += n_waves) {
+        const int64_t len = (int64_t)(hrp[r + 1] - hrp[r]);
+        for (int64_t k = lane(); k < len; k += WAVE) hcol[hrp[r] + k] = col[rp[r] + k];
     }
 }
 
@@ -1129,9 +1147,10 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
 }
 
 // The mask path's layout and schedule, built once per graph beside the DAG
-// (they depend on its out-degrees only): each root's first mask word, the
-// windows of roots for the fused last level, and the count pass's work
-// items (rounds of 64 level-1 entries).
+// (they depend on its out-degrees only): each light root's first mask
+// word, the windows of roots for the fused last level, the count pass's
+// work items (rounds of 64 level-1 entries of light roots), and the heavy
+// roots' out-lists as a CSR of their own for the general kernels.
 static void build_mask_plan(pg_graph* g) {
     MaskPlan& P = g->dag.plan;
     if (P.built) return;
@@ -1140,21 +1159,35 @@ static void build_mask_plan(pg_graph* g) {
     const int64_t* rp = g->dag.rp.as<int64_t>();
     hipStream_t s = g->stream;
     // temporaries in an arena of their own (the call's arena grows by need),
-    // none released before the end: three uint32[n] counts (28 B per root
-    // with the two uint64[n+1] offset arrays), the items at their bound
+    // none released before the end: four uint32[n] arrays and three
+    // uint64[n+1] offset arrays (40 B per root), the items at their bound
     // (round_items' bound), and the scans' tile sums
     const int64_t cap = E / WAVE + n + 1;
     Arena ar;
-    ar.buf.reserve(sizeof(uint64_t) * (size_t)(4 * (n + 1) + cap + 8 * ((n + 2047) / 2048)) + (size_t(1) << 20));
+    ar.buf.reserve(sizeof(uint64_t) * (size_t)(6 * (n + 1) + cap + 16 * ((n + 2047) / 2048)) + (size_t(1) << 20));
     P.moff.reserve(sizeof(uint64_t) * (n + 1));
     uint64_t* moff = P.moff.as<uint64_t>();
+    uint64_t* lseg = push<uint64_t>(ar, n + 1);
+    P.hrp.reserve(sizeof(uint64_t) * (n + 1));
+    uint64_t* hrp = P.hrp.as<uint64_t>();
     {
         uint32_t* words = push<uint32_t>(ar, n);
-        k_mask_words<<<grid_threads(n), 256, 0, s>>>(n, rp, words);
+        uint32_t* light = push<uint32_t>(ar, n);
+        uint32_t* heavy = push<uint32_t>(ar, n);
+        k_mask_words<<<grid_threads(n), 256, 0, s>>>(n, rp, words, light, heavy);
         PG_HIP(hipGetLastError());
         scan_u32(words, n, moff, ar, s);
+        scan_u32(light, n, lseg, ar, s);
+        scan_u32(heavy, n, hrp, ar, s);
     }
     const int64_t words = (int64_t)read_u64(moff + n, s);
+    const int64_t e_heavy = (int64_t)read_u64(hrp + n, s);
+    P.hcol.reserve(sizeof(int32_t) * (size_t)std::max<int64_t>(e_heavy, 1));
+    if (e_heavy > 0) {
+        k_heavy_lists<<<grid_threads(n * WAVE), 256, 0, s>>>(n, rp, g->dag.col.as<int32_t>(), hrp,
+                                                             P.hcol.as<int32_t>());
+        PG_HIP(hipGetLastError());
+    }
     int64_t nw = 0;
     {
         uint32_t* mark = push<uint32_t>(ar, n);
@@ -1168,7 +1201,7 @@ static void build_mask_plan(pg_graph* g) {
         PG_HIP(hipGetLastError());
     }
     uint64_t* items = nullptr;
-    const int64_t m = round_items(rp, 0, n, WAVE, ar, s, &items, E);
+    const int64_t m = round_items(lseg, 0, n, WAVE, ar, s, &items, E - e_heavy);
     P.item.reserve(sizeof(uint64_t) * std::max<int64_t>(m, 1));
     if (m > 0)
         PG_HIP(hipMemcpyAsync(P.item.as<uint64_t>(), items, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
@@ -1176,10 +1209,13 @@ static void build_mask_plan(pg_graph* g) {
     P.words = words;
     P.windows = nw;
     P.items = m;
+    P.heavy_edges = e_heavy;
     P.built = true;
 }
 
-// Returns the number of level-2 entries (the last level's inputs for k = 4).
+// Returns the number of level-2 entries: the triangles, which are the
+// count for k = 3 (the count pass alone) and the last level's inputs for
+// k = 4.
 static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     hipStream_t s = R.s;
     Arena& ar = g->arena;
@@ -1225,7 +1261,8 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     }
     scan_u32(cnt, E, start, ar, s);
     const uint64_t total = read_u64(start + E, s);
-    if (total == 0) return 0;
+    // level 2 holds the triangles (r, S[i], S[j]), i < j, each once
+    if (total == 0 || R.k == 3) return total;
     // edge blocking over level-1 entries: 6 bytes per level-2 entry, and
     // for k >= 5 its child count and offset (12 B) plus room for a chunk of
     // the next level
@@ -1310,9 +1347,20 @@ uint64_t count_cliques(pg_graph* g, int k) {
     R.stats = reinterpret_cast<unsigned long long*>(small);
     R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
     fill_u64(small, 8, 0, s);
-    const bool masks = k >= 4 && g->dag.max_out <= BM_MAXD && !g->force_generic;
+    const bool masks = k >= 3 && !g->force_generic;
     uint64_t n2 = 0;
     if (masks) {
+        // every clique is counted at its lowest vertex (its root): roots of
+        // out-degree above BM_MAXD through the general kernels, over the
+        // CSR of their out-lists, the others through the sibling masks
+        build_mask_plan(g);
+        const MaskPlan& P = g->dag.plan;
+        if (P.heavy_edges > 0) {
+            const size_t mk = ar.mark();
+            extend_level(R, 1, reinterpret_cast<const int64_t*>(P.hrp.as<uint64_t>()), 0, 0, g->n,
+                         P.hcol.as<int32_t>(), 0, P.heavy_edges);
+            ar.reset(mk);
+        }
         n2 = count_cliques4_masks(g, R);
     } else {
         // level L1: entries = DAG edges, parents = vertices (segment = out-list)
@@ -1336,12 +1384,14 @@ uint64_t count_cliques(pg_graph* g, int k) {
             ProfScope pc("clique_count_work", s, 32.0 * E + 8.0 * (double)R.mwords + 4.0 * (double)st[3]);
             // write pass: a start pair per level-1 entry, info and row of
             // every entry with children, 6 B per level-2 entry written
-            ProfScope pw("clique_write_work", s, 16.0 * E + (double)st[4] + 6.0 * (double)st[1]);
+            if (k >= 4) ProfScope pw("clique_write_work", s, 16.0 * E + (double)st[4] + 6.0 * (double)st[1]);
             if (k == 4)   // last level: 6 B SoA + 8 B info per entry, 16 B per pair of row words
                 ProfScope pl("clique_last_work", s, 14.0 * (double)st[1] + 16.0 * (double)st[2]);
         }
     }
-    return st[0];
+    // k = 3 on the mask path: the light roots' triangles are the level-2
+    // entries; the heavy roots' are in st[0]
+    return (masks && k == 3 ? n2 : 0) + st[0];
 }
 
 }  // namespace pg

@@ -110,14 +110,19 @@ const DeviceInfo& device_info();
 
 // Layout and schedule of the 4-clique sibling-mask path.  They depend on
 // the DAG's out-degrees only, so they are built once, beside the DAG.
+// Roots whose out-degree exceeds the masks' limit (heavy roots) go through
+// the general level kernels, over a CSR of their out-lists alone.
 struct MaskPlan {
     bool built = false;
-    int64_t words = 0;       // mask words of all roots
+    int64_t words = 0;       // mask words of all light roots
     int64_t items = 0;       // count-pass work items
     int64_t windows = 0;     // windows of roots for the fused last level
-    DevBuf moff;             // uint64[n+1]: first mask word of each root
-    DevBuf item;             // uint64[items]: (root, round of 64 level-1 entries)
+    int64_t heavy_edges = 0; // DAG edges of heavy roots
+    DevBuf moff;             // uint64[n+1]: first mask word of each root (heavy roots: none)
+    DevBuf item;             // uint64[items]: (light root, round of 64 level-1 entries)
     DevBuf wfirst;           // int64[windows+1]: first root of each window; wfirst[windows] = n
+    DevBuf hrp;              // uint64[n+1]: heavy roots' out-lists in hcol (empty for light roots)
+    DevBuf hcol;             // int32[heavy_edges]
 };
 
 struct Dag {
@@ -155,7 +160,7 @@ struct pg_graph {
     pg::Dag dag;
     pg::MotifL1 ml1;
     uint64_t budget = 0;     // bytes for materialised levels
-    bool force_generic = false;   // 4-cliques: skip the sibling-mask path
+    bool force_generic = false;   // cliques: skip the sibling-mask path
     pg::Arena arena;
 };
 

@@ -42,11 +42,24 @@ def test_complete_graphs(torch):
 def test_mask_row_width_limit(torch):
     """K_769: the lowest-ranked vertex has DAG out-degree 768, the most the
     sibling masks take (12-word rows, the deepest search of the count pass);
-    K_770 (out-degree 769) goes to the general kernels.  K_130 takes 3-word
-    rows through the deeper mask levels.  Every count against C(n, k)."""
+    in K_770 that vertex (out-degree 769) is a heavy root, counted by the
+    general kernels, and the rest by the masks.  K_130 takes 3-word rows
+    through the deeper mask levels.  Every count against C(n, k)."""
     for n, ks in ((769, (3, 4)), (770, (3, 4)), (130, (3, 4, 5, 6))):
         say("K", n)
         assert gpu_cliques(synth.complete(n), ks) == [comb(n, k) for k in ks]
+
+
+def test_heavy_and_light_roots(torch):
+    """K_780 beside an R-MAT graph: the 12 lowest-ranked vertices of K_780
+    have DAG out-degrees 779 .. 768, so 11 roots are heavy (general
+    kernels) and all others light (sibling masks); the counts add up."""
+    k_part = synth.complete(780)
+    r_part = synth.rmat(11, 16, seed=8)
+    g = synth.disjoint_union(k_part, r_part)
+    ks = (3, 4)
+    want = [comb(780, k) + oracle.clique_count(r_part, k) for k in ks]
+    assert gpu_cliques(g, ks) == want
 
 
 def test_empty_and_edge_cases(torch):
