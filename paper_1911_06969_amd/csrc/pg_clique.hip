@@ -36,12 +36,14 @@ namespace pg {
 constexpr int CQ_THREADS = 256;
 constexpr int CQ_WAVES = CQ_THREADS / WAVE;
 constexpr int CQ_SMAX = 1024;          // sibling lists up to this length live in LDS
+constexpr int CQ_ROUND = 256;          // entries of a segment per work item (long segments spread over waves)
 constexpr int CQ_TRIM_MIN = 48;        // out-lists at least this long are trimmed to max(S)
 
 enum { MODE_COUNT = 0, MODE_WRITE = 1, MODE_LAST = 2 };
 
 struct CliqueArgs {
-    XcdQueue Q;                         // items: parent segments [p_lo, p_lo + n_items)
+    XcdQueue Q;                         // over items[], or parent segments [p_lo, p_lo + n_items) if null
+    const uint64_t* items;              // (parent, round of CQ_ROUND entries of its segment)
     int64_t p_lo;
     const int64_t* seg;                 // seg[p] - seg_base = first entry of segment p
     int64_t seg_base;
@@ -71,10 +73,10 @@ struct CliqueAcc {
 // (LDS or global; the pointer's address space is known after inlining).
 template <int MODE, class SPtr>
 __device__ __forceinline__ void clique_segment(const CliqueArgs& A, CliqueLds& L, int w, SPtr S, int32_t s,
-                                               int64_t b, CliqueAcc& acc) {
+                                               int64_t b, int32_t r0, int32_t r1, CliqueAcc& acc) {
     const int32_t s_last = S[s - 1];
-    const int32_t x0 = (int32_t)max64(0, A.x_lo - b);
-    const int32_t x1 = (int32_t)min64(s, A.x_hi - b);
+    const int32_t x0 = (int32_t)max64(r0, A.x_lo - b);
+    const int32_t x1 = (int32_t)min64(min(s, r1), A.x_hi - b);
     for (int32_t xc = x0; xc < x1; xc += WAVE) {
         const int32_t x = xc + lane();
         int64_t lo = 0;
@@ -162,7 +164,15 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_ext(CliqueArgs A) {
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
-        for (int64_t p = A.p_lo + it; p < A.p_lo + it_end; ++p) {
+        for (int64_t j = it; j < it_end; ++j) {
+            int64_t p = A.p_lo + j;
+            int32_t r0 = 0, r1 = 0x7fffffff;
+            if (A.items) {
+                const uint64_t item = (uint64_t)uniform64((int64_t)A.items[j]);
+                p = item_seg(item);
+                r0 = (int32_t)item_round(item) * CQ_ROUND;
+                r1 = r0 + CQ_ROUND;
+            }
             const int64_t b = A.seg[p] - A.seg_base;
             const int64_t e = A.seg[p + 1] - A.seg_base;
             const int32_t s = (int32_t)(e - b);
@@ -170,9 +180,9 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_ext(CliqueArgs A) {
             if (s <= CQ_SMAX) {
                 for (int i = lane(); i < s; i += WAVE) L.S[w][i] = A.vid[b + i];
                 wave_sync();
-                clique_segment<MODE>(A, L, w, &L.S[w][0], s, b, acc);
+                clique_segment<MODE>(A, L, w, &L.S[w][0], s, b, r0, r1, acc);
             } else {
-                clique_segment<MODE>(A, L, w, A.vid + b, s, b, acc);
+                clique_segment<MODE>(A, L, w, A.vid + b, s, b, r0, r1, acc);
             }
             wave_sync();
         }
@@ -230,20 +240,37 @@ struct CliqueRun {
     int64_t waves;
     int blocks;
     uint64_t mwords = 0;        // mask path: words of all mask rows
+    bool long_segments = false; // general path: segments may exceed CQ_ROUND entries
 };
 
+// Work items are parent segments, or rounds of CQ_ROUND entries of them
+// when some segment is longer than a round (a segment's entries are then
+// spread over several waves).
 template <int MODE>
 static void launch(CliqueRun& R, CliqueArgs A, int64_t p_lo, int64_t n_seg, const char* name, double units) {
     if (n_seg <= 0) return;
-    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, R.s);
-    A.Q.next = R.qctr;
-    A.Q.n_items = n_seg;
-    A.Q.chunk = n_seg >= R.waves * 64 ? 16 : (n_seg >= R.waves * 8 ? 4 : 1);
-    A.p_lo = p_lo;
-    A.stats = R.stats;
-    ProfScope ps(name, R.s, units);
-    k_clique_ext<MODE><<<R.blocks, CQ_THREADS, 0, R.s>>>(A);
-    PG_HIP(hipGetLastError());
+    Arena& ar = R.g->arena;
+    const size_t mk = ar.mark();
+    int64_t n_items = n_seg;
+    A.items = nullptr;
+    if (R.long_segments) {
+        uint64_t* items = nullptr;
+        n_items = round_items(A.seg, p_lo, n_seg, CQ_ROUND, ar, R.s, &items);
+        A.items = items;
+        p_lo = 0;
+    }
+    if (n_items > 0) {
+        fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, R.s);
+        A.Q.next = R.qctr;
+        A.Q.n_items = n_items;
+        A.Q.chunk = n_items >= R.waves * 64 ? 16 : (n_items >= R.waves * 8 ? 4 : 1);
+        A.p_lo = p_lo;
+        A.stats = R.stats;
+        ProfScope ps(name, R.s, units);
+        k_clique_ext<MODE><<<R.blocks, CQ_THREADS, 0, R.s>>>(A);
+        PG_HIP(hipGetLastError());
+    }
+    ar.reset(mk);
 }
 
 // Extends the entries [x_lo, x_hi) of level `lev` (segments [p_lo, p_hi) of
@@ -1343,6 +1370,7 @@ uint64_t count_cliques(pg_graph* g, int k) {
     R.s = s;
     R.waves = grid_waves(32);
     R.blocks = (int)(R.waves / CQ_WAVES);
+    R.long_segments = g->dag.max_out > CQ_ROUND;
     uint64_t* small = push<uint64_t>(ar, 8 + Q_WORDS);
     R.stats = reinterpret_cast<unsigned long long*>(small);
     R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
