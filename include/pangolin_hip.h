@@ -119,6 +119,25 @@ int pg_graph_set_option(pg_graph* g, int option, int64_t value);
 int pg_count_cliques(pg_graph* g, int k, uint64_t* count);
 
 /*
+ * The k-cliques themselves (clique listing, section 3.3: the clique program
+ * with the last level written out instead of counted).  The levels are
+ * materialised as in pg_count_cliques (count pass, exclusive scan, write)
+ * up to the last one, whose entries are the cliques.
+ *   k         1 <= k <= PG_KMAX
+ *   out       host int32[capacity * k], caller-owned: row i holds the i-th
+ *             clique's vertex ids (original numbering), its lowest vertex
+ *             in the degree order first, then one vertex per level; the
+ *             order of the rows is that of the levels (by that lowest
+ *             vertex, then level by level) and is the same on every call.
+ *             May be NULL when capacity is 0.
+ *   capacity  rows of out; cliques past it are counted, not written
+ *   total     host uint64, receives the number of k-cliques
+ * Errors: PG_EINVAL for NULL total, or NULL out with capacity > 0;
+ * PG_EUNSUPPORTED for k out of range.
+ */
+int pg_list_cliques(pg_graph* g, int k, int32_t* out, uint64_t capacity, uint64_t* total);
+
+/*
  * Vertex-induced motif counts for k = 3 or 4 (section 2.2 motif counting,
  * section 3.3 Listing of motif counting with customised classification,
  * section 4.2).  Every connected induced k-vertex subgraph is counted once,

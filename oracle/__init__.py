@@ -79,6 +79,27 @@ def clique_count(g, k: int, nthreads: int = 0) -> int:
     return int(_load().or_clique_count(g.n, prp, pcol, k, nthreads))
 
 
+def clique_list(g, k: int) -> list:
+    """Every k-clique as its ascending tuple of vertex ids, in lexicographic
+    order (section 2.2 k-cliques; section 3.3 listing).  Plain ordered
+    extension: a clique (v1 < ... < vj) grows by each common neighbour of
+    all its vertices that is larger than vj.  For graphs with up to about
+    10^6 cliques."""
+    nbr = [set(int(u) for u in g.adj(v)) for v in range(g.n)]
+    out = []
+
+    def grow(clique, cand):
+        if len(clique) == k:
+            out.append(tuple(clique))
+            return
+        for u in sorted(cand):
+            grow(clique + [u], {w for w in cand if w > u and w in nbr[u]})
+
+    if k >= 1:
+        grow([], set(range(g.n)))
+    return out
+
+
 def clique_count_roots(g, k: int, roots, nthreads: int = 0):
     """k-cliques whose first vertex in the degree order is each given root."""
     rp, prp = _c(g.row_ptr, np.int64)

@@ -33,6 +33,14 @@ def clique_count(g, k: int) -> int:
     return total
 
 
+def clique_list(g, k: int) -> list:
+    """Every k-clique as its ascending tuple of vertex ids, in lexicographic
+    order (all k-subsets, kept when pairwise adjacent)."""
+    A = dense_adj(g)
+    return [s for s in itertools.combinations(range(g.n), k)
+            if all(A[a, b] for a, b in itertools.combinations(s, 2))]
+
+
 def _connected(A, s) -> bool:
     s = list(s)
     seen = {s[0]}

@@ -23,7 +23,8 @@ PG_BATCH_MAX_VERTICES = 512
 
 EXPORTS = (
     "pg_graph_load_csr", "pg_graph_free", "pg_graph_set_stream", "pg_graph_info",
-    "pg_set_memory_budget", "pg_graph_set_option", "pg_count_cliques", "pg_count_motifs", "pg_fsm",
+    "pg_set_memory_budget", "pg_graph_set_option", "pg_count_cliques", "pg_list_cliques", "pg_count_motifs",
+    "pg_fsm",
     "pg_fsm_num_patterns", "pg_fsm_pattern_key", "pg_batch_load", "pg_batch_free",
     "pg_batch_count_motifs", "pg_batch_slot_create", "pg_batch_slot_submit", "pg_batch_slot_query",
     "pg_batch_slot_wait", "pg_batch_slot_free", "pg_batch_work_estimate",
@@ -60,6 +61,7 @@ def load_library(path: str | None = None):
     lib.pg_set_memory_budget.argtypes = [ptr, u64]
     lib.pg_graph_set_option.argtypes = [ptr, cint, i64]
     lib.pg_count_cliques.argtypes = [ptr, cint, P(u64)]
+    lib.pg_list_cliques.argtypes = [ptr, cint, ptr, u64, P(u64)]
     lib.pg_count_motifs.argtypes = [ptr, cint, ptr]
     lib.pg_fsm.argtypes = [ptr, cint, u64, ptr, sz, P(sz)]
     lib.pg_fsm_num_patterns.argtypes = [cint, cint]
@@ -179,6 +181,16 @@ def pg_count_cliques(g, k: int) -> int:
     c = ctypes.c_uint64()
     _check(load_library().pg_count_cliques(g, int(k), ctypes.byref(c)))
     return int(c.value)
+
+
+def pg_list_cliques(g, k: int, capacity: int):
+    """(rows, total): the first min(total, capacity) k-cliques as an int32
+    array of shape (rows, k), and the number of k-cliques."""
+    out = np.zeros((max(int(capacity), 0), int(k)), dtype=np.int32)
+    t = ctypes.c_uint64()
+    p = ctypes.c_void_p(out.ctypes.data) if out.size else None
+    _check(load_library().pg_list_cliques(g, int(k), p, int(capacity), ctypes.byref(t)))
+    return out[:min(int(t.value), out.shape[0])], int(t.value)
 
 
 def pg_count_motifs(g, k: int) -> np.ndarray:
@@ -338,6 +350,9 @@ class Graph:
 
     def cliques(self, k: int) -> int:
         return pg_count_cliques(self.h, k)
+
+    def list_cliques(self, k: int, capacity: int):
+        return pg_list_cliques(self.h, k, capacity)
 
     def motifs(self, k: int) -> np.ndarray:
         return pg_count_motifs(self.h, k)

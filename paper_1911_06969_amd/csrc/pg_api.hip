@@ -157,6 +157,18 @@ int pg_count_cliques(pg_graph* g, int k, uint64_t* count) {
     });
 }
 
+int pg_list_cliques(pg_graph* g, int k, int32_t* out, uint64_t capacity, uint64_t* total) {
+    return guarded([&] {
+        PG_REQUIRE(g != nullptr && total != nullptr, PG_EINVAL, "NULL argument");
+        PG_REQUIRE(capacity == 0 || out != nullptr, PG_EINVAL, "out is NULL with a non-zero capacity");
+        PG_REQUIRE(k >= 1 && k <= PG_KMAX, PG_EUNSUPPORTED, "k must be in [1, 8]");
+        require_device();
+        uint64_t c = 0;
+        run_with_arena(g, [&] { c = list_cliques(g, k, out, capacity); });
+        *total = c;
+    });
+}
+
 int pg_count_motifs(pg_graph* g, int k, uint64_t* counts) {
     return guarded([&] {
         PG_REQUIRE(g != nullptr && counts != nullptr, PG_EINVAL, "NULL argument");

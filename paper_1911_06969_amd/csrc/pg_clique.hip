@@ -231,6 +231,28 @@ __global__ void k_chunk_bounds(const uint64_t* __restrict__ start, int64_t m, ui
     out_s[j] = start[c];
 }
 
+// One materialised level as the general path holds it: the vertex of each
+// entry, and the segments of the parent level that give each entry's parent
+// (the largest p in [p_lo, p_hi) with seg[p] - seg_base <= entry).  At
+// level 1 the parents are the roots.
+struct LevelRef {
+    const int32_t* vid = nullptr;
+    const int64_t* seg = nullptr;
+    int64_t seg_base = 0, p_lo = 0, p_hi = 0;
+};
+
+struct LevelChain {
+    LevelRef l[PG_KMAX];
+};
+
+// Listing: where the cliques go (host rows of k vertex ids).
+struct ListOut {
+    int32_t* host = nullptr;
+    uint64_t capacity = 0;       // rows
+    uint64_t found = 0;          // cliques met so far (also past capacity)
+    const int32_t* vertex_of_rank = nullptr;
+};
+
 struct CliqueRun {
     pg_graph* g;
     int k;
@@ -241,7 +263,58 @@ struct CliqueRun {
     int blocks;
     uint64_t mwords = 0;        // mask path: words of all mask rows
     bool long_segments = false; // general path: segments may exceed CQ_ROUND entries
+    ListOut* list = nullptr;    // listing instead of counting (general path)
+    LevelChain chain;           // general path: the levels above the current one
 };
+
+// Writes the k-cliques of entries [y0, y1) of level L = k - 1 as rows of
+// original vertex ids (root first, then one vertex per level), out[(y - y0)
+// * k + j].  Each thread walks one entry's parents up to its root.
+__global__ void k_clique_emit(LevelChain C, int L, int64_t y0, int64_t y1, const int32_t* __restrict__ vertex_of_rank,
+                              int32_t* __restrict__ out) {
+    for (int64_t y = y0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; y < y1;
+         y += (int64_t)gridDim.x * blockDim.x) {
+        int32_t* row = out + (y - y0) * (L + 1);
+        int64_t e = y;
+        for (int l = L; l >= 1; --l) {
+            const LevelRef& R = C.l[l - 1];
+            row[l] = vertex_of_rank[R.vid[e]];
+            // the parent: the last segment starting at or before e
+            int64_t lo = R.p_lo, hi = R.p_hi - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (R.seg[mid] - R.seg_base <= e) lo = mid; else hi = mid - 1;
+            }
+            e = lo;
+        }
+        row[0] = vertex_of_rank[e];
+    }
+}
+
+constexpr int64_t LIST_ROWS = 1 << 20;   // cliques per copy to the host
+
+// Cliques are entries [y0, y1) of the last level: those that still fit the
+// caller's rows are copied there (in pieces of LIST_ROWS), all are counted.
+static void emit_cliques(CliqueRun& R, int64_t y0, int64_t y1) {
+    ListOut& O = *R.list;
+    Arena& ar = R.g->arena;
+    const uint64_t before = O.found;
+    const uint64_t room = O.capacity > before ? O.capacity - before : 0;
+    const int64_t copy_end = y0 + (int64_t)std::min<uint64_t>((uint64_t)(y1 - y0), room);
+    for (int64_t a = y0; a < copy_end; a += LIST_ROWS) {
+        const int64_t b = std::min<int64_t>(copy_end, a + LIST_ROWS);
+        const size_t mk = ar.mark();
+        int32_t* rows = push<int32_t>(ar, (size_t)(b - a) * R.k);
+        const unsigned blocks = (unsigned)std::min<int64_t>((b - a + 255) / 256, 65535);
+        k_clique_emit<<<blocks, 256, 0, R.s>>>(R.chain, R.k - 1, a, b, O.vertex_of_rank, rows);
+        PG_HIP(hipGetLastError());
+        PG_HIP(hipMemcpyAsync(O.host + (before + (uint64_t)(a - y0)) * R.k, rows,
+                              sizeof(int32_t) * (size_t)(b - a) * R.k, hipMemcpyDeviceToHost, R.s));
+        PG_HIP(hipStreamSynchronize(R.s));
+        ar.reset(mk);
+    }
+    O.found = before + (uint64_t)(y1 - y0);
+}
 
 // Work items are parent segments, or rounds of CQ_ROUND entries of them
 // when some segment is longer than a round (a segment's entries are then
@@ -279,6 +352,11 @@ static void extend_level(CliqueRun& R, int lev, const int64_t* seg, int64_t seg_
                          const int32_t* vid, int64_t x_lo, int64_t x_hi) {
     pg_graph* g = R.g;
     Arena& ar = g->arena;
+    R.chain.l[lev - 1] = LevelRef{vid, seg, seg_base, p_lo, p_hi};
+    if (R.list && lev == R.k - 1) {   // listing: the entries of this level are the cliques
+        emit_cliques(R, x_lo, x_hi);
+        return;
+    }
     CliqueArgs A{};
     A.seg = seg;
     A.seg_base = seg_base;
@@ -287,7 +365,7 @@ static void extend_level(CliqueRun& R, int lev, const int64_t* seg, int64_t seg_
     A.x_hi = x_hi;
     A.rp = g->dag.rp.as<int64_t>();
     A.col = g->dag.col.as<int32_t>();
-    if (lev == R.k - 2) {
+    if (lev == R.k - 2 && !R.list) {
         launch<MODE_LAST>(R, A, p_lo, p_hi - p_lo, "clique_last", 0.0);
         return;
     }
@@ -306,7 +384,7 @@ static void extend_level(CliqueRun& R, int lev, const int64_t* seg, int64_t seg_
         return;
     }
     PG_REQUIRE(total < (uint64_t(1) << 40), PG_EOVERFLOW, "level size exceeds 2^40 entries");
-    const bool next_last = (lev + 1 == R.k - 2);
+    const bool next_last = (lev + 1 == R.k - 2) && !R.list;
     // bytes per entry of the next level: vid, plus count + start if it is
     // extended again
     const uint64_t per = next_last ? 4 : 4 + 4 + 8;
@@ -1420,6 +1498,56 @@ uint64_t count_cliques(pg_graph* g, int k) {
     // k = 3 on the mask path: the light roots' triangles are the level-2
     // entries; the heavy roots' are in st[0]
     return (masks && k == 3 ? n2 : 0) + st[0];
+}
+
+__global__ void k_vertex_of_rank(int64_t n, const int32_t* __restrict__ rank_of, int32_t* __restrict__ vor) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        vor[rank_of[v]] = (int32_t)v;
+}
+
+// Lists the k-cliques through the general level kernels: the last level is
+// materialised like the others (count pass, scan, write) and each of its
+// entries, walked up to its root, is one clique.  Rows of k original vertex
+// ids, the root (lowest in the degree order) first, then one vertex per
+// level; cliques in the order of the levels (by root, then level by level).
+// The first `capacity` go to `out`; returns the number of k-cliques.
+uint64_t list_cliques(pg_graph* g, int k, int32_t* out, uint64_t capacity) {
+    PG_REQUIRE(k >= 1 && k <= PG_KMAX, PG_EUNSUPPORTED, "k must be in [1, PG_KMAX]");
+    build_dag(g);
+    const int64_t n = g->n;
+    hipStream_t s = g->stream;
+    Arena& ar = g->arena;
+    int32_t* vor = push<int32_t>(ar, (size_t)std::max<int64_t>(n, 1));
+    if (n > 0) {
+        k_vertex_of_rank<<<grid_threads(n), 256, 0, s>>>(n, g->dag.rank_of.as<int32_t>(), vor);
+        PG_HIP(hipGetLastError());
+    }
+    if (k == 1) {   // the vertices, in the degree order
+        const uint64_t c = std::min<uint64_t>((uint64_t)n, capacity);
+        if (c > 0) PG_HIP(hipMemcpyAsync(out, vor, sizeof(int32_t) * c, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        return (uint64_t)n;
+    }
+    if (g->dag.n_edges == 0) return 0;
+    CliqueRun R;
+    R.g = g;
+    R.k = k;
+    R.s = s;
+    R.waves = grid_waves(32);
+    R.blocks = (int)(R.waves / CQ_WAVES);
+    R.long_segments = g->dag.max_out > CQ_ROUND;
+    uint64_t* small = push<uint64_t>(ar, 8 + Q_WORDS);
+    R.stats = reinterpret_cast<unsigned long long*>(small);
+    R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
+    fill_u64(small, 8, 0, s);
+    ListOut O;
+    O.host = out;
+    O.capacity = out ? capacity : 0;
+    O.vertex_of_rank = vor;
+    R.list = &O;
+    extend_level(R, 1, g->dag.rp.as<int64_t>(), 0, 0, n, g->dag.col.as<int32_t>(), 0, g->dag.n_edges);
+    PG_HIP(hipStreamSynchronize(s));
+    return O.found;
 }
 
 }  // namespace pg

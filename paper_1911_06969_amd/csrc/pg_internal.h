@@ -209,6 +209,7 @@ void graph_load(pg_graph* g, int64_t n, int64_t nnz, const int64_t* rp, const in
 void build_dag(pg_graph* g);
 void build_motif_l1(pg_graph* g);
 uint64_t count_cliques(pg_graph* g, int k);
+uint64_t list_cliques(pg_graph* g, int k, int32_t* out, uint64_t capacity);
 void count_motifs(pg_graph* g, int k, uint64_t* counts);
 void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports, size_t len,
              size_t* n_frequent);

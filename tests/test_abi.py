@@ -45,6 +45,9 @@ def test_null_arguments_rejected(lib):
     c = ctypes.c_uint64()
     assert lib.pg_count_cliques(None, 3, ctypes.byref(c)) == binding.PG_EINVAL
     assert lib.pg_count_motifs(None, 4, None) == binding.PG_EINVAL
+    assert lib.pg_list_cliques(None, 3, None, 0, ctypes.byref(c)) == binding.PG_EINVAL
+    # a non-zero capacity needs rows to write into
+    assert lib.pg_list_cliques(ctypes.c_void_p(8), 3, None, 5, ctypes.byref(c)) == binding.PG_EINVAL
     assert "NULL" in binding.pg_last_error()
     assert lib.pg_graph_free(None) == binding.PG_OK
 
@@ -54,6 +57,7 @@ def test_unsupported_sizes_rejected(lib):
     # size checks come before any device access
     assert lib.pg_count_cliques(ctypes.c_void_p(8), 0, ctypes.byref(c)) == binding.PG_EUNSUPPORTED
     assert lib.pg_count_cliques(ctypes.c_void_p(8), 9, ctypes.byref(c)) == binding.PG_EUNSUPPORTED
+    assert lib.pg_list_cliques(ctypes.c_void_p(8), 9, None, 0, ctypes.byref(c)) == binding.PG_EUNSUPPORTED
 
 
 def test_version(lib):

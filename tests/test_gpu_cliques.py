@@ -188,3 +188,53 @@ def test_clique_rmat_config_k5(torch):
         G.set_memory_budget(8 << 30)
         say("scale-21 k=5, sibling masks, 8 GiB")
         assert G.cliques(5) == want["k5"]
+
+
+# ------------------------------------------------------------ clique listing
+
+def _row_sets(rows):
+    return sorted(tuple(sorted(r)) for r in rows.tolist())
+
+
+def test_list_complete_graphs(torch):
+    import itertools
+    for n in (1, 2, 5, 9):
+        g = synth.complete(n)
+        with binding.Graph.from_csr(g) as G:
+            for k in range(1, min(n, 6) + 1):
+                rows, total = G.list_cliques(k, comb(n, k))
+                assert total == comb(n, k)
+                assert rows.shape == (comb(n, k), k)
+                assert _row_sets(rows) == list(itertools.combinations(range(n), k))
+
+
+@pytest.mark.parametrize("scale,ef,seed", [(8, 8, 1), (10, 8, 2)])
+def test_list_rmat_against_oracle(torch, scale, ef, seed):
+    g = synth.rmat(scale, ef, seed=seed)
+    with binding.Graph.from_csr(g) as G:
+        for k in (2, 3, 4, 5):
+            want = oracle.clique_list(g, k)
+            say("rmat", scale, "k", k, len(want))
+            rows, total = G.list_cliques(k, len(want) + 5)
+            again, total2 = G.list_cliques(k, len(want) + 5)
+            assert total == total2 == len(want)
+            assert np.array_equal(rows, again)   # the same rows in the same order
+            assert _row_sets(rows) == want
+
+
+def test_list_capacity_and_edge_blocking(torch):
+    """A short buffer gets the first rows of the full listing; capacity 0
+    only counts; a tiny memory budget (many chunks) lists the same rows in
+    the same order."""
+    g = synth.rmat(10, 16, seed=3)
+    with binding.Graph.from_csr(g) as G:
+        none, total = G.list_cliques(4, 0)
+        full, t1 = G.list_cliques(4, total)
+        part, t2 = G.list_cliques(4, 1000)
+        G.set_memory_budget(1 << 20)
+        blocked, t3 = G.list_cliques(4, total)
+    assert total == t1 == t2 == t3 == oracle.clique_count(g, 4)
+    assert none.shape == (0, 4)
+    assert np.array_equal(part, full[:1000])
+    assert np.array_equal(blocked, full)
+    assert _row_sets(full) == oracle.clique_list(g, 4)

@@ -79,3 +79,30 @@ def test_edges_and_vertices():
     g = synth.rmat(9, 4, seed=14)
     assert oracle.clique_count(g, 2) == g.n_edges
     assert oracle.clique_count(g, 1) == g.n
+
+
+# ------------------------------------------------------------ clique listing
+
+@pytest.mark.parametrize("n,k", [(1, 1), (5, 2), (6, 3), (7, 4), (8, 8), (6, 7)])
+def test_list_complete_graph_all_subsets(n, k):
+    """K_n: the k-cliques are exactly the k-subsets, in lexicographic order."""
+    g = synth.complete(n)
+    assert oracle.clique_list(g, k) == list(itertools.combinations(range(n), k))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_list_matches_brute_force(seed):
+    rng = np.random.default_rng(100 + seed)
+    g = synth.gnp_small(int(rng.integers(5, 12)), float(rng.uniform(0.3, 0.9)), 100 + seed)
+    for k in (1, 2, 3, 4, 5):
+        assert oracle.clique_list(g, k) == brute.clique_list(g, k)
+
+
+def test_list_sizes_match_counts():
+    """Listing and the C++ clique enumeration agree on R-MAT graphs."""
+    g = synth.rmat(9, 8, seed=11)
+    for k in (3, 4, 5):
+        lst = oracle.clique_list(g, k)
+        assert len(lst) == oracle.clique_count(g, k)
+        assert len(set(lst)) == len(lst)
+        assert all(all(a < b for a, b in zip(t, t[1:])) for t in lst)
