@@ -118,3 +118,13 @@ def test_motif_batch_config(torch):
     assert [int(x) for x in got.sum(axis=0)] == want["sum"]
     assert [[int(x) for x in got[i]] for i in want["sample_index"]] == want["sample_rows"]
     assert hashlib.sha256(got.astype(np.uint64).tobytes()).hexdigest() == want["sha256"]
+
+
+def test_every_graph_on_six_vertices(torch):
+    """All 32,768 labelled graphs on six vertices in one batch: each graph's
+    3- and 4-motif counts against brute force over its vertex subsets."""
+    graphs = list(synth.all_graphs(6))
+    b = synth.batch_from_graphs(graphs)
+    for k in (3, 4):
+        want = np.stack([brute.motif_counts(g, k) for g in graphs]).astype(np.uint64)
+        assert np.array_equal(batch_counts(b, k), want)

@@ -238,3 +238,16 @@ def test_list_capacity_and_edge_blocking(torch):
     assert np.array_equal(part, full[:1000])
     assert np.array_equal(blocked, full)
     assert _row_sets(full) == oracle.clique_list(g, 4)
+
+
+def test_every_graph_on_five_vertices(torch):
+    """All 1,024 labelled graphs on five vertices: k-clique counts through
+    both paths against brute force, and the listed cliques as sets."""
+    for g in synth.all_graphs(5):
+        want = [brute.clique_count(g, k) for k in (3, 4, 5)]
+        assert gpu_cliques(g, (3, 4, 5)) == want
+        with binding.Graph.from_csr(g) as G:
+            for k in (2, 3, 4):
+                rows, total = G.list_cliques(k, 16)
+                assert total == len(rows)
+                assert _row_sets(rows) == brute.clique_list(g, k)

@@ -1,0 +1,65 @@
+"""Failure handling on the GPU path: device memory through the allocator
+hook (pg_set_allocator), with the n-th allocation refused.  Every call must
+then fail with PG_ENOMEM, and every block the library took must come back;
+with the hook allowing everything the counts are the oracle's."""
+import ctypes
+
+import pytest
+
+import oracle
+from paper_1911_06969_amd import binding, synth
+from tests.gpu_common import gpu_or_skip
+
+pytestmark = pytest.mark.gpu
+
+ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return gpu_or_skip()
+
+
+def test_allocator_hook_refusals_leak_nothing(torch):
+    live = {}           # pointer -> tensor holding the block
+    left = [None]       # allocations still granted (None: all)
+    unknown = []        # frees of pointers the hook did not hand out
+
+    def alloc(nbytes, ctx):
+        if left[0] is not None:
+            if left[0] <= 0:
+                return None
+            left[0] -= 1
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def free(p, ctx):
+        if live.pop(p, None) is None:
+            unknown.append(p)
+
+    a, f = ALLOC(alloc), FREE(free)
+    lib = binding.load_library()
+    g = synth.rmat(10, 8, seed=12)
+    want = {k: oracle.clique_count(g, k) for k in (3, 4, 5)}
+    assert lib.pg_set_allocator(a, f, None) == binding.PG_OK
+    try:
+        with binding.Graph.from_csr(g) as G:
+            assert [G.cliques(k) for k in (3, 4, 5)] == [want[k] for k in (3, 4, 5)]
+            assert [int(x) for x in G.motifs(3)] == [int(x) for x in oracle.motif_esu(g, 3)]
+        assert not live and not unknown
+        # the refusal lands in the load, the DAG build, the mask plan or the
+        # arena's growth: either the right count or PG_ENOMEM, never a leak
+        for n_ok in (0, 1, 2, 4, 8, 16, 32, 64):
+            left[0] = n_ok
+            try:
+                with binding.Graph.from_csr(g) as G:
+                    assert G.cliques(5) == want[5]
+            except binding.PgError as e:
+                assert e.code == binding.PG_ENOMEM
+            left[0] = None
+            assert not live and not unknown
+    finally:
+        left[0] = None
+        assert lib.pg_set_allocator(None, None, None) == binding.PG_OK
