@@ -251,3 +251,4 @@ def test_every_graph_on_five_vertices(torch):
                 rows, total = G.list_cliques(k, 16)
                 assert total == len(rows)
                 assert _row_sets(rows) == brute.clique_list(g, k)
+

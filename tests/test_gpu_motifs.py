@@ -130,3 +130,14 @@ def test_motif_rmat_config(torch):
         assert [int(x) for x in G.motifs(3)] == want["motif3"]
         say("scale-18 k=4")
         assert [int(x) for x in G.motifs(4)] == want["motif4"]
+
+
+def test_binary_search_connectivity_example(torch):
+    """The connectivity check of section 5 (binary search figure): embedding
+    {2, 5, 8} (here the path 2-5-8) and candidate 9, whose neighbour list
+    holds 2 and 5 but not 8.  The 4-set {2, 5, 8, 9} is then a triangle
+    2-5-9 with the pendant 8 (a paw), the only connected 4-set."""
+    g = synth.from_edges(10, [(2, 5), (5, 8), (2, 9), (5, 9)])
+    assert gpu_motifs(g, 4) == [0, 0, 0, 1, 0, 0]
+    assert gpu_motifs(g, 4) == [int(x) for x in brute.motif_counts(g, 4)]
+    assert gpu_motifs(g, 3) == [int(x) for x in brute.motif_counts(g, 3)]
