@@ -311,9 +311,15 @@ __device__ __forceinline__ void set_bits(const Bits& Bt, const Emb& E) {
     uint32_t* base = Bt.bm + (int64_t)(sl - Bt.s_lo) * 4 * Bt.words;
     // every vertex of an orbit has the orbit's label, so its bit is indexed
     // by its rank within that label (bitmaps of max-label-count bits)
+    // Most embeddings meet bits that are set already (a domain holds at most
+    // one bit per vertex, and each vertex lies in many embeddings): the word
+    // is read first and the atomic skipped when the bit is there.  Bits only
+    // go from 0 to 1, so a stale read can only cost a redundant atomic.
     for (int i = 0; i < E.nv; ++i) {
         const uint32_t v = (uint32_t)Bt.lrank[E.v[i]];
-        atomicOr(base + E.orb[i] * Bt.words + (v >> 5), 1u << (v & 31));
+        uint32_t* w = base + E.orb[i] * Bt.words + (v >> 5);
+        const uint32_t bit = 1u << (v & 31);
+        if ((__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit) == 0u) atomicOr(w, bit);
     }
 }
 
