@@ -270,9 +270,35 @@ __global__ __launch_bounds__(256) void k_edge_ids(int64_t n, const int64_t* __re
     }
 }
 
-__global__ void k_hist(int64_t m, const int32_t* __restrict__ pid, uint32_t* __restrict__ counts) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&counts[pid[i]], 1u);
+// Histogram of m values into counts[].  Values in [lo, lo + nb) with nb <=
+// HIST_LDS bins gather in a histogram of the workgroup's own in LDS (few
+// global counters would otherwise take every element's atomic), which is
+// added to counts once per workgroup; other values go to counts directly.
+constexpr int HIST_LDS = 8192;
+
+__global__ __launch_bounds__(256) void k_hist(int64_t m, const int32_t* __restrict__ val, uint32_t* __restrict__ counts,
+                                              int32_t lo, int32_t nb) {
+    __shared__ uint32_t h[HIST_LDS];
+    const bool local = nb <= HIST_LDS;
+    if (local) {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
+        __syncthreads();
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = val[i];
+        const uint32_t b = (uint32_t)(v - lo);
+        if (local && b < (uint32_t)nb) atomicAdd(&h[b], 1u);
+        else atomicAdd(&counts[v], 1u);
+    }
+    if (local) {
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            if (h[b]) atomicAdd(&counts[lo + b], h[b]);
+    }
+}
+
+static unsigned hist_blocks(int64_t m) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((m + 255) / 256, (int64_t)device_info().n_cu * 2));
 }
 
 // candidate flag: the pattern has enough embeddings to possibly reach sigma
@@ -524,12 +550,9 @@ static void reduce_level(pg_graph* g, FsmCtx& C, const int32_t* lrank, int64_t l
     ar.reset(mk);
 }
 
-__global__ void k_label_keys(int64_t n, const int32_t* __restrict__ lab, uint64_t* __restrict__ keys,
-                             uint32_t* __restrict__ hist) {
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+__global__ void k_label_keys(int64_t n, const int32_t* __restrict__ lab, uint64_t* __restrict__ keys) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         keys[v] = ((uint64_t)(uint32_t)lab[v] << 32) | (uint64_t)v;
-        atomicAdd(&hist[lab[v]], 1u);
-    }
 }
 
 __global__ void k_label_ranks(int64_t n, const uint64_t* __restrict__ sorted, const uint64_t* __restrict__ first,
@@ -553,7 +576,9 @@ static int64_t label_ranks(pg_graph* g, int32_t* lrank) {
     uint32_t* hist = push<uint32_t>(ar, L);
     uint64_t* first = push<uint64_t>(ar, L + 1);
     fill_u32(hist, L, 0, s);
-    k_label_keys<<<grid1(n), 256, 0, s>>>(n, g->labels.as<int32_t>(), keys, hist);
+    k_label_keys<<<grid1(n), 256, 0, s>>>(n, g->labels.as<int32_t>(), keys);
+    PG_HIP(hipGetLastError());
+    k_hist<<<hist_blocks(n), 256, 0, s>>>(n, g->labels.as<int32_t>(), hist, 0, (int32_t)L);
     PG_HIP(hipGetLastError());
     int lb = 1;
     while ((int64_t(1) << lb) < L) ++lb;
@@ -629,7 +654,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
         ProfScope ps("fsm_l1", s, (double)E);
         k_fsm_l1<false><<<grid1(E), 256, 0, s>>>(C, E, pid1, Bits{});
         PG_HIP(hipGetLastError());
-        k_hist<<<grid1(E), 256, 0, s>>>(E, pid1, counts);
+        k_hist<<<hist_blocks(E), 256, 0, s>>>(E, pid1, counts, (int32_t)C.B.edge, (int32_t)(C.B.wedge - C.B.edge));
         PG_HIP(hipGetLastError());
     }
     reduce_level(g, C, lrank, label_max, C.B.edge, C.B.wedge, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
@@ -666,7 +691,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
             ProfScope ps("fsm_l2_write", s, (double)n2);
             k_fsm_l2<true><<<grid1(m1), 256, 0, s>>>(C, m1, f1, nullptr, st2, a2, b2, p2);
             PG_HIP(hipGetLastError());
-            k_hist<<<grid1(n2), 256, 0, s>>>(n2, p2, counts);
+            k_hist<<<hist_blocks(n2), 256, 0, s>>>(n2, p2, counts, (int32_t)C.B.wedge, (int32_t)(C.B.tri - C.B.wedge));
             PG_HIP(hipGetLastError());
         }
         reduce_level(g, C, lrank, label_max, C.B.wedge, C.B.tri, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
