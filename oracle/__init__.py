@@ -114,25 +114,30 @@ MOTIF3_NAMES = ("wedge", "triangle")
 MOTIF4_NAMES = ("path", "star", "cycle", "paw", "diamond", "clique")
 
 
+MOTIF_CLASSES = {3: 2, 4: 6, 5: 21}
+
+
 def motif_esu(g, k: int, nthreads: int = 0) -> np.ndarray:
     """Induced k-motif counts (k = 3: wedge, triangle; k = 4: path, star,
-    cycle, paw, diamond, 4-clique) by ESU enumeration."""
-    assert k in (3, 4)
+    cycle, paw, diamond, 4-clique; k = 5: the 21 connected graphs in the
+    order of ``brute.motif5_classes``) by ESU enumeration."""
+    assert k in MOTIF_CLASSES
     rp, prp = _c(g.row_ptr, np.int64)
     col, pcol = _c(g.col, np.int32)
-    out = np.zeros(6, dtype=np.uint64)
+    out = np.zeros(21, dtype=np.uint64)
     _load().or_motif_esu(g.n, prp, pcol, k, out.ctypes.data, nthreads)
-    return out[: 2 if k == 3 else 6]
+    return out[: MOTIF_CLASSES[k]]
 
 
 def motif_esu_roots(g, k: int, roots, nthreads: int = 0) -> np.ndarray:
     """ESU restricted to connected subsets whose smallest vertex is a root."""
+    assert k in MOTIF_CLASSES
     rp, prp = _c(g.row_ptr, np.int64)
     col, pcol = _c(g.col, np.int32)
     r, pr = _c(roots, np.int64)
-    out = np.zeros(6, dtype=np.uint64)
+    out = np.zeros(21, dtype=np.uint64)
     _load().or_motif_esu_roots(g.n, prp, pcol, k, pr, r.shape[0], out.ctypes.data, nthreads)
-    return out[: 2 if k == 3 else 6]
+    return out[: MOTIF_CLASSES[k]]
 
 
 def motif_parts(g, nthreads: int = 0) -> dict:

@@ -3,7 +3,8 @@
 Everything here follows a definition directly, with no pruning:
   * k-cliques: every k-subset, pairwise adjacent (Pangolin section 2.2).
   * k-motifs: every k-subset whose induced subgraph is connected, grouped by
-    isomorphism class (sections 2.1-2.2, vertex-induced embeddings).
+    isomorphism class (sections 2.1-2.2, vertex-induced embeddings); for
+    k = 5 the class is the smallest relabelled adjacency mask.
   * FSM: for each labelled pattern with at most 3 edges, every injective,
     label-preserving map of its vertices into the graph that sends pattern
     edges to graph edges; the minimum-image (domain) support is the smallest
@@ -71,8 +72,71 @@ def motif_class(A, s) -> int:
     return 4 if e == 5 else 5
 
 
+# Five vertices: the 21 connected graphs, numbered by (number of edges,
+# canonical code).  A graph on positions 0..4 is a 10-bit mask, bit
+# b(b-1)/2 + a for the pair a < b (the 4-vertex pair order extended by
+# 04, 14, 24, 34); its canonical code is the smallest mask over the 120
+# relabellings of the positions.
+PAIRS5 = [(a, b) for b in range(5) for a in range(b)]
+
+
+def _relabel5(m: int, perm) -> int:
+    out = 0
+    for i, (a, b) in enumerate(PAIRS5):
+        if (m >> i) & 1:
+            x, y = sorted((perm[a], perm[b]))
+            out |= 1 << (y * (y - 1) // 2 + x)
+    return out
+
+
+def _mask_connected5(m: int) -> bool:
+    seen, stack = {0}, [0]
+    while stack:
+        x = stack.pop()
+        for i, (a, b) in enumerate(PAIRS5):
+            if (m >> i) & 1 and x in (a, b):
+                y = b if x == a else a
+                if y not in seen:
+                    seen.add(y)
+                    stack.append(y)
+    return len(seen) == 5
+
+
+def motif5_classes() -> list:
+    """Canonical codes of the connected 5-vertex graphs, in class order."""
+    perms = list(itertools.permutations(range(5)))
+    codes = {min(_relabel5(m, p) for p in perms) for m in range(1 << 10) if _mask_connected5(m)}
+    return sorted(codes, key=lambda c: (bin(c).count("1"), c))
+
+
+_CLASS5 = None
+
+
+def motif5_class_of_mask() -> dict:
+    """10-bit mask -> class id, for the connected masks."""
+    global _CLASS5
+    if _CLASS5 is None:
+        perms = list(itertools.permutations(range(5)))
+        index = {c: i for i, c in enumerate(motif5_classes())}
+        _CLASS5 = {m: index[min(_relabel5(m, p) for p in perms)]
+                   for m in range(1 << 10) if _mask_connected5(m)}
+    return _CLASS5
+
+
 def motif_counts(g, k: int) -> np.ndarray:
     A = dense_adj(g)
+    if k == 5:
+        cls = motif5_class_of_mask()
+        out = np.zeros(21, dtype=np.uint64)
+        for s in itertools.combinations(range(g.n), 5):
+            m = 0
+            for i, (a, b) in enumerate(PAIRS5):
+                if A[s[a], s[b]]:
+                    m |= 1 << i
+            c = cls.get(m)
+            if c is not None:
+                out[c] += 1
+        return out
     out = np.zeros(2 if k == 3 else 6, dtype=np.uint64)
     for s in itertools.combinations(range(g.n), k):
         if _connected(A, s):

@@ -16,7 +16,7 @@
  *    (section 2.1 vertex-induced embeddings, section 2.2 motif counting).
  *    Enumeration by ESU (Wernicke 2006), which visits every connected
  *    induced subset exactly once; classification by edge count and maximum
- *    degree, not by any bitmap table.
+ *    degree for k = 3, 4; for k = 5 by the smallest relabelled pair mask.
  *  - Closed-form pieces for 4-motifs: non-induced pattern counts from
  *    degrees, per-edge triangle counts and common-neighbour counts.
  *  - Frequent subgraph mining: edge-induced embeddings (section 2.1) are
@@ -136,6 +136,64 @@ static int classify(const i32* vs, int k, const i64* rp, const i32* col) {
     return -1; /* disconnected: never reached by ESU */
 }
 
+/* k=5: the class of an induced 5-subset is found from its 10-bit pair mask
+ * (bit b(b-1)/2 + a for positions a < b).  Classes are the connected
+ * 5-vertex graphs numbered by (edge count, smallest mask over all 120
+ * relabellings); the table is built once by trying every relabelling. */
+struct Class5 {
+    signed char of[1024];
+    Class5() {
+        int perm[5] = {0, 1, 2, 3, 4};
+        std::vector<int> canon(1024, 1 << 20);
+        do {
+            for (int m = 0; m < 1024; ++m) {
+                int r = 0;
+                for (int b = 1; b < 5; ++b)
+                    for (int a = 0; a < b; ++a)
+                        if ((m >> (b * (b - 1) / 2 + a)) & 1) {
+                            int x = std::min(perm[a], perm[b]), y = std::max(perm[a], perm[b]);
+                            r |= 1 << (y * (y - 1) / 2 + x);
+                        }
+                canon[m] = std::min(canon[m], r);
+            }
+        } while (std::next_permutation(perm, perm + 5));
+        std::vector<int> codes;
+        for (int m = 0; m < 1024; ++m) {
+            /* connected: grow the component of vertex 0 */
+            int comp = 1, grew = 1;
+            while (grew) {
+                grew = 0;
+                for (int b = 1; b < 5; ++b)
+                    for (int a = 0; a < b; ++a)
+                        if (((m >> (b * (b - 1) / 2 + a)) & 1) && (((comp >> a) ^ (comp >> b)) & 1)) {
+                            comp |= (1 << a) | (1 << b);
+                            grew = 1;
+                        }
+            }
+            of[m] = -1;
+            if (comp == 31) codes.push_back(canon[m]);
+        }
+        std::sort(codes.begin(), codes.end(), [](int x, int y) {
+            int px = __builtin_popcount(x), py = __builtin_popcount(y);
+            return px != py ? px < py : x < y;
+        });
+        codes.erase(std::unique(codes.begin(), codes.end()), codes.end());
+        /* isomorphic masks share the code, so only connected masks match one */
+        for (int m = 0; m < 1024; ++m)
+            for (size_t c = 0; c < codes.size(); ++c)
+                if (codes[c] == canon[m]) of[m] = (signed char)c;
+    }
+};
+
+static int classify5(const i32* vs, const i64* rp, const i32* col) {
+    static const Class5 table;
+    int m = 0;
+    for (int b = 1; b < 5; ++b)
+        for (int a = 0; a < b; ++a)
+            if (adjacent(rp, col, vs[a], vs[b])) m |= 1 << (b * (b - 1) / 2 + a);
+    return table.of[m];
+}
+
 struct Esu {
     const i64* rp; const i32* col; int k; u64* counts;
 };
@@ -144,7 +202,7 @@ struct Esu {
  * vertex), ext the extension set. */
 static void esu_rec(const Esu& E, std::vector<i32>& sub, std::vector<i32> ext) {
     if ((int)sub.size() == E.k) {
-        int p = classify(sub.data(), E.k, E.rp, E.col);
+        int p = E.k == 5 ? classify5(sub.data(), E.rp, E.col) : classify(sub.data(), E.k, E.rp, E.col);
         E.counts[p]++;
         return;
     }
@@ -169,14 +227,14 @@ static void esu_rec(const Esu& E, std::vector<i32>& sub, std::vector<i32> ext) {
     }
 }
 
-/* counts[] receives 2 (k=3) or 6 (k=4) values. */
+/* counts[] receives 2 (k=3), 6 (k=4) or 21 (k=5) values. */
 extern "C" void or_motif_esu(i64 n, const i64* rp, const i32* col, int k, u64* counts, int nthreads) {
     ThreadScope threads(nthreads);
-    const int np = (k == 3) ? 2 : 6;
+    const int np = (k == 3) ? 2 : (k == 4 ? 6 : 21);
     for (int p = 0; p < np; ++p) counts[p] = 0;
 #pragma omp parallel
     {
-        u64 local[6] = {0, 0, 0, 0, 0, 0};
+        u64 local[21] = {0};
         Esu E{rp, col, k, local};
 #pragma omp for schedule(dynamic, 16)
         for (i64 v = 0; v < n; ++v) {
@@ -196,11 +254,11 @@ extern "C" void or_motif_esu_roots(i64 n, const i64* rp, const i32* col, int k, 
                                    i64 nr, u64* counts, int nthreads) {
     (void)n;
     ThreadScope threads(nthreads);
-    const int np = (k == 3) ? 2 : 6;
+    const int np = (k == 3) ? 2 : (k == 4 ? 6 : 21);
     for (int p = 0; p < np; ++p) counts[p] = 0;
 #pragma omp parallel
     {
-        u64 local[6] = {0, 0, 0, 0, 0, 0};
+        u64 local[21] = {0};
         Esu E{rp, col, k, local};
 #pragma omp for schedule(dynamic, 1)
         for (i64 i = 0; i < nr; ++i) {
