@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="clique4",
-                    choices=["clique4", "clique5", "motif4", "motif3", "tc", "fsm", "copy", "tune-batch", "rmat-sweep"],
+                    choices=["clique4", "clique5", "motif4", "motif3", "motif5", "tc", "fsm", "copy", "tune-batch",
+                             "rmat-sweep"],
                     help="copy: a plain 1 GiB device-to-device copy, the known-size reference "
                          "for scaling HBM counters; rmat-sweep: triangles and 4-cliques on R-MAT "
                          "graphs of 2^20 .. 2^25 vertices, average degree 20 (weak scaling)")
@@ -113,6 +114,32 @@ def cpu_baseline_motifs(g, k):
     }
 
 
+def cpu_baseline_motif5(g, want_seconds: float = 10.0):
+    """The oracle's ESU over a random sample of roots (5-sets whose smallest
+    vertex is a root), grown until it takes about want_seconds."""
+    import numpy as np
+    from oracle import max_threads, motif_esu_roots
+    rng = np.random.default_rng(13)
+    perm = rng.permutation(g.n).astype(np.int64)
+    take, dt, found = 256, 0.0, 0
+    while True:
+        roots = np.sort(perm[:take])
+        t = time.perf_counter()
+        found = int(motif_esu_roots(g, 5, roots).sum())
+        dt = time.perf_counter() - t
+        if dt >= want_seconds / 4 or take >= g.n:
+            break
+        take = min(g.n, take * 4)
+    return {
+        "value": found / dt,
+        "unit": "embeddings/s",
+        "cores": max_threads(),
+        "kind": "oracle",
+        "sample": f"{take} random root vertices of {g.n}: {found} 5-motif embeddings whose smallest vertex "
+                  f"is a root, ESU in {dt:.1f} s",
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -179,6 +206,14 @@ def main():
         workload = {"workload": f"{k}-clique counting, R-MAT scale 21 (2,097,152 vertices), edge factor 13, "
                                 f"a=0.57 b=0.19 c=0.19, degree-ordered DAG, int32 CSR, seed 2",
                     "k": k, "vertices": g.n, "edges": g.n_edges}
+    elif w == "motif5":
+        n = 100_000
+        g = synth.erdos_renyi(n, 8.0 / (n - 1), seed=12)
+        k = 5
+        run = lambda G: G.motifs(5)  # noqa: E731
+        dominant, work_key = "motif_last", "motif_last_work"
+        workload = {"workload": "5-motif counting, G(n,p) n=100,000, average degree 8, seed 12",
+                    "k": 5, "vertices": g.n, "edges": g.n_edges}
     elif w == "tc":
         g = synth.triangle_rmat()
         k = 3
@@ -270,6 +305,8 @@ def main():
         note("cpu baseline (oracle)")
         if w.startswith("clique") or w == "tc":
             cpu = cpu_baseline_cliques(g, k, args.cpu_sample_seconds)
+        elif w == "motif5":
+            cpu = cpu_baseline_motif5(g, args.cpu_sample_seconds)
         elif w.startswith("motif"):
             cpu = cpu_baseline_motifs(g, k)
 

@@ -138,14 +138,20 @@ int pg_count_cliques(pg_graph* g, int k, uint64_t* count);
 int pg_list_cliques(pg_graph* g, int k, int32_t* out, uint64_t capacity, uint64_t* total);
 
 /*
- * Vertex-induced motif counts for k = 3 or 4 (section 2.2 motif counting,
- * section 3.3 Listing of motif counting with customised classification,
- * section 4.2).  Every connected induced k-vertex subgraph is counted once,
- * in the slot of its isomorphism class:
+ * Vertex-induced motif counts for k = 3, 4 or 5 (section 2.2 motif
+ * counting, section 3.3 Listing of motif counting with customised
+ * classification, section 4.2).  Every connected induced k-vertex subgraph
+ * is counted once, in the slot of its isomorphism class:
  *   k = 3: counts[0] wedge (path on 3 vertices), counts[1] triangle
  *   k = 4: counts[0] path, [1] 3-star, [2] 4-cycle, [3] paw (triangle with
  *          a pendant edge), [4] diamond (4-cycle with one chord), [5] 4-clique
- *   counts  host uint64[2] or uint64[6]
+ *   k = 5: the 21 connected graphs on five vertices, ordered by edge count,
+ *          ties by the smallest 10-bit adjacency mask over all orderings of
+ *          the five vertices (bit b(b-1)/2 + a set iff vertices a < b are
+ *          adjacent); [0] the 4-star, [2] the path, [20] the 5-clique
+ *   counts  host uint64[2], uint64[6] or uint64[21]
+ * Errors: PG_EINVAL for NULL g or counts, PG_EUNSUPPORTED for k outside
+ * 3..5.
  */
 int pg_count_motifs(pg_graph* g, int k, uint64_t* counts);
 

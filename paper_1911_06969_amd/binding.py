@@ -193,10 +193,13 @@ def pg_list_cliques(g, k: int, capacity: int):
     return out[:min(int(t.value), out.shape[0])], int(t.value)
 
 
+MOTIF_CLASSES = {3: 2, 4: 6, 5: 21}
+
+
 def pg_count_motifs(g, k: int) -> np.ndarray:
-    out = np.zeros(6, dtype=np.uint64)
+    out = np.zeros(21, dtype=np.uint64)
     _check(load_library().pg_count_motifs(g, int(k), ctypes.c_void_p(out.ctypes.data)))
-    return out[: 2 if k == 3 else 6]
+    return out[: MOTIF_CLASSES.get(int(k), 0)]
 
 
 def pg_fsm_num_patterns(max_edges: int, n_labels: int) -> int:

@@ -172,11 +172,11 @@ int pg_list_cliques(pg_graph* g, int k, int32_t* out, uint64_t capacity, uint64_
 int pg_count_motifs(pg_graph* g, int k, uint64_t* counts) {
     return guarded([&] {
         PG_REQUIRE(g != nullptr && counts != nullptr, PG_EINVAL, "NULL argument");
-        PG_REQUIRE(k == 3 || k == 4, PG_EUNSUPPORTED, "motif size must be 3 or 4");
+        PG_REQUIRE(k >= 3 && k <= 5, PG_EUNSUPPORTED, "motif size must be 3, 4 or 5");
         require_device();
-        uint64_t c[6] = {0, 0, 0, 0, 0, 0};
+        uint64_t c[21] = {0};
         run_with_arena(g, [&] { count_motifs(g, k, c); });
-        std::memcpy(counts, c, sizeof(uint64_t) * (k == 3 ? 2 : 6));
+        std::memcpy(counts, c, sizeof(uint64_t) * (k == 3 ? 2 : (k == 4 ? 6 : 21)));
     });
 }
 

@@ -1,4 +1,4 @@
-// Vertex-induced motif counting for k = 3 and k = 4 (Pangolin sections 2.2,
+// Vertex-induced motif counting for k = 3, 4 and 5 (Pangolin sections 2.2,
 // 3.3 motif Listing, 4.2).
 //
 // Canonical test (isAutoCanonical for vertex extension).  An embedding is
@@ -28,7 +28,7 @@
 // support 1 and Aggregate = sum) without enumerating candidates.
 //
 // Output order: k = 3: wedge, triangle; k = 4: path, star, cycle, paw,
-// diamond, 4-clique.
+// diamond, 4-clique; k = 5: the 21 classes described at k_motif_last5.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -603,6 +603,153 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
     }
 }
 
+// ------------------------------------------------------- last level, k = 5
+//
+// Five vertices: a pattern is the 10-bit mask of adjacent position pairs,
+// bit b(b-1)/2 + a for a < b (the 4-vertex order followed by 04, 14, 24,
+// 34).  Classes are the 21 connected graphs numbered by (edge count,
+// smallest mask over the relabellings of the positions); the table maps a
+// mask to its class (-1 when disconnected).
+//
+// Level 3 (four vertices) is not materialised: each lane takes one L2 entry
+// (v0, v1, v2), walks its canonical extensions u by the rule above and,
+// for each, the canonical extensions w of (v0, v1, v2, u), and adds one to
+// the class of the 10-bit mask.  Adjacency is a binary search in the CSR.
+
+__device__ __forceinline__ bool adj_g(const MotifArgs& A, int32_t a, int32_t u) {
+    const int64_t r0 = A.rp[a];
+    return member(A.col + r0, (int32_t)(A.rp[a + 1] - r0), u);
+}
+
+// extensions w of (x0, x1, x2, x3) from the list of x_I (I = their first
+// adjacent position), the current pair mask m4 and p3 = p(3)
+template <int I>
+__device__ __forceinline__ void last5_from(const MotifArgs& A, const int8_t* __restrict__ lut, int32_t x0,
+                                           int32_t x1, int32_t x2, int32_t x3, int m4, int p3,
+                                           unsigned long long* cnt) {
+    const int32_t xi = I == 0 ? x0 : (I == 1 ? x1 : (I == 2 ? x2 : x3));
+    const int64_t t1 = A.rp[xi + 1];
+    for (int64_t t = A.rp[xi]; t < t1; ++t) {
+        const int32_t w = A.col[t];
+        if (w <= x0 || w == x1 || w == x2 || w == x3) continue;
+        if (I == p3 && w <= x3) continue;
+        if (I > 0 && adj_g(A, x0, w)) continue;
+        if (I > 1 && adj_g(A, x1, w)) continue;
+        if (I > 2 && adj_g(A, x2, w)) continue;
+        const int a0 = I == 0 ? 1 : 0;
+        const int a1 = I == 1 ? 1 : (I < 1 ? (int)adj_g(A, x1, w) : 0);
+        const int a2 = I == 2 ? 1 : (I < 2 ? (int)adj_g(A, x2, w) : 0);
+        const int a3 = I == 3 ? 1 : (int)adj_g(A, x3, w);
+        const int c = lut[m4 | (a0 << 6) | (a1 << 7) | (a2 << 8) | (a3 << 9)];
+        if (c >= 0) atomicAdd(&cnt[c], 1ull);   // always connected; the test keeps LDS in bounds
+    }
+}
+
+// extensions u of (v0, v1, v2) from the list of v_I, each extended once more
+template <int I>
+__device__ __forceinline__ void ext4_from(const MotifArgs& A, const int8_t* __restrict__ lut, int32_t v0,
+                                          int32_t v1, int32_t v2, int m3, int p2, unsigned long long* cnt) {
+    const int32_t vi = I == 0 ? v0 : (I == 1 ? v1 : v2);
+    const int64_t t1 = A.rp[vi + 1];
+    for (int64_t t = A.rp[vi]; t < t1; ++t) {
+        const int32_t u = A.col[t];
+        if (u <= v0 || u == v1 || u == v2) continue;
+        if (I == p2 && u <= v2) continue;
+        if (I > 0 && adj_g(A, v0, u)) continue;
+        if (I > 1 && adj_g(A, v1, u)) continue;
+        const int a0 = I == 0 ? 1 : 0;
+        const int a1 = I == 1 ? 1 : (I < 1 ? (int)adj_g(A, v1, u) : 0);
+        const int a2 = I == 2 ? 1 : (int)adj_g(A, v2, u);
+        const int m4 = m3 | (a0 << 3) | (a1 << 4) | (a2 << 5);
+        // p(3) = I: w's first adjacent position must be at least I
+        if (I <= 0) last5_from<0>(A, lut, v0, v1, v2, u, m4, I, cnt);
+        if (I <= 1) last5_from<1>(A, lut, v0, v1, v2, u, m4, I, cnt);
+        last5_from<2>(A, lut, v0, v1, v2, u, m4, I, cnt);
+        last5_from<3>(A, lut, v0, v1, v2, u, m4, I, cnt);
+    }
+}
+
+__global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const int8_t* __restrict__ lut) {
+    __shared__ unsigned long long cnt[21];
+    for (int i = threadIdx.x; i < 21; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    QueueCursor cur = queue_start();
+    int64_t it_end = 0;
+    for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
+        for (int64_t j = it; j < it_end; ++j) {
+            const uint64_t item = A.items[j];
+            const int64_t p = item_seg(item);
+            const int32_t x = (int32_t)item_round(item) * WAVE + lane();
+            const int32_t s = (int32_t)(A.seg2[p + 1] - A.seg2[p]);
+            if (x >= s) continue;
+            const int64_t e = (int64_t)(A.seg2[p] - A.seg2_base) + x;
+            const int32_t v0 = A.l1_src[p], v1 = A.l1_dst[p], v2 = A.vid2[e];
+            const int code = A.code2[e];
+            const int m3 = 1 | ((code & 1) << 1) | (((code >> 1) & 1) << 2);
+            const int p2 = (code & 1) ? 0 : 1;   // p(2): v2's first adjacent position
+            if (p2 == 0) ext4_from<0>(A, lut, v0, v1, v2, m3, p2, cnt);
+            ext4_from<1>(A, lut, v0, v1, v2, m3, p2, cnt);
+            ext4_from<2>(A, lut, v0, v1, v2, m3, p2, cnt);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 21; i += blockDim.x)
+        if (cnt[i]) atomicAdd(&A.out[i], cnt[i]);
+}
+
+// The 1024-entry class table of five vertices (see above), built once.
+struct Lut5 {
+    int8_t v[1024];
+};
+
+static const Lut5& lut5_host() {
+    static const Lut5 t = [] {
+        Lut5 r{};
+        int pos[5] = {0, 1, 2, 3, 4};
+        int best[1024];
+        for (int m = 0; m < 1024; ++m) best[m] = 1024;
+        do {   // every relabelling of the positions
+            for (int m = 0; m < 1024; ++m) {
+                int q = 0;
+                for (int b = 1; b < 5; ++b)
+                    for (int a = 0; a < b; ++a) {
+                        if (!((m >> (b * (b - 1) / 2 + a)) & 1)) continue;
+                        const int x = std::min(pos[a], pos[b]), y = std::max(pos[a], pos[b]);
+                        q |= 1 << (y * (y - 1) / 2 + x);
+                    }
+                best[m] = std::min(best[m], q);
+            }
+        } while (std::next_permutation(pos, pos + 5));
+        std::vector<int> classes;
+        std::vector<bool> conn(1024);
+        for (int m = 0; m < 1024; ++m) {
+            int reach = 1;   // vertices reachable from position 0
+            for (int round = 0; round < 4; ++round)
+                for (int b = 1; b < 5; ++b)
+                    for (int a = 0; a < b; ++a)
+                        if (((m >> (b * (b - 1) / 2 + a)) & 1) && ((reach >> a) & 1 || (reach >> b) & 1))
+                            reach |= (1 << a) | (1 << b);
+            conn[m] = reach == 31;
+            if (conn[m] && best[m] == m) classes.push_back(m);
+        }
+        std::sort(classes.begin(), classes.end(), [](int a, int b) {
+            const int ea = __builtin_popcount(a), eb = __builtin_popcount(b);
+            return ea != eb ? ea < eb : a < b;
+        });
+        for (int m = 0; m < 1024; ++m) {
+            r.v[m] = -1;
+            if (!conn[m]) continue;
+            const auto it = std::lower_bound(classes.begin(), classes.end(), best[m], [](int a, int b) {
+                const int ea = __builtin_popcount(a), eb = __builtin_popcount(b);
+                return ea != eb ? ea < eb : a < b;
+            });
+            r.v[m] = (int8_t)(it - classes.begin());
+        }
+        return r;
+    }();
+    return t;
+}
+
 // ------------------------------------------------------------------ host
 
 struct MotifRun {
@@ -743,12 +890,17 @@ __global__ void k_chunk_entries(const uint64_t* __restrict__ start, int64_t m, u
     out_s[j] = start[c];
 }
 
+static int motif_classes(int k) {
+    return k == 3 ? 2 : (k == 4 ? 6 : 21);
+}
+
 void count_motifs(pg_graph* g, int k, uint64_t* counts) {
-    PG_REQUIRE(k == 3 || k == 4, PG_EUNSUPPORTED, "motif size must be 3 or 4");
+    PG_REQUIRE(k >= 3 && k <= 5, PG_EUNSUPPORTED, "motif size must be 3, 4 or 5");
     build_motif_l1(g);
     build_hubs(g);
     const int64_t E = g->ml1.n_edges;
-    for (int i = 0; i < (k == 3 ? 2 : 6); ++i) counts[i] = 0;
+    const int nc = motif_classes(k);
+    for (int i = 0; i < nc; ++i) counts[i] = 0;
     if (E == 0) return;
     hipStream_t s = g->stream;
     Arena& ar = g->arena;
@@ -757,10 +909,15 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
     R.s = s;
     R.waves = grid_waves(16);
     R.blocks = (int)(R.waves / MO_WAVES);
-    uint64_t* small = push<uint64_t>(ar, 16 + Q_WORDS);
+    uint64_t* small = push<uint64_t>(ar, 32 + Q_WORDS);
     R.out = reinterpret_cast<unsigned long long*>(small);
-    R.qctr = reinterpret_cast<unsigned long long*>(small + 16);
-    fill_u64(small, 16, 0, s);
+    R.qctr = reinterpret_cast<unsigned long long*>(small + 32);
+    fill_u64(small, 32, 0, s);
+    int8_t* lut5 = nullptr;
+    if (k == 5) {
+        lut5 = push<int8_t>(ar, 1024);
+        PG_HIP(hipMemcpyAsync(lut5, lut5_host().v, 1024, hipMemcpyHostToDevice, s));
+    }
     MotifArgs A = base_args(g);
     A.x_lo = 0;
     A.x_hi = E;
@@ -828,16 +985,17 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
             if (m > 0) {
                 set_queue(R, L, items, m);
                 ProfScope ps("motif_last", s, 0.0);
-                k_motif_last4<<<R.blocks, MO_THREADS, 0, s>>>(L);
+                if (k == 4) k_motif_last4<<<R.blocks, MO_THREADS, 0, s>>>(L);
+                else k_motif_last5<<<R.blocks, MO_THREADS, 0, s>>>(L, lut5);
                 PG_HIP(hipGetLastError());
             }
             ar.reset(mk);
         }
     }
-    uint64_t h[16];
+    uint64_t h[32];
     PG_HIP(hipMemcpyAsync(h, small, sizeof(h), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < (k == 3 ? 2 : 6); ++i) counts[i] = h[i];
+    for (int i = 0; i < nc; ++i) counts[i] = h[i];
     if (prof_on() && k == 4) {
         // algorithmic bytes of the fused last level: per input embedding the
         // SoA entry (5 B), the three row-pointer pairs (48 B) and one 4-byte
