@@ -330,7 +330,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
-        "data": "synthetic (seeded R-MAT)",
+        "data": "synthetic (seeded G(n,p))" if w in ("fsm", "motif5") else "synthetic (seeded R-MAT)",
         "config": workload,
         "result": found if isinstance(result, int) else [int(x) for x in result],
         "roofline": roofline,

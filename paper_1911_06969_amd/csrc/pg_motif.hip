@@ -626,10 +626,11 @@ __device__ __forceinline__ bool adj_g(const MotifArgs& A, int32_t a, int32_t u) 
 template <int I>
 __device__ __forceinline__ void last5_from(const MotifArgs& A, const int8_t* __restrict__ lut, int32_t x0,
                                            int32_t x1, int32_t x2, int32_t x3, int m4, int p3,
-                                           unsigned long long* cnt) {
+                                           unsigned long long* cnt, uint64_t& walked) {
     const int32_t xi = I == 0 ? x0 : (I == 1 ? x1 : (I == 2 ? x2 : x3));
-    const int64_t t1 = A.rp[xi + 1];
-    for (int64_t t = A.rp[xi]; t < t1; ++t) {
+    const int64_t t0 = A.rp[xi], t1 = A.rp[xi + 1];
+    walked += (uint64_t)(t1 - t0);
+    for (int64_t t = t0; t < t1; ++t) {
         const int32_t w = A.col[t];
         if (w <= x0 || w == x1 || w == x2 || w == x3) continue;
         if (I == p3 && w <= x3) continue;
@@ -648,10 +649,12 @@ __device__ __forceinline__ void last5_from(const MotifArgs& A, const int8_t* __r
 // extensions u of (v0, v1, v2) from the list of v_I, each extended once more
 template <int I>
 __device__ __forceinline__ void ext4_from(const MotifArgs& A, const int8_t* __restrict__ lut, int32_t v0,
-                                          int32_t v1, int32_t v2, int m3, int p2, unsigned long long* cnt) {
+                                          int32_t v1, int32_t v2, int m3, int p2, unsigned long long* cnt,
+                                          uint64_t& walked, uint64_t& n3) {
     const int32_t vi = I == 0 ? v0 : (I == 1 ? v1 : v2);
-    const int64_t t1 = A.rp[vi + 1];
-    for (int64_t t = A.rp[vi]; t < t1; ++t) {
+    const int64_t t0 = A.rp[vi], t1 = A.rp[vi + 1];
+    walked += (uint64_t)(t1 - t0);
+    for (int64_t t = t0; t < t1; ++t) {
         const int32_t u = A.col[t];
         if (u <= v0 || u == v1 || u == v2) continue;
         if (I == p2 && u <= v2) continue;
@@ -661,11 +664,12 @@ __device__ __forceinline__ void ext4_from(const MotifArgs& A, const int8_t* __re
         const int a1 = I == 1 ? 1 : (I < 1 ? (int)adj_g(A, v1, u) : 0);
         const int a2 = I == 2 ? 1 : (int)adj_g(A, v2, u);
         const int m4 = m3 | (a0 << 3) | (a1 << 4) | (a2 << 5);
+        ++n3;
         // p(3) = I: w's first adjacent position must be at least I
-        if (I <= 0) last5_from<0>(A, lut, v0, v1, v2, u, m4, I, cnt);
-        if (I <= 1) last5_from<1>(A, lut, v0, v1, v2, u, m4, I, cnt);
-        last5_from<2>(A, lut, v0, v1, v2, u, m4, I, cnt);
-        last5_from<3>(A, lut, v0, v1, v2, u, m4, I, cnt);
+        if (I <= 0) last5_from<0>(A, lut, v0, v1, v2, u, m4, I, cnt, walked);
+        if (I <= 1) last5_from<1>(A, lut, v0, v1, v2, u, m4, I, cnt, walked);
+        last5_from<2>(A, lut, v0, v1, v2, u, m4, I, cnt, walked);
+        last5_from<3>(A, lut, v0, v1, v2, u, m4, I, cnt, walked);
     }
 }
 
@@ -673,6 +677,7 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const i
     __shared__ unsigned long long cnt[21];
     for (int i = threadIdx.x; i < 21; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
+    uint64_t walked = 0, n2 = 0, n3 = 0;   // work record: list elements walked, entries
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
@@ -687,10 +692,17 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const i
             const int code = A.code2[e];
             const int m3 = 1 | ((code & 1) << 1) | (((code >> 1) & 1) << 2);
             const int p2 = (code & 1) ? 0 : 1;   // p(2): v2's first adjacent position
-            if (p2 == 0) ext4_from<0>(A, lut, v0, v1, v2, m3, p2, cnt);
-            ext4_from<1>(A, lut, v0, v1, v2, m3, p2, cnt);
-            ext4_from<2>(A, lut, v0, v1, v2, m3, p2, cnt);
+            ++n2;
+            if (p2 == 0) ext4_from<0>(A, lut, v0, v1, v2, m3, p2, cnt, walked, n3);
+            ext4_from<1>(A, lut, v0, v1, v2, m3, p2, cnt, walked, n3);
+            ext4_from<2>(A, lut, v0, v1, v2, m3, p2, cnt, walked, n3);
         }
+    }
+    const uint64_t ws = wave_sum_u64(walked), s2 = wave_sum_u64(n2), s3 = wave_sum_u64(n3);
+    if (lane() == 0) {
+        if (ws) atomicAdd(&A.out[24], (unsigned long long)ws);
+        if (s2) atomicAdd(&A.out[25], (unsigned long long)s2);
+        if (s3) atomicAdd(&A.out[26], (unsigned long long)s3);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 21; i += blockDim.x)
@@ -1001,6 +1013,12 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
         // SoA entry (5 B), the three row-pointer pairs (48 B) and one 4-byte
         // probe per intersection item
         ProfScope ps("motif_last_work", s, 53.0 * (double)h[7] + 4.0 * (double)h[6]);
+    }
+    if (prof_on() && k == 5) {
+        // k = 5: per level-2 entry its SoA entry and a row-pointer pair
+        // (16 B), per level-3 extension a row-pointer pair (16 B), and 4 B
+        // per element of every list walked at levels 3 and 4
+        ProfScope ps("motif_last_work", s, 16.0 * (double)(h[25] + h[26]) + 4.0 * (double)h[24]);
     }
 }
 
