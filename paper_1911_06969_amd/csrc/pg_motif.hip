@@ -43,6 +43,7 @@ constexpr int MO_THREADS = 128;
 constexpr int MO_WAVES = MO_THREADS / WAVE;
 constexpr int MO_STAGE = 512;     // adjacency lists up to this long are staged in LDS
 constexpr int MO_CMAX = 512;      // common-neighbour lists up to this long live in LDS
+constexpr int MO5_WAVES_PER_CU = 32;   // k = 5 last level (16: 53 ms, 32: 43 ms, 48: 43 ms per call on G(n,p) n=100,000, d=8)
 
 enum { ML1_COUNT = 0, ML1_WRITE = 1, ML1_LAST3 = 2 };
 
@@ -925,6 +926,8 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
     R.out = reinterpret_cast<unsigned long long*>(small);
     R.qctr = reinterpret_cast<unsigned long long*>(small + 32);
     fill_u64(small, 32, 0, s);
+    // k = 5: lanes wait on dependent searches, so more waves per CU hide them
+    const int blocks5 = (int)(grid_waves(MO5_WAVES_PER_CU) / MO_WAVES);
     int8_t* lut5 = nullptr;
     if (k == 5) {
         lut5 = push<int8_t>(ar, 1024);
@@ -998,7 +1001,7 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
                 set_queue(R, L, items, m);
                 ProfScope ps("motif_last", s, 0.0);
                 if (k == 4) k_motif_last4<<<R.blocks, MO_THREADS, 0, s>>>(L);
-                else k_motif_last5<<<R.blocks, MO_THREADS, 0, s>>>(L, lut5);
+                else k_motif_last5<<<blocks5, MO_THREADS, 0, s>>>(L, lut5);
                 PG_HIP(hipGetLastError());
             }
             ar.reset(mk);
