@@ -43,7 +43,7 @@ constexpr int MO_THREADS = 128;
 constexpr int MO_WAVES = MO_THREADS / WAVE;
 constexpr int MO_STAGE = 512;     // adjacency lists up to this long are staged in LDS
 constexpr int MO_CMAX = 512;      // common-neighbour lists up to this long live in LDS
-constexpr int MO5_WAVES_PER_CU = 32;   // k = 5 last level (16: 53 ms, 32: 43 ms, 48: 43 ms per call on G(n,p) n=100,000, d=8)
+constexpr int MO5_WAVES_PER_CU = 32;   // k = 5 last level: latency-bound lanes, more waves in flight
 
 enum { ML1_COUNT = 0, ML1_WRITE = 1, ML1_LAST3 = 2 };
 
@@ -612,71 +612,61 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
 // smallest mask over the relabellings of the positions); the table maps a
 // mask to its class (-1 when disconnected).
 //
-// Level 3 (four vertices) is not materialised: each lane takes one L2 entry
-// (v0, v1, v2), walks its canonical extensions u by the rule above and,
-// for each, the canonical extensions w of (v0, v1, v2, u), and adds one to
-// the class of the 10-bit mask.  Adjacency is a binary search in the CSR.
+// Level 3 (four vertices) is not materialised.  A wave takes 64 L2 entries
+// (v0, v1, v2) of one L1 entry (v0, v1), one per lane.  In rounds, every
+// lane walks its entry's canonical extensions u by the rule above and
+// queues each (v2, u, pair mask, p(3)) in the wave's LDS queue until the
+// queue is full (a lane whose push does not fit retries that u in the next
+// round); then the lanes take the queued 4-sets one each, walk their
+// canonical extensions w and add one to the class of each 10-bit mask.  So
+// lanes wait on the degrees of single 4-sets, not of whole subtrees.
+// Adjacency is a binary search in the CSR.
+
+constexpr int M5_Q = 512;   // queued 4-sets per wave
+
+struct M5Lds {
+    int32_t v2[MO_WAVES][M5_Q];
+    int32_t u[MO_WAVES][M5_Q];
+    int32_t m[MO_WAVES][M5_Q];   // pair mask of the 4-set | p(3) << 8
+    uint32_t n[MO_WAVES];
+    unsigned long long cnt[21];
+};
 
 __device__ __forceinline__ bool adj_g(const MotifArgs& A, int32_t a, int32_t u) {
     const int64_t r0 = A.rp[a];
     return member(A.col + r0, (int32_t)(A.rp[a + 1] - r0), u);
 }
 
-// extensions w of (x0, x1, x2, x3) from the list of x_I (I = their first
-// adjacent position), the current pair mask m4 and p3 = p(3)
-template <int I>
-__device__ __forceinline__ void last5_from(const MotifArgs& A, const int8_t* __restrict__ lut, int32_t x0,
-                                           int32_t x1, int32_t x2, int32_t x3, int m4, int p3,
+// canonical extensions w of the 4-set (v0, v1, x2, x3) with pair mask m4 and
+// p(3) = p3, from the lists of positions p3..3
+__device__ __forceinline__ void last5_walk(const MotifArgs& A, const int8_t* __restrict__ lut, int32_t v0,
+                                           int32_t v1, int32_t x2, int32_t x3, int m4, int p3,
                                            unsigned long long* cnt, uint64_t& walked) {
-    const int32_t xi = I == 0 ? x0 : (I == 1 ? x1 : (I == 2 ? x2 : x3));
-    const int64_t t0 = A.rp[xi], t1 = A.rp[xi + 1];
-    walked += (uint64_t)(t1 - t0);
-    for (int64_t t = t0; t < t1; ++t) {
-        const int32_t w = A.col[t];
-        if (w <= x0 || w == x1 || w == x2 || w == x3) continue;
-        if (I == p3 && w <= x3) continue;
-        if (I > 0 && adj_g(A, x0, w)) continue;
-        if (I > 1 && adj_g(A, x1, w)) continue;
-        if (I > 2 && adj_g(A, x2, w)) continue;
-        const int a0 = I == 0 ? 1 : 0;
-        const int a1 = I == 1 ? 1 : (I < 1 ? (int)adj_g(A, x1, w) : 0);
-        const int a2 = I == 2 ? 1 : (I < 2 ? (int)adj_g(A, x2, w) : 0);
-        const int a3 = I == 3 ? 1 : (int)adj_g(A, x3, w);
-        const int c = lut[m4 | (a0 << 6) | (a1 << 7) | (a2 << 8) | (a3 << 9)];
-        if (c >= 0) atomicAdd(&cnt[c], 1ull);   // always connected; the test keeps LDS in bounds
-    }
-}
-
-// extensions u of (v0, v1, v2) from the list of v_I, each extended once more
-template <int I>
-__device__ __forceinline__ void ext4_from(const MotifArgs& A, const int8_t* __restrict__ lut, int32_t v0,
-                                          int32_t v1, int32_t v2, int m3, int p2, unsigned long long* cnt,
-                                          uint64_t& walked, uint64_t& n3) {
-    const int32_t vi = I == 0 ? v0 : (I == 1 ? v1 : v2);
-    const int64_t t0 = A.rp[vi], t1 = A.rp[vi + 1];
-    walked += (uint64_t)(t1 - t0);
-    for (int64_t t = t0; t < t1; ++t) {
-        const int32_t u = A.col[t];
-        if (u <= v0 || u == v1 || u == v2) continue;
-        if (I == p2 && u <= v2) continue;
-        if (I > 0 && adj_g(A, v0, u)) continue;
-        if (I > 1 && adj_g(A, v1, u)) continue;
-        const int a0 = I == 0 ? 1 : 0;
-        const int a1 = I == 1 ? 1 : (I < 1 ? (int)adj_g(A, v1, u) : 0);
-        const int a2 = I == 2 ? 1 : (int)adj_g(A, v2, u);
-        const int m4 = m3 | (a0 << 3) | (a1 << 4) | (a2 << 5);
-        ++n3;
-        // p(3) = I: w's first adjacent position must be at least I
-        if (I <= 0) last5_from<0>(A, lut, v0, v1, v2, u, m4, I, cnt, walked);
-        if (I <= 1) last5_from<1>(A, lut, v0, v1, v2, u, m4, I, cnt, walked);
-        last5_from<2>(A, lut, v0, v1, v2, u, m4, I, cnt, walked);
-        last5_from<3>(A, lut, v0, v1, v2, u, m4, I, cnt, walked);
+    for (int J = p3; J < 4; ++J) {
+        const int32_t xj = J == 0 ? v0 : (J == 1 ? v1 : (J == 2 ? x2 : x3));
+        const int64_t t0 = A.rp[xj], t1 = A.rp[xj + 1];
+        walked += (uint64_t)(t1 - t0);
+        for (int64_t t = t0; t < t1; ++t) {
+            const int32_t w = A.col[t];
+            if (w <= v0 || w == v1 || w == x2 || w == x3) continue;
+            if (J == p3 && w <= x3) continue;
+            if (J > 0 && adj_g(A, v0, w)) continue;
+            if (J > 1 && adj_g(A, v1, w)) continue;
+            if (J > 2 && adj_g(A, x2, w)) continue;
+            const int a0 = J == 0 ? 1 : 0;
+            const int a1 = J == 1 ? 1 : (J < 1 ? (int)adj_g(A, v1, w) : 0);
+            const int a2 = J == 2 ? 1 : (J < 2 ? (int)adj_g(A, x2, w) : 0);
+            const int a3 = J == 3 ? 1 : (int)adj_g(A, x3, w);
+            const int c = lut[m4 | (a0 << 6) | (a1 << 7) | (a2 << 8) | (a3 << 9)];
+            if (c >= 0) atomicAdd(&cnt[c], 1ull);   // always connected; the test keeps LDS in bounds
+        }
     }
 }
 
 __global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const int8_t* __restrict__ lut) {
-    __shared__ unsigned long long cnt[21];
-    for (int i = threadIdx.x; i < 21; i += blockDim.x) cnt[i] = 0;
+    __shared__ M5Lds L;
+    const int w = threadIdx.x / WAVE;
+    for (int i = threadIdx.x; i < 21; i += blockDim.x) L.cnt[i] = 0;
     __syncthreads();
     uint64_t walked = 0, n2 = 0, n3 = 0;   // work record: list elements walked, entries
     QueueCursor cur = queue_start();
@@ -687,16 +677,67 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const i
             const int64_t p = item_seg(item);
             const int32_t x = (int32_t)item_round(item) * WAVE + lane();
             const int32_t s = (int32_t)(A.seg2[p + 1] - A.seg2[p]);
-            if (x >= s) continue;
-            const int64_t e = (int64_t)(A.seg2[p] - A.seg2_base) + x;
-            const int32_t v0 = A.l1_src[p], v1 = A.l1_dst[p], v2 = A.vid2[e];
-            const int code = A.code2[e];
-            const int m3 = 1 | ((code & 1) << 1) | (((code >> 1) & 1) << 2);
-            const int p2 = (code & 1) ? 0 : 1;   // p(2): v2's first adjacent position
-            ++n2;
-            if (p2 == 0) ext4_from<0>(A, lut, v0, v1, v2, m3, p2, cnt, walked, n3);
-            ext4_from<1>(A, lut, v0, v1, v2, m3, p2, cnt, walked, n3);
-            ext4_from<2>(A, lut, v0, v1, v2, m3, p2, cnt, walked, n3);
+            const int32_t v0 = A.l1_src[p], v1 = A.l1_dst[p];
+            bool done = x >= s;
+            int32_t v2 = 0;
+            int m3 = 0, I = 3;
+            int64_t t = 0, t1 = 0;
+            if (!done) {
+                const int64_t e = (int64_t)(A.seg2[p] - A.seg2_base) + x;
+                v2 = A.vid2[e];
+                const int code = A.code2[e];
+                m3 = 1 | ((code & 1) << 1) | (((code >> 1) & 1) << 2);
+                I = (code & 1) ? 0 : 1;   // p(2): v2's first adjacent position
+                const int32_t vi = I == 0 ? v0 : v1;
+                t = A.rp[vi];
+                t1 = A.rp[vi + 1];
+                walked += (uint64_t)(t1 - t);
+                ++n2;
+            }
+            const int p2 = (I == 0) ? 0 : 1;
+            while (ballot(!done) != 0ull) {
+                if (lane() == 0) L.n[w] = 0u;
+                __threadfence_block();
+                wave_sync();
+                // level 3: queue extensions u until the queue is full
+                while (!done) {
+                    if (t >= t1) {   // the next list: positions I + 1 .. 2
+                        if (++I > 2) {
+                            done = true;
+                            break;
+                        }
+                        const int32_t vi = I == 1 ? v1 : v2;
+                        t = A.rp[vi];
+                        t1 = A.rp[vi + 1];
+                        walked += (uint64_t)(t1 - t);
+                        continue;
+                    }
+                    const int32_t u = A.col[t];
+                    bool ok = u > v0 && u != v1 && u != v2 && !(I == p2 && u <= v2);
+                    ok = ok && !(I > 0 && adj_g(A, v0, u)) && !(I > 1 && adj_g(A, v1, u));
+                    if (ok) {
+                        const int a0 = I == 0 ? 1 : 0;
+                        const int a1 = I == 1 ? 1 : (I < 1 ? (int)adj_g(A, v1, u) : 0);
+                        const int a2 = I == 2 ? 1 : (int)adj_g(A, v2, u);
+                        const uint32_t slot = atomicAdd(&L.n[w], 1u);
+                        if (slot >= (uint32_t)M5_Q) break;   // full: retry u next round
+                        L.v2[w][slot] = v2;
+                        L.u[w][slot] = u;
+                        L.m[w][slot] = (m3 | (a0 << 3) | (a1 << 4) | (a2 << 5)) | (I << 8);
+                        ++n3;
+                    }
+                    ++t;
+                }
+                __threadfence_block();
+                wave_sync();
+                // level 4: one queued 4-set per lane
+                const uint32_t nq = min(L.n[w], (uint32_t)M5_Q);
+                for (uint32_t q = lane(); q < nq; q += WAVE) {
+                    const int mq = L.m[w][q];
+                    last5_walk(A, lut, v0, v1, L.v2[w][q], L.u[w][q], mq & 255, mq >> 8, L.cnt, walked);
+                }
+                wave_sync();
+            }
         }
     }
     const uint64_t ws = wave_sum_u64(walked), s2 = wave_sum_u64(n2), s3 = wave_sum_u64(n3);
@@ -707,7 +748,7 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const i
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 21; i += blockDim.x)
-        if (cnt[i]) atomicAdd(&A.out[i], cnt[i]);
+        if (L.cnt[i]) atomicAdd(&A.out[i], L.cnt[i]);
 }
 
 // The 1024-entry class table of five vertices (see above), built once.
