@@ -91,3 +91,14 @@ def test_relabel_invariance(torch):
     g = synth.rmat(9, 4, seed=7)
     h = synth.relabel(g, np.random.default_rng(3).permutation(g.n))
     assert gpu_motifs(g) == gpu_motifs(h)
+
+
+def test_bench_workload_against_esu(torch):
+    """The measured workload at full size: G(n,p), n = 100,000, average
+    degree 8, seed 12 (about 4.3e8 embeddings), against the oracle's ESU."""
+    n = 100_000
+    g = synth.erdos_renyi(n, 8.0 / (n - 1), seed=12)
+    say("motif5 bench workload: er(100000, d=8) seed 12")
+    got = gpu_motifs(g)
+    assert got == [int(x) for x in oracle.motif_esu(g, 5)]
+    assert sum(got) > 4 * 10**8
