@@ -622,9 +622,12 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
 // lanes wait on the degrees of single 4-sets, not of whole subtrees.
 // Adjacency is a binary search in the CSR.
 
-constexpr int M5_Q = 512;   // queued 4-sets per wave
+constexpr int M5_Q = 512;       // queued 4-sets per wave
+constexpr int M5_STAGE = 256;   // lists of v0 and v1 up to this long are staged in LDS
 
 struct M5Lds {
+    int32_t s0[MO_WAVES][M5_STAGE];
+    int32_t s1[MO_WAVES][M5_STAGE];
     int32_t v2[MO_WAVES][M5_Q];
     int32_t u[MO_WAVES][M5_Q];
     int32_t m[MO_WAVES][M5_Q];   // pair mask of the 4-set | p(3) << 8
@@ -637,10 +640,17 @@ __device__ __forceinline__ bool adj_g(const MotifArgs& A, int32_t a, int32_t u) 
     return member(A.col + r0, (int32_t)(A.rp[a + 1] - r0), u);
 }
 
+// the lists of v0 and v1 (shared by the wave's entries): LDS copies or the CSR
+struct M5Lists {
+    const int32_t* l0;
+    const int32_t* l1;
+    int32_t d0, d1;
+};
+
 // canonical extensions w of the 4-set (v0, v1, x2, x3) with pair mask m4 and
 // p(3) = p3, from the lists of positions p3..3
-__device__ __forceinline__ void last5_walk(const MotifArgs& A, const int8_t* __restrict__ lut, int32_t v0,
-                                           int32_t v1, int32_t x2, int32_t x3, int m4, int p3,
+__device__ __forceinline__ void last5_walk(const MotifArgs& A, const M5Lists& S, const int8_t* __restrict__ lut,
+                                           int32_t v0, int32_t v1, int32_t x2, int32_t x3, int m4, int p3,
                                            unsigned long long* cnt, uint64_t& walked) {
     for (int J = p3; J < 4; ++J) {
         const int32_t xj = J == 0 ? v0 : (J == 1 ? v1 : (J == 2 ? x2 : x3));
@@ -650,11 +660,11 @@ __device__ __forceinline__ void last5_walk(const MotifArgs& A, const int8_t* __r
             const int32_t w = A.col[t];
             if (w <= v0 || w == v1 || w == x2 || w == x3) continue;
             if (J == p3 && w <= x3) continue;
-            if (J > 0 && adj_g(A, v0, w)) continue;
-            if (J > 1 && adj_g(A, v1, w)) continue;
+            if (J > 0 && member(S.l0, S.d0, w)) continue;
+            if (J > 1 && member(S.l1, S.d1, w)) continue;
             if (J > 2 && adj_g(A, x2, w)) continue;
             const int a0 = J == 0 ? 1 : 0;
-            const int a1 = J == 1 ? 1 : (J < 1 ? (int)adj_g(A, v1, w) : 0);
+            const int a1 = J == 1 ? 1 : (J < 1 ? (int)member(S.l1, S.d1, w) : 0);
             const int a2 = J == 2 ? 1 : (J < 2 ? (int)adj_g(A, x2, w) : 0);
             const int a3 = J == 3 ? 1 : (int)adj_g(A, x3, w);
             const int c = lut[m4 | (a0 << 6) | (a1 << 7) | (a2 << 8) | (a3 << 9)];
@@ -678,6 +688,24 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const i
             const int32_t x = (int32_t)item_round(item) * WAVE + lane();
             const int32_t s = (int32_t)(A.seg2[p + 1] - A.seg2[p]);
             const int32_t v0 = A.l1_src[p], v1 = A.l1_dst[p];
+            M5Lists S;
+            {
+                const int64_t r0 = A.rp[v0], q0 = A.rp[v1];
+                S.d0 = (int32_t)(A.rp[v0 + 1] - r0);
+                S.d1 = (int32_t)(A.rp[v1 + 1] - q0);
+                S.l0 = A.col + r0;
+                S.l1 = A.col + q0;
+                if (S.d0 <= M5_STAGE) {
+                    for (int i = lane(); i < S.d0; i += WAVE) L.s0[w][i] = A.col[r0 + i];
+                    S.l0 = &L.s0[w][0];
+                }
+                if (S.d1 <= M5_STAGE) {
+                    for (int i = lane(); i < S.d1; i += WAVE) L.s1[w][i] = A.col[q0 + i];
+                    S.l1 = &L.s1[w][0];
+                }
+                __threadfence_block();
+                wave_sync();
+            }
             bool done = x >= s;
             int32_t v2 = 0;
             int m3 = 0, I = 3;
@@ -714,10 +742,10 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const i
                     }
                     const int32_t u = A.col[t];
                     bool ok = u > v0 && u != v1 && u != v2 && !(I == p2 && u <= v2);
-                    ok = ok && !(I > 0 && adj_g(A, v0, u)) && !(I > 1 && adj_g(A, v1, u));
+                    ok = ok && !(I > 0 && member(S.l0, S.d0, u)) && !(I > 1 && member(S.l1, S.d1, u));
                     if (ok) {
                         const int a0 = I == 0 ? 1 : 0;
-                        const int a1 = I == 1 ? 1 : (I < 1 ? (int)adj_g(A, v1, u) : 0);
+                        const int a1 = I == 1 ? 1 : (I < 1 ? (int)member(S.l1, S.d1, u) : 0);
                         const int a2 = I == 2 ? 1 : (int)adj_g(A, v2, u);
                         const uint32_t slot = atomicAdd(&L.n[w], 1u);
                         if (slot >= (uint32_t)M5_Q) break;   // full: retry u next round
@@ -734,10 +762,11 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last5(MotifArgs A, const i
                 const uint32_t nq = min(L.n[w], (uint32_t)M5_Q);
                 for (uint32_t q = lane(); q < nq; q += WAVE) {
                     const int mq = L.m[w][q];
-                    last5_walk(A, lut, v0, v1, L.v2[w][q], L.u[w][q], mq & 255, mq >> 8, L.cnt, walked);
+                    last5_walk(A, S, lut, v0, v1, L.v2[w][q], L.u[w][q], mq & 255, mq >> 8, L.cnt, walked);
                 }
                 wave_sync();
             }
+            wave_sync();   // the next item overwrites the staged lists
         }
     }
     const uint64_t ws = wave_sum_u64(walked), s2 = wave_sum_u64(n2), s3 = wave_sum_u64(n3);
