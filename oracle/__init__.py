@@ -8,7 +8,8 @@ may import this package.  It shares no code with the HIP library.
 Layers:
   * ``oracle.cpp`` (built to ``liboracle.so`` with g++/OpenMP): clique
     enumeration in the degree order, ESU motif enumeration, closed-form
-    pieces, edge-subset enumeration with domain (MNI) support.
+    pieces, edge-subset enumeration with domain (MNI) support for patterns
+    of up to four edges (pattern index by enumerated tables).
   * ``brute.py``: brute force over vertex subsets and over injective maps,
     for graphs of a dozen vertices.
   * ``closed_form.py``: exact 4-motif counts from non-induced counts.
@@ -150,29 +151,37 @@ def motif_parts(g, nthreads: int = 0) -> dict:
     return {k: int(v) for k, v in zip(keys, out)}
 
 
+FSM_SHAPES = ("edge", "wedge", "triangle", "path4", "star3", "path5", "star4", "fork", "cycle4", "paw")
+
+
 def fsm_num_patterns(max_edges: int, n_labels: int) -> int:
+    """Size of the dense index of labelled patterns with 1..max_edges edges
+    (max_edges <= 4), counted by enumerating the label tuples of each shape."""
     return int(_load().or_fsm_num_patterns(max_edges, n_labels))
 
 
 def fsm_pattern_index(shape: int, labels, n_labels: int) -> int:
-    lab, pl = _c(list(labels) + [0] * (4 - len(labels)), np.int32)
+    """Dense index of the pattern of `shape` whose positions carry `labels`
+    (any of the tuples naming it)."""
+    lab, pl = _c(list(labels) + [0] * (5 - len(labels)), np.int32)
     return int(_load().or_fsm_pattern_index(shape, pl, n_labels))
 
 
 def fsm_supports_all(g, max_edges: int, nthreads: int = 0):
     """Unfiltered MNI support of every labelled pattern with 1..max_edges
-    edges at its dense index, and the number of embeddings per size."""
+    edges (max_edges <= 4) at its dense index, and the number of embeddings
+    per size."""
     assert g.labels is not None and g.n_labels > 0
     rp, prp = _c(g.row_ptr, np.int64)
     col, pcol = _c(g.col, np.int32)
     lab, plab = _c(g.labels, np.int32)
     npat = fsm_num_patterns(max_edges, g.n_labels)
     sup = np.zeros(npat, dtype=np.uint64)
-    cnt = np.zeros(3, dtype=np.uint64)
+    cnt = np.zeros(4, dtype=np.uint64)
     rc = _load().or_fsm_supports(g.n, prp, pcol, plab, g.n_labels, max_edges,
                                  sup.ctypes.data, cnt.ctypes.data, nthreads)
     if rc != 0:
-        raise ValueError("unsupported max_edges")
+        raise ValueError("unsupported max_edges or label count")
     return sup, cnt[:max_edges]
 
 

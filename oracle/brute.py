@@ -5,7 +5,7 @@ Everything here follows a definition directly, with no pruning:
   * k-motifs: every k-subset whose induced subgraph is connected, grouped by
     isomorphism class (sections 2.1-2.2, vertex-induced embeddings); for
     k = 5 the class is the smallest relabelled adjacency mask.
-  * FSM: for each labelled pattern with at most 3 edges, every injective,
+  * FSM: for each labelled pattern with at most 4 edges, every injective,
     label-preserving map of its vertices into the graph that sends pattern
     edges to graph edges; the minimum-image (domain) support is the smallest
     number of distinct images over the pattern's vertices (section 2.2).
@@ -153,50 +153,55 @@ def connected_subsets(g, k: int) -> int:
 
 # shape id -> (number of vertices, edges between pattern vertex positions)
 SHAPES = {
-    0: (2, [(0, 1)]),                    # single edge, labels (a, b)
-    1: (3, [(0, 1), (0, 2)]),            # wedge, labels (centre, leaf, leaf)
-    2: (3, [(0, 1), (0, 2), (1, 2)]),    # triangle
-    3: (4, [(0, 1), (1, 2), (2, 3)]),    # path, labels along the path
-    4: (4, [(0, 1), (0, 2), (0, 3)]),    # star, labels (centre, leaves)
+    0: (2, [(0, 1)]),                            # single edge, labels (a, b)
+    1: (3, [(0, 1), (0, 2)]),                    # wedge, labels (centre, leaf, leaf)
+    2: (3, [(0, 1), (0, 2), (1, 2)]),            # triangle
+    3: (4, [(0, 1), (1, 2), (2, 3)]),            # path on 4 vertices, labels along the path
+    4: (4, [(0, 1), (0, 2), (0, 3)]),            # 3-star, labels (centre, leaves)
+    5: (5, [(0, 1), (1, 2), (2, 3), (3, 4)]),    # path on 5 vertices
+    6: (5, [(0, 1), (0, 2), (0, 3), (0, 4)]),    # 4-star
+    7: (5, [(0, 1), (0, 2), (0, 3), (3, 4)]),    # fork: centre, two leaves, leg (middle, end)
+    8: (4, [(0, 1), (1, 2), (2, 3), (3, 0)]),    # 4-cycle, labels around the cycle
+    9: (4, [(0, 1), (0, 2), (0, 3), (2, 3)]),    # paw: degree-3 vertex, pendant, the two others
 }
-SHAPE_EDGES = {0: 1, 1: 2, 2: 3, 3: 3, 4: 3}
+SHAPE_EDGES = {s: len(e) for s, (_, e) in SHAPES.items()}
 
 
-def pattern_table(max_edges: int, L: int):
-    """The dense pattern numbering, generated block by block in order:
-    edges (a<=b), wedges (centre c, leaves a<=b), triangles (a<=b<=c),
-    paths (a,b,c,d) <= (d,c,b,a), stars (centre c, leaves a<=b<=c);
-    each block in lexicographic order.  Returns a list of (shape, labels)
-    whose position is the index."""
-    table = []
-    r = range(L)
-    if max_edges >= 1:
-        table += [(0, (a, b)) for a in r for b in r if a <= b]
-    if max_edges >= 2:
-        table += [(1, (c, a, b)) for c in r for a in r for b in r if a <= b]
-    if max_edges >= 3:
-        table += [(2, (a, b, c)) for a in r for b in r for c in r if a <= b <= c]
-        table += [(3, t) for t in itertools.product(r, repeat=4) if t <= t[::-1]]
-        table += [(4, (c, a, b, d)) for c in r for a in r for b in r for d in r if a <= b <= d]
-    return table
+def _automorphisms(shape: int) -> list:
+    """Position permutations that map the shape's edge set onto itself."""
+    nv, edges = SHAPES[shape]
+    es = {frozenset(e) for e in edges}
+    return [p for p in itertools.permutations(range(nv))
+            if {frozenset((p[a], p[b])) for a, b in edges} == es]
 
 
 def canonical_labels(shape: int, labels) -> tuple:
-    """Representative label tuple of a labelled shape under its symmetries."""
+    """Representative label tuple of a labelled shape: the smallest tuple
+    over the shape's automorphisms (a label tuple read through each)."""
     lab = tuple(labels)
-    if shape == 0:
-        return tuple(sorted(lab))
-    if shape == 1:
-        return (lab[0],) + tuple(sorted(lab[1:]))
-    if shape == 2:
-        return tuple(sorted(lab))
-    if shape == 3:
-        return min(lab, lab[::-1])
-    return (lab[0],) + tuple(sorted(lab[1:]))
+    return min(tuple(lab[p[i]] for i in range(len(lab))) for p in _automorphisms(shape))
+
+
+def pattern_table(max_edges: int, L: int):
+    """The dense pattern numbering, block by block in shape order (edge,
+    wedge, triangle, 4-path, 3-star, 5-path, 4-star, fork, 4-cycle, paw);
+    within a block the representative label tuples (canonical_labels) in
+    lexicographic order.  Returns a list of (shape, labels) whose position is
+    the index."""
+    table = []
+    for shape in sorted(SHAPES):
+        if SHAPE_EDGES[shape] > max_edges:
+            continue
+        nv = SHAPES[shape][0]
+        autos = _automorphisms(shape)
+        for t in itertools.product(range(L), repeat=nv):
+            if all(tuple(t[p[i]] for i in range(nv)) >= t for p in autos):
+                table.append((shape, t))
+    return table
 
 
 def pattern_index(shape: int, labels, L: int, max_edges: int = 3) -> int:
-    table = pattern_table(max_edges, L)
+    table = pattern_table(max(max_edges, SHAPE_EDGES[shape]), L)
     return table.index((shape, canonical_labels(shape, labels)))
 
 

@@ -27,6 +27,7 @@
  *    label-preserving subgraph isomorphisms.
  */
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -354,91 +355,132 @@ extern "C" void or_motif_parts(i64 n, const i64* rp, const i32* col, u64* parts,
 
 /* ==================================================================== FSM */
 
-/* Dense index of a labelled pattern with at most 3 edges over L labels.
- * shape: 0 edge (a<=b), 1 wedge (centre c; leaves a<=b), 2 triangle
- * (a<=b<=c), 3 path (a,b,c,d) read from the end that gives the smaller
- * sequence, 4 star (centre c; leaves a<=b<=c).  Blocks are laid out in
- * that order. */
-static u64 pairs_count(u64 L) { return L * (L + 1) / 2; }
-static u64 triples_count(u64 L) { return L * (L + 1) * (L + 2) / 6; }
-/* rank of a multiset a<=b<=c in lexicographic order of sorted triples */
-static u64 triple_rank(u64 a, u64 b, u64 c, u64 L) {
-    u64 r = 0;
-    for (u64 x = 0; x < a; ++x) r += (L - x) * (L - x + 1) / 2;
-    for (u64 y = a; y < b; ++y) r += (L - y);
-    r += c - b;
-    return r;
-}
-static u64 pair_rank(u64 a, u64 b, u64 L) {
-    u64 r = 0;
-    for (u64 x = 0; x < a; ++x) r += L - x;
-    return r + (b - a);
+/* Labelled patterns with 1..4 edges.  A shape is a connected unlabelled
+ * graph with numbered vertices (positions); a labelled pattern is a shape
+ * with one label per position.  Tuples that a symmetry of the shape maps
+ * onto each other name one pattern, represented by the tuple that
+ * canonical_tuple() returns.  The dense index lists the shapes in the order
+ * below and, inside a shape, its representative tuples in lexicographic
+ * order:
+ *   0 edge        (a, b)
+ *   1 wedge       (centre, leaf, leaf)
+ *   2 triangle    (a, b, c)
+ *   3 path P4     labels along the path
+ *   4 star K1,3   (centre, leaf, leaf, leaf)
+ *   5 path P5     labels along the path
+ *   6 star K1,4   (centre, four leaves)
+ *   7 fork        (vertex of degree 3, its two leaves, the middle vertex of
+ *                  its leg of length 2, the end of that leg)
+ *   8 cycle C4    labels around the cycle
+ *   9 paw         (triangle vertex of degree 3, its pendant vertex, the two
+ *                  other triangle vertices)
+ * Shapes 0, 1-2, 3-4 and 5-9 have 1, 2, 3 and 4 edges. */
+static const int SHAPE_NV[10] = {2, 3, 3, 4, 4, 5, 5, 5, 4, 4};
+static const int SHAPE_NE[10] = {1, 2, 3, 3, 3, 4, 4, 4, 4, 4};
+static const int N_SHAPES = 10;
+
+/* the representative of label tuple t of shape s, in place */
+static void canonical_tuple(int s, int* t) {
+    const int n = SHAPE_NV[s];
+    switch (s) {
+        case 0: case 2:                      /* every position alike */
+            std::sort(t, t + n);
+            break;
+        case 1: case 4: case 6:              /* leaves of a star */
+            std::sort(t + 1, t + n);
+            break;
+        case 3: case 5: {                    /* a path read from either end */
+            int r[5];
+            for (int i = 0; i < n; ++i) r[i] = t[n - 1 - i];
+            if (std::lexicographical_compare(r, r + n, t, t + n)) std::copy(r, r + n, t);
+            break;
+        }
+        case 7:                              /* the fork's two leaves */
+            std::sort(t + 1, t + 3);
+            break;
+        case 8: {                            /* a cycle: rotations and reflections */
+            int best[4] = {t[0], t[1], t[2], t[3]};
+            for (int rot = 0; rot < 4; ++rot)
+                for (int dir = 0; dir < 2; ++dir) {
+                    int c[4];
+                    for (int i = 0; i < 4; ++i) c[i] = dir ? t[(rot - i + 4) % 4] : t[(rot + i) % 4];
+                    if (std::lexicographical_compare(c, c + 4, best, best + 4)) std::copy(c, c + 4, best);
+                }
+            std::copy(best, best + 4, t);
+            break;
+        }
+        case 9:                              /* the paw's two triangle vertices of degree 2 */
+            std::sort(t + 2, t + 4);
+            break;
+    }
 }
 
-extern "C" u64 or_fsm_num_patterns(int max_edges, int L_) {
-    u64 L = (u64)L_;
-    u64 t = 0;
-    if (max_edges >= 1) t += pairs_count(L);
-    if (max_edges >= 2) t += L * pairs_count(L);
-    if (max_edges >= 3) t += triples_count(L) + (L * L * L * L + L * L) / 2 + L * triples_count(L);
-    return t;
+/* Index tables by enumeration: every label tuple of a shape, in
+ * lexicographic order, is tested for being its own representative; the
+ * representatives get consecutive numbers. */
+struct PatternIndex {
+    int L = -1, max_edges = -1;
+    u64 base[N_SHAPES + 1];
+    std::vector<int32_t> rank[N_SHAPES];     /* tuple code -> rank in its block, or -1 */
+
+    static u64 code_of(const int* t, int n, u64 L) {
+        u64 c = 0;
+        for (int i = 0; i < n; ++i) c = c * L + (u64)t[i];
+        return c;
+    }
+    void build(int L_, int me) {
+        if (L_ == L && me == max_edges) return;
+        L = L_;
+        max_edges = me;
+        base[0] = 0;
+        for (int s = 0; s < N_SHAPES; ++s) {
+            rank[s].clear();
+            u64 count = 0;
+            if (SHAPE_NE[s] <= me) {
+                const int n = SHAPE_NV[s];
+                u64 size = 1;
+                for (int i = 0; i < n; ++i) size *= (u64)L;
+                rank[s].assign((size_t)size, -1);
+                int t[5], c[5];
+                for (u64 x = 0; x < size; ++x) {
+                    u64 r = x;
+                    for (int i = n - 1; i >= 0; --i) { t[i] = (int)(r % (u64)L); r /= (u64)L; }
+                    std::copy(t, t + n, c);
+                    canonical_tuple(s, c);
+                    if (std::equal(t, t + n, c)) rank[s][(size_t)x] = (int32_t)count++;
+                }
+            }
+            base[s + 1] = base[s] + count;
+        }
+    }
+    u64 total() const { return base[N_SHAPES]; }
+    /* index of the pattern of shape s whose positions carry labels lab */
+    u64 index(int s, const int* lab) const {
+        int t[5];
+        std::copy(lab, lab + SHAPE_NV[s], t);
+        canonical_tuple(s, t);
+        return base[s] + (u64)rank[s][(size_t)code_of(t, SHAPE_NV[s], (u64)L)];
+    }
+};
+
+static PatternIndex g_index;
+
+/* label tuples of 5 positions are enumerated in full: keep the tables small */
+static bool index_fits(int max_edges, int L) {
+    const double size = std::pow((double)L, max_edges >= 4 ? 5.0 : 4.0);
+    return L >= 1 && max_edges >= 1 && max_edges <= 4 && size <= (double)(1 << 26);
 }
 
-/* Rank of a path label sequence among the sequences x with x <= reverse(x)
- * (each path pattern read from the end giving the smaller sequence), in
- * lexicographic order.  Built once per label count by walking all L^4
- * sequences in order. */
-static std::vector<u64> g_path_rank;
-static u64 g_path_rank_L = 0;
-static void build_path_rank(u64 L) {
-    if (g_path_rank_L == L) return;
-    g_path_rank.assign((size_t)(L * L * L * L), ~0ULL);
-    u64 r = 0;
-    for (u64 x = 0; x < L * L * L * L; ++x) {
-        u64 p0 = x / (L * L * L), p1 = (x / (L * L)) % L, p2 = (x / L) % L, p3 = x % L;
-        u64 rev = ((p3 * L + p2) * L + p1) * L + p0;
-        if (x <= rev) g_path_rank[x] = r++;
-    }
-    g_path_rank_L = L;
-}
-static u64 path_rank(u64 a, u64 b, u64 c, u64 d, u64 L) {
-    return g_path_rank[(size_t)(((a * L + b) * L + c) * L + d)];
-}
-
-static u64 pattern_index(int shape, const int* lab, u64 L) {
-    u64 base = 0;
-    if (shape == 0) {
-        u64 a = std::min(lab[0], lab[1]), b = std::max(lab[0], lab[1]);
-        return pair_rank(a, b, L);
-    }
-    base += pairs_count(L);
-    if (shape == 1) { /* lab = centre, leaf, leaf */
-        u64 a = std::min(lab[1], lab[2]), b = std::max(lab[1], lab[2]);
-        return base + (u64)lab[0] * pairs_count(L) + pair_rank(a, b, L);
-    }
-    base += L * pairs_count(L);
-    if (shape == 2) {
-        int s[3] = {lab[0], lab[1], lab[2]};
-        std::sort(s, s + 3);
-        return base + triple_rank(s[0], s[1], s[2], L);
-    }
-    base += triples_count(L);
-    if (shape == 3) { /* lab = a,b,c,d along the path */
-        u64 f = ((u64)lab[0] * L + lab[1]) * L * L + (u64)lab[2] * L + lab[3];
-        u64 r = ((u64)lab[3] * L + lab[2]) * L * L + (u64)lab[1] * L + lab[0];
-        if (r < f) return base + path_rank(lab[3], lab[2], lab[1], lab[0], L);
-        return base + path_rank(lab[0], lab[1], lab[2], lab[3], L);
-    }
-    base += (L * L * L * L + L * L) / 2;
-    /* shape 4: lab = centre, leaf, leaf, leaf */
-    int s[3] = {lab[1], lab[2], lab[3]};
-    std::sort(s, s + 3);
-    return base + (u64)lab[0] * triples_count(L) + triple_rank(s[0], s[1], s[2], L);
+extern "C" u64 or_fsm_num_patterns(int max_edges, int L) {
+    if (!index_fits(max_edges, L)) return 0;
+    g_index.build(L, max_edges);
+    return g_index.total();
 }
 
 extern "C" u64 or_fsm_pattern_index(int shape, const int* lab, int L) {
-    build_path_rank((u64)L);
-    return pattern_index(shape, lab, (u64)L);
+    if (shape < 0 || shape >= N_SHAPES || !index_fits(SHAPE_NE[shape], L)) return ~0ULL;
+    g_index.build(L, std::max(g_index.max_edges, SHAPE_NE[shape]));
+    return g_index.index(shape, lab);
 }
 
 struct FsmCtx {
@@ -446,6 +488,7 @@ struct FsmCtx {
     const i64* rp; const i32* col; const i32* lab; int L; int K;
     const i32* eu; const i32* ev;             /* undirected edges, id order */
     const i64* inc_ptr; const i64* inc;       /* edges incident to a vertex */
+    const PatternIndex* index;
     std::vector<u64>* keys;                   /* (pattern, position, vertex) */
     u64* emb_count;                           /* embeddings per level */
 };
@@ -454,23 +497,92 @@ static inline bool share(const FsmCtx& C, i64 x, i64 y) {
     return C.eu[x] == C.eu[y] || C.eu[x] == C.ev[y] || C.ev[x] == C.eu[y] || C.ev[x] == C.ev[y];
 }
 
+/* Shape of a connected edge set on vertices 0..nv-1 with adjacency adj and
+ * degrees deg, and its vertices in the shape's position order. */
+static int shape_positions(int ne, int nv, int adj[5][5], const int* deg, int* pos) {
+    int dmax = 0;
+    for (int i = 0; i < nv; ++i) dmax = std::max(dmax, deg[i]);
+    auto first_of_degree = [&](int d, int skip) {
+        for (int i = 0; i < nv; ++i) if (deg[i] == d && i != skip) return i;
+        return -1;
+    };
+    auto walk = [&](int start) {     /* a path or a cycle, from start */
+        int prev = -1, cur = start;
+        for (int s = 0; s < nv; ++s) {
+            pos[s] = cur;
+            int nxt = -1;
+            for (int j = 0; j < nv; ++j)
+                if (j != prev && j != cur && adj[cur][j]) { nxt = j; break; }
+            prev = cur;
+            cur = nxt;
+        }
+    };
+    auto star = [&](int centre) {
+        int k = 1;
+        pos[0] = centre;
+        for (int i = 0; i < nv; ++i) if (i != centre) pos[k++] = i;
+    };
+    if (ne == 1) { pos[0] = 0; pos[1] = 1; return 0; }
+    if (ne == 2) { star(first_of_degree(2, -1)); return 1; }
+    if (ne == 3 && nv == 3) { pos[0] = 0; pos[1] = 1; pos[2] = 2; return 2; }
+    if (ne == 3) {
+        if (dmax == 3) { star(first_of_degree(3, -1)); return 4; }
+        walk(first_of_degree(1, -1));
+        return 3;
+    }
+    /* four edges */
+    if (nv == 5) {
+        if (dmax == 4) { star(first_of_degree(4, -1)); return 6; }
+        if (dmax == 2) { walk(first_of_degree(1, -1)); return 5; }
+        const int c = first_of_degree(3, -1);
+        int k = 1, x = -1;
+        pos[0] = c;
+        for (int j = 0; j < nv; ++j) {
+            if (!adj[c][j]) continue;
+            if (deg[j] == 1) pos[k++] = j;
+            else x = j;
+        }
+        pos[3] = x;
+        for (int j = 0; j < nv; ++j) if (j != c && adj[x][j]) pos[4] = j;
+        return 7;
+    }
+    if (dmax == 2) { walk(0); return 8; }
+    pos[0] = first_of_degree(3, -1);
+    pos[1] = first_of_degree(1, -1);
+    pos[2] = first_of_degree(2, -1);
+    pos[3] = first_of_degree(2, pos[2]);
+    return 9;
+}
+
 /* Classify one connected edge set and emit its domain keys. */
 static void fsm_emit(const FsmCtx& C, const std::vector<i64>& es) {
-    i32 vs[4]; int nv = 0;
+    i32 vs[5]; int nv = 0;
     auto addv = [&](i32 v) {
         for (int i = 0; i < nv; ++i) if (vs[i] == v) return;
         vs[nv++] = v;
     };
     for (i64 e : es) { addv(C.eu[e]); addv(C.ev[e]); }
-    int adj[4][4] = {{0}};
-    auto pos = [&](i32 v) { for (int i = 0; i < nv; ++i) if (vs[i] == v) return i; return -1; };
+    int adj[5][5] = {{0}};
+    auto at = [&](i32 v) { for (int i = 0; i < nv; ++i) if (vs[i] == v) return i; return -1; };
     for (i64 e : es) {
-        int a = pos(C.eu[e]), b = pos(C.ev[e]);
+        int a = at(C.eu[e]), b = at(C.ev[e]);
         adj[a][b] = adj[b][a] = 1;
     }
-    /* canonical code: minimum over vertex permutations of
-     * (labels in order, adjacency bits in order) */
-    int perm[4] = {0, 1, 2, 3};
+    int deg[5] = {0, 0, 0, 0, 0};
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) deg[i] += adj[i][j];
+    const int ne = (int)es.size();
+    int pos[5];
+    const int shape = shape_positions(ne, nv, adj, deg, pos);
+    int lab[5];
+    for (int i = 0; i < nv; ++i) lab[i] = C.lab[vs[pos[i]]];
+    const u64 pid = C.index->index(shape, lab);
+    C.emb_count[ne - 1]++;
+    /* domains: a canonical code per vertex order (labels in order, then the
+     * absent pairs in order); the orders that minimise it differ by the
+     * pattern's label-preserving automorphisms, so vertex vs[pp[i]] of any
+     * minimising order pp belongs to the domain of code position i */
+    int perm[5] = {0, 1, 2, 3, 4};
     u64 best = ~0ULL;
     std::vector<std::vector<int>> best_perms;
     do {
@@ -481,48 +593,9 @@ static void fsm_emit(const FsmCtx& C, const std::vector<i64>& es) {
         if (code < best) { best = code; best_perms.clear(); }
         if (code == best) best_perms.push_back(std::vector<int>(perm, perm + nv));
     } while (std::next_permutation(perm, perm + nv));
-    /* shape and labels of canonical positions */
-    const std::vector<int>& p0 = best_perms[0];
-    int deg[4] = {0, 0, 0, 0};
-    for (int i = 0; i < nv; ++i)
-        for (int j = 0; j < nv; ++j) deg[i] += adj[p0[i]][p0[j]];
-    int lab[4];
-    int ne = (int)es.size();
-    int shape = -1;
-    if (ne == 1) { shape = 0; lab[0] = C.lab[vs[p0[0]]]; lab[1] = C.lab[vs[p0[1]]]; }
-    else if (ne == 2) {
-        shape = 1;
-        int c = 0; for (int i = 0; i < 3; ++i) if (deg[i] == 2) c = i;
-        int k = 1; lab[0] = C.lab[vs[p0[c]]];
-        for (int i = 0; i < 3; ++i) if (i != c) lab[k++] = C.lab[vs[p0[i]]];
-    } else if (nv == 3) {
-        shape = 2; for (int i = 0; i < 3; ++i) lab[i] = C.lab[vs[p0[i]]];
-    } else {
-        int dmax = 0; for (int i = 0; i < 4; ++i) dmax = std::max(dmax, deg[i]);
-        if (dmax == 3) {
-            shape = 4;
-            int c = 0; for (int i = 0; i < 4; ++i) if (deg[i] == 3) c = i;
-            int k = 1; lab[0] = C.lab[vs[p0[c]]];
-            for (int i = 0; i < 4; ++i) if (i != c) lab[k++] = C.lab[vs[p0[i]]];
-        } else {
-            shape = 3;  /* walk the path from one end */
-            int cur = 0; for (int i = 0; i < 4; ++i) if (deg[i] == 1) { cur = i; break; }
-            int prev = -1;
-            for (int s = 0; s < 4; ++s) {
-                lab[s] = C.lab[vs[p0[cur]]];
-                int nxt = -1;
-                for (int j = 0; j < 4; ++j) if (j != prev && j != cur && adj[p0[cur]][p0[j]]) nxt = j;
-                prev = cur; cur = nxt;
-            }
-        }
-    }
-    u64 pid = pattern_index(shape, lab, (u64)C.L);
-    C.emb_count[ne - 1]++;
-    /* every minimising permutation maps canonical position i to a vertex of
-     * the orbit of that position: all of them enter the domain of i */
     for (const auto& pp : best_perms)
         for (int i = 0; i < nv; ++i)
-            C.keys->push_back(((pid * 4 + (u64)i) << 32) | (u64)(uint32_t)vs[pp[i]]);
+            C.keys->push_back(((pid * 8 + (u64)i) << 32) | (u64)(uint32_t)vs[pp[i]]);
 }
 
 static void fsm_esu(const FsmCtx& C, std::vector<i64>& sub, std::vector<i64> ext) {
@@ -553,12 +626,13 @@ static void fsm_esu(const FsmCtx& C, std::vector<i64>& sub, std::vector<i64> ext
 }
 
 /* Unfiltered MNI supports of every labelled connected pattern with
- * 1..max_edges edges (max_edges <= 3), written at the dense index.
- * emb_count[j] = number of (j+1)-edge embeddings. */
+ * 1..max_edges edges (max_edges <= 4), written at the dense index.
+ * emb_count[j] = number of (j+1)-edge embeddings (j < 4).  Returns -1 for
+ * sizes the index tables do not cover. */
 extern "C" int or_fsm_supports(i64 n, const i64* rp, const i32* col, const i32* labels, int L,
                                int max_edges, u64* supports, u64* emb_count, int nthreads) {
     ThreadScope threads(nthreads);
-    if (max_edges < 1 || max_edges > 3) return -1;
+    if (!index_fits(max_edges, L)) return -1;
     std::vector<i32> eu, ev;
     for (i64 u = 0; u < n; ++u)
         for (i64 j = rp[u]; j < rp[u + 1]; ++j)
@@ -571,19 +645,19 @@ extern "C" int or_fsm_supports(i64 n, const i64* rp, const i32* col, const i32* 
         std::vector<i64> fill(inc_ptr.begin(), inc_ptr.end() - 1);
         for (i64 e = 0; e < E; ++e) { inc[fill[eu[e]]++] = e; inc[fill[ev[e]]++] = e; }
     }
-    const u64 np = or_fsm_num_patterns(max_edges, L);
-    build_path_rank((u64)L);
+    g_index.build(L, max_edges);
+    const u64 np = g_index.total();
     for (u64 i = 0; i < np; ++i) supports[i] = 0;
-    for (int j = 0; j < 3; ++j) emb_count[j] = 0;
+    for (int j = 0; j < 4; ++j) emb_count[j] = 0;
 
     int nt = omp_get_max_threads();
     std::vector<std::vector<u64>> keys((size_t)nt);
-    std::vector<u64> cnt((size_t)nt * 3, 0);
+    std::vector<u64> cnt((size_t)nt * 4, 0);
 #pragma omp parallel
     {
         int t = omp_get_thread_num();
         FsmCtx C{n, rp, col, labels, L, max_edges, eu.data(), ev.data(), inc_ptr.data(), inc.data(),
-                 &keys[t], &cnt[(size_t)t * 3]};
+                 &g_index, &keys[t], &cnt[(size_t)t * 4]};
 #pragma omp for schedule(dynamic, 256)
         for (i64 e = 0; e < E; ++e) {
             std::vector<i64> sub{e};
@@ -598,7 +672,7 @@ extern "C" int or_fsm_supports(i64 n, const i64* rp, const i32* col, const i32* 
         }
     }
     for (int t = 0; t < nt; ++t)
-        for (int j = 0; j < 3; ++j) emb_count[j] += cnt[(size_t)t * 3 + j];
+        for (int j = 0; j < 4; ++j) emb_count[j] += cnt[(size_t)t * 4 + j];
     size_t total = 0;
     for (auto& k : keys) total += k.size();
     std::vector<u64> all;
@@ -606,15 +680,16 @@ extern "C" int or_fsm_supports(i64 n, const i64* rp, const i32* col, const i32* 
     for (auto& k : keys) { all.insert(all.end(), k.begin(), k.end()); std::vector<u64>().swap(k); }
     __gnu_parallel::sort(all.begin(), all.end());
     all.erase(std::unique(all.begin(), all.end()), all.end());
-    /* distinct vertices per (pattern, position); support = min over positions */
-    std::vector<u64> dom((size_t)np * 4, 0);
-    std::vector<uint8_t> has((size_t)np * 4, 0);
-    for (u64 key : all) { dom[key >> 32]++; has[key >> 32] = 1; }
-    for (u64 p = 0; p < np; ++p) {
-        u64 s = ~0ULL; bool any = false;
-        for (int i = 0; i < 4; ++i)
-            if (has[p * 4 + i]) { s = std::min(s, dom[p * 4 + i]); any = true; }
-        supports[p] = any ? s : 0;
+    /* keys are sorted by (pattern, position): the distinct vertices of each
+     * position are a run; the support is the smallest run of the pattern */
+    size_t i = 0;
+    while (i < all.size()) {
+        const u64 pp = all[i] >> 32;
+        size_t j = i;
+        while (j < all.size() && (all[j] >> 32) == pp) ++j;
+        const u64 pid = pp / 8, run = (u64)(j - i);
+        if (supports[pid] == 0 || run < supports[pid]) supports[pid] = run;
+        i = j;
     }
     return 0;
 }
