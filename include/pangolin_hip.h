@@ -218,6 +218,26 @@ int pg_batch_free(pg_batch* b);
 int pg_batch_count_motifs(pg_batch* b, int k, const int64_t* ids, int64_t n_ids, uint64_t* counts);
 
 /*
+ * Allocation-free form of pg_batch_count_motifs, for callers that cannot
+ * allocate device memory during the call (tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors, and it runs
+ * the same kernel.  It calls no device allocation routine: its temporaries
+ * (the ids, the queue items, the output rows and the queue counter) live in
+ * one fixed device array of 2 MiB per GPU, set up on the GPU's first call
+ * and held until the process ends.
+ * Limits: n_ids (the batch size when ids == NULL) at most
+ * PG_BATCH_STATIC_MAX_IDS, else PG_EINVAL; each graph is split into at most
+ * 4 queue items.
+ * Every call on a GPU uses that GPU's one array, which keeps the previous
+ * call's contents (the call clears what must start at zero).  Calls that
+ * overlapped on one GPU would race on it, so the library serialises them
+ * with a per-device lock: a concurrent caller waits.  The batch's device is
+ * made current for the call and the caller's current device is restored.
+ */
+#define PG_BATCH_STATIC_MAX_IDS 16384
+int pg_batch_count_motifs_noalloc(pg_batch* b, int k, const int64_t* ids, int64_t n_ids, uint64_t* counts);
+
+/*
  * Asynchronous slots for a serving loop.  A slot owns pinned host buffers,
  * device buffers for up to max_ids graphs and a captured HIP graph of one
  * batched launch (copy in, clear, count, copy out), replayed on the slot's

@@ -26,7 +26,7 @@ EXPORTS = (
     "pg_set_memory_budget", "pg_graph_set_option", "pg_count_cliques", "pg_list_cliques", "pg_count_motifs",
     "pg_fsm",
     "pg_fsm_num_patterns", "pg_fsm_pattern_key", "pg_batch_load", "pg_batch_free",
-    "pg_batch_count_motifs", "pg_batch_slot_create", "pg_batch_slot_submit", "pg_batch_slot_query",
+    "pg_batch_count_motifs", "pg_batch_count_motifs_noalloc", "pg_batch_slot_create", "pg_batch_slot_submit", "pg_batch_slot_query",
     "pg_batch_slot_wait", "pg_batch_slot_free", "pg_batch_work_estimate",
     "pg_batch_set_params", "pg_last_error", "pg_set_allocator", "pg_profile_enable",
     "pg_profile_reset", "pg_profile_query", "pg_profile_list", "pg_version",
@@ -70,6 +70,7 @@ def load_library(path: str | None = None):
     lib.pg_batch_load.argtypes = [i64, ptr, ptr, ptr, ctypes.c_uint, ptr, P(ptr)]
     lib.pg_batch_free.argtypes = [ptr]
     lib.pg_batch_count_motifs.argtypes = [ptr, cint, ptr, i64, ptr]
+    lib.pg_batch_count_motifs_noalloc.argtypes = [ptr, cint, ptr, i64, ptr]
     lib.pg_batch_slot_create.argtypes = [ptr, i64, ptr, P(ptr)]
     lib.pg_batch_slot_submit.argtypes = [ptr, cint, ptr, i64]
     lib.pg_batch_slot_query.argtypes = [ptr]
@@ -261,6 +262,26 @@ def pg_batch_count_motifs(b, k: int, ids=None, n_graphs: int | None = None) -> n
     idv, pid = _host(ids, np.int64)
     out = np.zeros((idv.shape[0], width), dtype=np.uint64)
     _check(lib.pg_batch_count_motifs(b, int(k), pid, idv.shape[0], ctypes.c_void_p(out.ctypes.data)))
+    return out
+
+
+PG_BATCH_STATIC_MAX_IDS = 16384
+
+
+def pg_batch_count_motifs_noalloc(b, k: int, ids=None, n_graphs: int | None = None) -> np.ndarray:
+    """pg_batch_count_motifs through the allocation-free entry point (at most
+    PG_BATCH_STATIC_MAX_IDS graphs per call)."""
+    lib = load_library()
+    width = 2 if k == 3 else 6
+    if ids is None:
+        if n_graphs is None:
+            raise ValueError("n_graphs is needed when ids is None")
+        out = np.zeros((n_graphs, width), dtype=np.uint64)
+        _check(lib.pg_batch_count_motifs_noalloc(b, int(k), None, 0, ctypes.c_void_p(out.ctypes.data)))
+        return out
+    idv, pid = _host(ids, np.int64)
+    out = np.zeros((idv.shape[0], width), dtype=np.uint64)
+    _check(lib.pg_batch_count_motifs_noalloc(b, int(k), pid, idv.shape[0], ctypes.c_void_p(out.ctypes.data)))
     return out
 
 

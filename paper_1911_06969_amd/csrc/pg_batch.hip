@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -502,6 +503,101 @@ int pg_batch_count_motifs(pg_batch* b, int k, const int64_t* ids, int64_t n_ids,
                 throw;
             }
         }
+    });
+}
+
+}  // extern "C"
+
+// ----------------------------------------------- allocation-free entry point
+//
+// pg_batch_count_motifs_noalloc keeps its temporaries in one fixed device
+// array instead of the batch's arena: the caller's ids, the queue items, the
+// output rows and the queue counter.  Each GPU holds its own copy of the
+// array (at its own address) until the process ends.  Host code never
+// passes the array's name to a kernel or a copy: that name is a host-side
+// stand-in, not a device address.  The device address is looked up once per
+// device with hipGetSymbolAddress and kept.
+
+namespace pg {
+
+constexpr int64_t NA_MAX_IDS = PG_BATCH_STATIC_MAX_IDS;
+constexpr int NA_PARTS = 4;   // queue items per graph at most
+constexpr size_t na_align(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t NA_IDS = 0;
+constexpr size_t NA_ITEMS = NA_IDS + na_align(sizeof(int64_t) * NA_MAX_IDS);
+constexpr size_t NA_OUT = NA_ITEMS + na_align(sizeof(BatchItem) * NA_MAX_IDS * NA_PARTS);
+constexpr size_t NA_NEXT = NA_OUT + na_align(sizeof(uint64_t) * 6 * NA_MAX_IDS);
+constexpr size_t NA_BYTES = NA_NEXT + 256;
+static_assert(NA_BYTES <= (size_t(2) << 20), "the allocation-free scratch is 2 MiB at most");
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+constexpr int NA_MAX_DEVICES = 64;
+static std::mutex g_na_mu[NA_MAX_DEVICES];
+static unsigned char* g_na_ptr[NA_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the
+// device's first call); the caller holds g_na_mu[dev].
+static unsigned char* scratch_ptr(int dev) {
+    if (!g_na_ptr[dev]) {
+        void* p = nullptr;
+        PG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        PG_REQUIRE(p != nullptr, PG_EDEVICE, "no device address for the static scratch array");
+        g_na_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    return g_na_ptr[dev];
+}
+
+}  // namespace pg
+
+extern "C" {
+
+int pg_batch_count_motifs_noalloc(pg_batch* b, int k, const int64_t* ids, int64_t n_ids, uint64_t* counts) {
+    return guarded([&] {
+        PG_REQUIRE(b != nullptr && counts != nullptr, PG_EINVAL, "NULL argument");
+        PG_REQUIRE(k == 3 || k == 4, PG_EUNSUPPORTED, "motif size must be 3 or 4");
+        PG_REQUIRE(b->device >= 0 && b->device < NA_MAX_DEVICES, PG_EDEVICE, "device index out of range");
+        std::vector<int64_t> all;
+        if (ids == nullptr) {
+            n_ids = b->n_graphs;
+            all.resize((size_t)n_ids);
+            std::iota(all.begin(), all.end(), 0);
+            ids = all.data();
+        }
+        PG_REQUIRE(n_ids >= 0, PG_EINVAL, "n_ids < 0");
+        PG_REQUIRE(n_ids <= NA_MAX_IDS, PG_EINVAL,
+                   "n_ids exceeds PG_BATCH_STATIC_MAX_IDS (" + std::to_string(NA_MAX_IDS) + ")");
+        for (int64_t i = 0; i < n_ids; ++i)
+            PG_REQUIRE(ids[i] >= 0 && ids[i] < b->n_graphs, PG_EINVAL, "graph id out of range");
+        if (n_ids == 0) return;
+        const int width = k == 3 ? 2 : 6;
+        std::vector<BatchItem> items;
+        build_items(b, ids, n_ids, items, NA_PARTS);
+        PG_REQUIRE((int64_t)items.size() <= NA_MAX_IDS * NA_PARTS, PG_EINVAL, "too many queue items");
+
+        int prev = 0;
+        PG_HIP(hipGetDevice(&prev));
+        PG_HIP(hipSetDevice(b->device));
+        struct Restore {
+            int d;
+            ~Restore() { (void)hipSetDevice(d); }
+        } restore{prev};
+        std::lock_guard<std::mutex> lock(g_na_mu[b->device]);
+        unsigned char* base = scratch_ptr(b->device);
+        int64_t* d_ids = reinterpret_cast<int64_t*>(base + NA_IDS);
+        BatchItem* d_items = reinterpret_cast<BatchItem*>(base + NA_ITEMS);
+        uint64_t* d_out = reinterpret_cast<uint64_t*>(base + NA_OUT);
+        unsigned long long* d_next = reinterpret_cast<unsigned long long*>(base + NA_NEXT);
+        hipStream_t s = b->stream;
+        PG_HIP(hipMemcpyAsync(d_ids, ids, sizeof(int64_t) * n_ids, hipMemcpyHostToDevice, s));
+        PG_HIP(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+        // the array keeps the previous call's rows: clear this call's (a fill
+        // kernel); launch_batch clears the queue counter the same way
+        fill_u64(d_out, (int64_t)n_ids * width, 0, s);
+        launch_batch(b, k, d_ids, d_items, (int64_t)items.size(), d_out, d_next, s);
+        PG_HIP(hipMemcpyAsync(counts, d_out, sizeof(uint64_t) * n_ids * width, hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        prof_flush();
     });
 }
 
