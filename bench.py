@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=2000)
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "profiles", "batch_tuning.json"),
+                    help="batch-kernel parameters picked by the autotuner (applied when present)")
+    ap.add_argument("--tuning-out", default=os.path.join(ROOT, "profiles", "batch_tuning.json"),
+                    help="where --workload tune-batch writes its result")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch of the dominant kernel (from rocprofv3 --pmc)")
     return ap.parse_args()
@@ -183,9 +187,10 @@ def main():
         n_cu = torch.cuda.get_device_properties(0).multi_processor_count
         best, table = tune.tune(h, ids, n_cu, log=lambda r: print(json.dumps(r), flush=True))
         binding.pg_batch_free(h)
-        out = os.path.join(ROOT, "gpurun_out", "batch_tuning.json")
+        out = args.tuning_out
         os.makedirs(os.path.dirname(out), exist_ok=True)
-        tune.save(out, best, table, "sample: 20,000 of the 100,000 graphs of the motif batch (seed 9)")
+        tune.save(out, best, table, "sample: 20,000 of the 100,000 graphs of the motif batch (seed 9), "
+                                    "command: python bench.py --workload tune-batch")
         print(json.dumps({"best": best}), flush=True)
         return
     if w == "rmat-sweep":
@@ -407,8 +412,8 @@ def measure_batch_and_serve(args):
     b = synth.motif_batch()
     h = binding.pg_batch_load(b.voff, b.row_ptr, b.col)
     try:
-        tuned = os.path.join(ROOT, "profiles", "batch_tuning.json")
-        if os.path.exists(tuned):
+        tuned = args.tuning
+        if tuned and os.path.exists(tuned):
             from paper_1911_06969_amd import tune
             best = tune.load(tuned)
             binding.pg_batch_set_params(h, best["block_threads"], best["split_work"], best["grid_blocks"])
@@ -439,6 +444,14 @@ def measure_batch_and_serve(args):
             G.close()
         note(f"plain: {pdt:.2f} s for {sample.shape[0]} graphs")
         assert np.array_equal(plain, counts[sample]), "plain and batched counts differ"
+        # plain path with the same kernel: one pg_batch_count_motifs launch per graph
+        binding.pg_batch_count_motifs(h, 4, sample[:8])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        same = np.concatenate([binding.pg_batch_count_motifs(h, 4, sample[i:i + 1]) for i in range(sample.shape[0])])
+        sdt = time.perf_counter() - t
+        note(f"plain, same kernel: {sdt:.2f} s for {sample.shape[0]} graphs")
+        assert np.array_equal(same, counts[sample]), "per-graph launches and the batched run differ"
         # the sample's share of the batch's work, to compare like with like
         work = binding.pg_batch_work_estimate(h, b.n_graphs)
         frac = float(work[sample].sum() / work.sum())
@@ -447,6 +460,9 @@ def measure_batch_and_serve(args):
         out["plain_seconds_for_sample"] = pdt
         out["plain_sample_work_fraction"] = frac
         out["batched_over_plain_graphs_per_s"] = out["batched_graphs_per_s"] / out["plain_graphs_per_s"]
+        out["plain_same_kernel_graphs_per_s"] = sample.shape[0] / sdt
+        out["plain_same_kernel_seconds_for_sample"] = sdt
+        out["batched_over_plain_same_kernel"] = out["batched_graphs_per_s"] / out["plain_same_kernel_graphs_per_s"]
         # serving: Poisson arrivals at fractions of the batched capacity
         fp = serve.graph_footprints(b.voff, b.row_ptr)
         srv = serve.Server(h, fp, n_slots=4, max_batch=1024, budget_bytes=8 << 30)

@@ -163,7 +163,7 @@ int pg_count_motifs(pg_graph* g, int k, uint64_t* counts);
  * each extension the embeddings of patterns whose support is below
  * min_support are dropped (Filter; pattern is frequent iff support >=
  * min_support).
- *   max_edges     1..3
+ *   max_edges     1..4 (4 needs n_labels <= 32, else PG_EUNSUPPORTED)
  *   min_support   threshold sigma
  *   supports      host uint64[supports_len]; supports[i] = support of the
  *                 pattern with dense index i if it is frequent, else 0
@@ -175,22 +175,34 @@ int pg_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports,
            size_t supports_len, size_t* n_frequent);
 
 /*
- * Size of the dense pattern index used by pg_fsm for n_labels labels.  The
- * index enumerates, block after block and each block in lexicographic order
- * of its label tuple:
- *   shape 0  single edge, labels (a, b) with a <= b
- *   shape 1  wedge, labels (centre, a, b) with a <= b            [>= 2 edges]
- *   shape 2  triangle, labels (a, b, c) with a <= b <= c         [>= 3 edges]
- *   shape 3  path on 4 vertices, labels (a, b, c, d) read from the end that
- *            makes the tuple lexicographically smaller            [>= 3 edges]
- *   shape 4  3-star, labels (centre, a, b, c) with a <= b <= c    [>= 3 edges]
- * Returns 0 for arguments out of range.
+ * Size of the dense pattern index used by pg_fsm for n_labels labels.  A
+ * labelled pattern is a shape whose numbered vertex positions carry labels;
+ * label tuples that a symmetry of the shape maps onto each other name one
+ * pattern, represented by the lexicographically smallest of them.  The
+ * index enumerates the shapes in this order, and within a shape its
+ * representative tuples in lexicographic order:
+ *   shape 0  single edge (a, b)                                   [1 edge]
+ *   shape 1  wedge (centre, leaf, leaf)                           [2 edges]
+ *   shape 2  triangle (a, b, c)                                   [3 edges]
+ *   shape 3  path on 4 vertices, labels along the path
+ *   shape 4  3-star (centre, three leaves)
+ *   shape 5  path on 5 vertices, labels along the path            [4 edges]
+ *   shape 6  4-star (centre, four leaves)
+ *   shape 7  fork (the vertex of degree 3, its two leaves, the middle vertex
+ *            of its leg of length 2, the end of that leg)
+ *   shape 8  4-cycle, labels around the cycle
+ *   shape 9  paw (the triangle vertex of degree 3, its pendant vertex, the
+ *            two other triangle vertices)
+ * so that, for instance, a wedge is (c, a, b) with a <= b and a path
+ * (a, b, c, d) is read from the end that gives the smaller tuple.  Returns
+ * 0 for arguments out of range.
  */
 uint64_t pg_fsm_num_patterns(int max_edges, int n_labels);
 
-/* Decodes a dense index into its shape and its 2-4 labels (host outputs;
- * unused label slots are set to -1). */
-int pg_fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* labels4);
+/* Decodes a dense index into its shape (0..9) and the labels of its 2-5
+ * positions (host outputs; labels5 is int32[5], unused slots are set to
+ * -1). */
+int pg_fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* labels5);
 
 /* ---------------------------------------------------- many small graphs */
 
@@ -268,10 +280,12 @@ int pg_batch_slot_free(pg_batch_slot* s);
  * quantity the batch scheduler orders graphs by. */
 int pg_batch_work_estimate(const pg_batch* b, double* work);
 
-/* Tile/work-split parameters of the batch kernel.  0 keeps the current
- * value.  block_threads in {64, 128, 256, 512}; waves_per_graph_split is
- * the estimated work above which a graph is split into several queue
- * items; grid_blocks is the persistent grid size. */
+/* Tile/work-split parameters of the batch kernel (the values an autotuner
+ * picks).  0 keeps the current value.  block_threads in {64, 128, 256,
+ * 512}; split_work is the estimated work above which a graph is split into
+ * several queue items; grid_blocks is the persistent grid size.  They apply
+ * to every later pg_batch_count_motifs call, and slots re-capture their
+ * launch with them at their next submission. */
 int pg_batch_set_params(pg_batch* b, int block_threads, double split_work, int grid_blocks);
 
 /* --------------------------------------------------------------- runtime */

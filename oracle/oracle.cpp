@@ -141,48 +141,71 @@ static int classify(const i32* vs, int k, const i64* rp, const i32* col) {
  * (bit b(b-1)/2 + a for positions a < b).  Classes are the connected
  * 5-vertex graphs numbered by (edge count, smallest mask over all 120
  * relabellings); the table is built once by trying every relabelling. */
+/* Classes of 5-vertex graphs, built by discovery: the 1024 pair masks are
+ * visited by increasing (edge count, mask value); a connected mask that is
+ * isomorphic to no class found so far opens a new class.  So classes come
+ * out ordered by edge count, and each class's first mask is its smallest,
+ * which is the documented order.  of[m] = the class isomorphic to m (-1 for
+ * a disconnected mask).  Isomorphism is tested on 5x5 adjacency matrices
+ * under all 120 vertex orders. */
 struct Class5 {
     signed char of[1024];
-    Class5() {
-        int perm[5] = {0, 1, 2, 3, 4};
-        std::vector<int> canon(1024, 1 << 20);
+    static void matrix(int m, bool a[5][5]) {
+        int bit = 0;
+        for (int j = 0; j < 5; ++j)
+            for (int i = 0; i < 5; ++i) a[i][j] = false;
+        for (int j = 1; j < 5; ++j)
+            for (int i = 0; i < j; ++i, ++bit) a[i][j] = a[j][i] = (m >> bit) & 1;
+    }
+    static bool isomorphic(int x, int y) {
+        if (__builtin_popcount(x) != __builtin_popcount(y)) return false;
+        bool A[5][5], B[5][5];
+        matrix(x, A);
+        matrix(y, B);
+        int p[5] = {0, 1, 2, 3, 4};
         do {
-            for (int m = 0; m < 1024; ++m) {
-                int r = 0;
-                for (int b = 1; b < 5; ++b)
-                    for (int a = 0; a < b; ++a)
-                        if ((m >> (b * (b - 1) / 2 + a)) & 1) {
-                            int x = std::min(perm[a], perm[b]), y = std::max(perm[a], perm[b]);
-                            r |= 1 << (y * (y - 1) / 2 + x);
-                        }
-                canon[m] = std::min(canon[m], r);
-            }
-        } while (std::next_permutation(perm, perm + 5));
-        std::vector<int> codes;
-        for (int m = 0; m < 1024; ++m) {
-            /* connected: grow the component of vertex 0 */
-            int comp = 1, grew = 1;
-            while (grew) {
-                grew = 0;
-                for (int b = 1; b < 5; ++b)
-                    for (int a = 0; a < b; ++a)
-                        if (((m >> (b * (b - 1) / 2 + a)) & 1) && (((comp >> a) ^ (comp >> b)) & 1)) {
-                            comp |= (1 << a) | (1 << b);
-                            grew = 1;
-                        }
-            }
-            of[m] = -1;
-            if (comp == 31) codes.push_back(canon[m]);
+            bool same = true;
+            for (int i = 0; i < 5 && same; ++i)
+                for (int j = 0; j < 5 && same; ++j) same = A[i][j] == B[p[i]][p[j]];
+            if (same) return true;
+        } while (std::next_permutation(p, p + 5));
+        return false;
+    }
+    static bool connected(int m) {
+        bool A[5][5];
+        matrix(m, A);
+        bool seen[5] = {true, false, false, false, false};
+        int stack[5] = {0}, top = 1, count = 1;
+        while (top) {
+            int v = stack[--top];
+            for (int u = 0; u < 5; ++u)
+                if (A[v][u] && !seen[u]) {
+                    seen[u] = true;
+                    stack[top++] = u;
+                    ++count;
+                }
         }
-        std::sort(codes.begin(), codes.end(), [](int x, int y) {
-            int px = __builtin_popcount(x), py = __builtin_popcount(y);
-            return px != py ? px < py : x < y;
-        });
-        codes.erase(std::unique(codes.begin(), codes.end()), codes.end());
-        /* isomorphic masks share the code, so only connected masks match one */
-        for (int m = 0; m < 1024; ++m)
-            for (size_t c = 0; c < codes.size(); ++c)
-                if (codes[c] == canon[m]) of[m] = (signed char)c;
+        return count == 5;
+    }
+    Class5() {
+        std::vector<int> order(1024);
+        for (int m = 0; m < 1024; ++m) order[m] = m;
+        std::stable_sort(order.begin(), order.end(),
+                         [](int x, int y) { return __builtin_popcount(x) < __builtin_popcount(y); });
+        std::vector<int> reps;
+        for (int m : order) {
+            if (!connected(m)) continue;
+            bool known = false;
+            for (int r : reps)
+                if (isomorphic(m, r)) { known = true; break; }
+            if (!known) reps.push_back(m);
+        }
+        for (int m = 0; m < 1024; ++m) {
+            of[m] = -1;
+            if (!connected(m)) continue;
+            for (size_t c = 0; c < reps.size(); ++c)
+                if (isomorphic(m, reps[c])) { of[m] = (signed char)c; break; }
+        }
     }
 };
 

@@ -220,7 +220,7 @@ def pg_fsm(g, max_edges: int, min_support: int, n_labels: int):
 
 def pg_fsm_pattern_key(index: int, max_edges: int, n_labels: int):
     shape = ctypes.c_int()
-    lab = np.zeros(4, dtype=np.int32)
+    lab = np.zeros(5, dtype=np.int32)
     _check(load_library().pg_fsm_pattern_key(int(index), int(max_edges), int(n_labels), ctypes.byref(shape),
                                              ctypes.c_void_p(lab.ctypes.data)))
     return int(shape.value), [int(x) for x in lab if x >= 0]

@@ -15,7 +15,7 @@ void prof_enable(bool on);
 void prof_reset();
 bool prof_query(const char* name, double* ms, uint64_t* launches, double* units);
 std::string prof_list();
-int fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* labels4);
+int fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* labels5);
 
 static int g_live_objects = 0;
 
@@ -184,8 +184,10 @@ int pg_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports,
            size_t* n_frequent) {
     return guarded([&] {
         PG_REQUIRE(g != nullptr && supports != nullptr, PG_EINVAL, "NULL argument");
-        PG_REQUIRE(max_edges >= 1 && max_edges <= 3, PG_EUNSUPPORTED, "max_edges must be in [1, 3]");
+        PG_REQUIRE(max_edges >= 1 && max_edges <= 4, PG_EUNSUPPORTED, "max_edges must be in [1, 4]");
         PG_REQUIRE(g->n_labels > 0, PG_EINVAL, "FSM needs a labelled graph");
+        PG_REQUIRE(fsm_num_patterns(max_edges, g->n_labels) > 0, PG_EUNSUPPORTED,
+                   "patterns of four edges need at most 32 labels");
         const uint64_t np = fsm_num_patterns(max_edges, g->n_labels);
         PG_REQUIRE(supports_len >= np, PG_EINVAL, "supports array too short");
         require_device();
@@ -198,17 +200,17 @@ int pg_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports,
 }
 
 uint64_t pg_fsm_num_patterns(int max_edges, int n_labels) {
-    if (max_edges < 1 || max_edges > 3 || n_labels < 1 || n_labels > 64) return 0;
+    if (max_edges < 1 || max_edges > 4 || n_labels < 1 || n_labels > 64) return 0;
     return fsm_num_patterns(max_edges, n_labels);
 }
 
-int pg_fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* labels4) {
+int pg_fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* labels5) {
     return guarded([&] {
-        PG_REQUIRE(shape != nullptr && labels4 != nullptr, PG_EINVAL, "NULL argument");
-        PG_REQUIRE(max_edges >= 1 && max_edges <= 3 && n_labels >= 1 && n_labels <= 64, PG_EINVAL,
+        PG_REQUIRE(shape != nullptr && labels5 != nullptr, PG_EINVAL, "NULL argument");
+        PG_REQUIRE(max_edges >= 1 && max_edges <= 4 && n_labels >= 1 && n_labels <= 64, PG_EINVAL,
                    "arguments out of range");
         PG_REQUIRE(index < fsm_num_patterns(max_edges, n_labels), PG_EINVAL, "index out of range");
-        fsm_pattern_key(index, max_edges, n_labels, shape, labels4);
+        fsm_pattern_key(index, max_edges, n_labels, shape, labels5);
     });
 }
 

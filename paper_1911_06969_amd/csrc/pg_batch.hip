@@ -276,6 +276,7 @@ struct pg_batch {
     int block_threads = 256;
     double split_work = 4.0e6;
     int grid_blocks = 0;
+    int params_gen = 0;        // bumped by pg_batch_set_params; slots re-capture when it moves
     Arena arena;
 };
 
@@ -314,6 +315,14 @@ static void build_items(pg_batch* b, const int64_t* ids, int64_t n_ids, std::vec
     for (size_t i = 0; i < tmp.size(); ++i) items[i] = tmp[i].second;
 }
 
+// Persistent grid of the batch kernel: the tuned size, else one or two
+// workgroups per CU; never more workgroups than items.
+static int batch_grid(const pg_batch* b, int64_t n_items) {
+    const int per_cu = b->block_threads >= 512 ? 1 : 2;
+    const int blocks = b->grid_blocks > 0 ? b->grid_blocks : device_info().n_cu * per_cu;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(blocks, n_items));
+}
+
 static void launch_batch(pg_batch* b, int k, const int64_t* d_ids, const BatchItem* d_items, int64_t n_items,
                          uint64_t* d_out, unsigned long long* d_next, hipStream_t s) {
     BatchArgs A;
@@ -328,9 +337,7 @@ static void launch_batch(pg_batch* b, int k, const int64_t* d_ids, const BatchIt
     A.out = reinterpret_cast<unsigned long long*>(d_out);
     A.k = k;
     fill_u64(reinterpret_cast<uint64_t*>(d_next), 1, 0, s);
-    const int per_cu = b->block_threads >= 512 ? 1 : 2;
-    int blocks = b->grid_blocks > 0 ? b->grid_blocks : device_info().n_cu * per_cu;
-    blocks = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, n_items));
+    const int blocks = batch_grid(b, n_items);
     ProfScope ps("batch_motifs", s, (double)n_items);
     switch (b->block_threads) {
         case 64: k_batch_motifs<64><<<blocks, 64, 0, s>>>(A); break;
@@ -448,6 +455,7 @@ int pg_batch_set_params(pg_batch* b, int block_threads, double split_work, int g
         }
         if (split_work > 0) b->split_work = split_work;
         if (grid_blocks > 0) b->grid_blocks = grid_blocks;
+        b->params_gen++;
     });
 }
 
@@ -621,6 +629,7 @@ struct pg_batch_slot {
     bool pending = false;
     int pending_k = 4;
     int64_t pending_n = 0;
+    int params_gen = -1;               // batch parameters the captured graphs were made with
     ~pg_batch_slot() {
         for (int i = 0; i < 2; ++i) {
             if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
@@ -658,7 +667,9 @@ static void capture_slot(pg_batch_slot* S, int k) {
     A.next = S->d_next.as<unsigned long long>();
     A.out = S->d_out.as<unsigned long long>();
     A.k = k;
-    const int blocks = device_info().n_cu * (b->block_threads >= 512 ? 1 : 2);
+    // the same grid as a direct launch; the item count is only known on the
+    // device, so the slot's maximum bounds it
+    const int blocks = batch_grid(b, S->max_items);
     hipGraph_t gr = nullptr;
     PG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
@@ -688,8 +699,19 @@ static void capture_slot(pg_batch_slot* S, int k) {
         (void)hipGraphDestroy(gr);
         throw Error{PG_EDEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(e3)};
     }
+    if (S->exec[k - 3]) (void)hipGraphExecDestroy(S->exec[k - 3]);
+    if (S->graph[k - 3]) (void)hipGraphDestroy(S->graph[k - 3]);
     S->graph[k - 3] = gr;
     S->exec[k - 3] = ex;
+}
+
+// (Re)captures both graphs when the batch's parameters changed since the
+// last capture; the slot must be idle.
+static void ensure_captured(pg_batch_slot* S) {
+    if (S->params_gen == S->b->params_gen) return;
+    capture_slot(S, 3);
+    capture_slot(S, 4);
+    S->params_gen = S->b->params_gen;
 }
 
 }  // namespace pg
@@ -723,8 +745,7 @@ int pg_batch_slot_create(pg_batch* b, int64_t max_ids, void* stream, pg_batch_sl
             S->d_out.reserve(sizeof(uint64_t) * max_ids * 6);
             S->d_next.reserve(sizeof(uint64_t));
             PG_HIP(hipEventCreateWithFlags(&S->done, hipEventDisableTiming));
-            capture_slot(S, 3);
-            capture_slot(S, 4);
+            ensure_captured(S);
         } catch (...) {
             delete S;
             throw;
@@ -742,6 +763,7 @@ int pg_batch_slot_submit(pg_batch_slot* S, int k, const int64_t* ids, int64_t n_
         PG_REQUIRE(n_ids >= 0 && n_ids <= S->max_ids, PG_EINVAL, "too many ids for this slot");
         for (int64_t i = 0; i < n_ids; ++i)
             PG_REQUIRE(ids[i] >= 0 && ids[i] < S->b->n_graphs, PG_EINVAL, "graph id out of range");
+        ensure_captured(S);   // pg_batch_set_params since the last submission
         std::vector<BatchItem> items;
         build_items(S->b, ids, n_ids, items, SLOT_PARTS);
         std::memcpy(S->h_ids, ids, sizeof(int64_t) * n_ids);

@@ -47,7 +47,11 @@ namespace pg {
 struct PatBase {
     int64_t L;
     int64_t p2, t3, paths;
-    int64_t edge, wedge, tri, path, star, total;
+    int64_t edge, wedge, tri, path, star;
+    // four edges: 5-path, 4-star, fork, 4-cycle, paw
+    int64_t q4, s4n, p5n, fkn, c4n, pwn;
+    int64_t p5, star4, fork, cyc, paw;
+    int64_t total;
 };
 
 __host__ __device__ inline PatBase pat_base(int64_t L, int max_edges) {
@@ -61,7 +65,21 @@ __host__ __device__ inline PatBase pat_base(int64_t L, int max_edges) {
     B.tri = B.wedge + L * B.p2;
     B.path = B.tri + B.t3;
     B.star = B.path + B.paths;
-    B.total = max_edges >= 3 ? B.star + L * B.t3 : (max_edges == 2 ? B.tri : B.p2);
+    // label multisets of four leaves; palindromic 5-sequences; cycles up to
+    // rotation and reflection (Burnside over the 8 symmetries of a square)
+    B.q4 = L * (L + 1) * (L + 2) * (L + 3) / 24;
+    B.p5n = (L * L * L * L * L + L * L * L) / 2;
+    B.s4n = L * B.q4;
+    B.fkn = L * B.p2 * L * L;
+    B.c4n = (L * L * L * L + 2 * L * L * L + 3 * L * L + 2 * L) / 8;
+    B.pwn = L * L * B.p2;
+    B.p5 = B.star + L * B.t3;
+    B.star4 = B.p5 + B.p5n;
+    B.fork = B.star4 + B.s4n;
+    B.cyc = B.fork + B.fkn;
+    B.paw = B.cyc + B.c4n;
+    B.total = max_edges >= 4 ? B.paw + B.pwn
+              : max_edges == 3 ? B.p5 : (max_edges == 2 ? B.tri : B.p2);
     return B;
 }
 
@@ -78,16 +96,69 @@ __host__ __device__ inline int64_t triple_rank(int64_t a, int64_t b, int64_t c, 
     return r + (c - b);
 }
 
+// Largest label count for patterns of four edges: the 5-path table has
+// n_labels^5 entries.
+constexpr int FSM4_MAX_LABELS = 32;
+
 uint64_t fsm_num_patterns(int max_edges, int n_labels) {
-    if (max_edges < 1 || max_edges > 3 || n_labels < 1) return 0;
+    if (max_edges < 1 || max_edges > 4 || n_labels < 1) return 0;
+    if (max_edges == 4 && n_labels > FSM4_MAX_LABELS) return 0;
     return (uint64_t)pat_base(n_labels, max_edges).total;
+}
+
+// Representative label tuples of the table-ranked shapes, as host checks of
+// a tuple code (digits base L, first position most significant).
+static bool path_rep(int64_t x, int64_t L, int n) {   // x <= its reversal
+    int64_t d[5];
+    for (int i = n - 1; i >= 0; --i) { d[i] = x % L; x /= L; }
+    for (int i = 0; i < n; ++i) {
+        if (d[i] != d[n - 1 - i]) return d[i] < d[n - 1 - i];
+    }
+    return true;
+}
+
+static bool sorted_rep(int64_t x, int64_t L) {   // non-decreasing 4-tuple
+    int64_t d[4];
+    for (int i = 3; i >= 0; --i) { d[i] = x % L; x /= L; }
+    return d[0] <= d[1] && d[1] <= d[2] && d[2] <= d[3];
+}
+
+static bool cycle_rep(int64_t x, int64_t L) {    // smallest of the 8 readings
+    int64_t d[4];
+    for (int i = 3; i >= 0; --i) { d[i] = x % L; x /= L; }
+    for (int r = 0; r < 4; ++r)
+        for (int dir = 0; dir < 2; ++dir) {
+            for (int i = 0; i < 4; ++i) {
+                const int64_t c = dir ? d[(r - i + 4) % 4] : d[(r + i) % 4];
+                if (c != d[i]) {
+                    if (c < d[i]) return false;
+                    break;
+                }
+            }
+        }
+    return true;
+}
+
+// the r-th representative code of a table-ranked shape (host, by walking)
+template <class Rep>
+static int64_t nth_rep(int64_t r, int64_t count, Rep&& rep) {
+    for (int64_t x = 0; x < count; ++x)
+        if (rep(x)) {
+            if (r == 0) return x;
+            --r;
+        }
+    return -1;
+}
+
+static void digits(int64_t x, int64_t L, int n, int32_t* out) {
+    for (int i = n - 1; i >= 0; --i) { out[i] = (int32_t)(x % L); x /= L; }
 }
 
 int fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* lab) {
     const PatBase B = pat_base(n_labels, max_edges);
     const int64_t L = n_labels;
     int64_t i = (int64_t)index;
-    for (int j = 0; j < 4; ++j) lab[j] = -1;
+    for (int j = 0; j < 5; ++j) lab[j] = -1;
     auto pair_of = [&](int64_t r, int32_t* out) {
         for (int64_t a = 0; a < L; ++a)
             for (int64_t b = a; b < L; ++b)
@@ -110,21 +181,49 @@ int fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int
     if (i < B.path) { *shape = 2; triple_of(i - B.tri, lab); return PG_OK; }
     if (i < B.star) {
         *shape = 3;
-        int64_t r = i - B.path;
-        for (int64_t x = 0; x < L * L * L * L; ++x) {
-            const int64_t a = x / (L * L * L), b = (x / (L * L)) % L, c = (x / L) % L, d = x % L;
-            const int64_t rev = ((d * L + c) * L + b) * L + a;
-            if (x <= rev) {
-                if (r == 0) { lab[0] = (int32_t)a; lab[1] = (int32_t)b; lab[2] = (int32_t)c; lab[3] = (int32_t)d; return PG_OK; }
-                --r;
-            }
-        }
-        return PG_EINVAL;
+        digits(nth_rep(i - B.path, L * L * L * L, [&](int64_t x) { return path_rep(x, L, 4); }), L, 4, lab);
+        return PG_OK;
     }
-    *shape = 4;
-    const int64_t r = i - B.star;
-    lab[0] = (int32_t)(r / B.t3);
-    triple_of(r % B.t3, lab + 1);
+    if (i < B.p5) {
+        *shape = 4;
+        const int64_t r = i - B.star;
+        lab[0] = (int32_t)(r / B.t3);
+        triple_of(r % B.t3, lab + 1);
+        return PG_OK;
+    }
+    if (i < B.star4) {
+        *shape = 5;
+        digits(nth_rep(i - B.p5, L * L * L * L * L, [&](int64_t x) { return path_rep(x, L, 5); }), L, 5, lab);
+        return PG_OK;
+    }
+    if (i < B.fork) {
+        *shape = 6;
+        const int64_t r = i - B.star4;
+        lab[0] = (int32_t)(r / B.q4);
+        digits(nth_rep(r % B.q4, L * L * L * L, [&](int64_t x) { return sorted_rep(x, L); }), L, 4, lab + 1);
+        return PG_OK;
+    }
+    if (i < B.cyc) {
+        *shape = 7;
+        int64_t r = i - B.fork;
+        lab[4] = (int32_t)(r % L);
+        r /= L;
+        lab[3] = (int32_t)(r % L);
+        r /= L;
+        pair_of(r % B.p2, lab + 1);
+        lab[0] = (int32_t)(r / B.p2);
+        return PG_OK;
+    }
+    if (i < B.paw) {
+        *shape = 8;
+        digits(nth_rep(i - B.cyc, L * L * L * L, [&](int64_t x) { return cycle_rep(x, L); }), L, 4, lab);
+        return PG_OK;
+    }
+    *shape = 9;
+    const int64_t r = i - B.paw;
+    pair_of(r % B.p2, lab + 2);
+    lab[1] = (int32_t)((r / B.p2) % L);
+    lab[0] = (int32_t)(r / B.p2 / L);
     return PG_OK;
 }
 
@@ -138,14 +237,21 @@ struct FsmCtx {
     const int32_t* edst;     // edge -> larger endpoint
     const int32_t* lab;
     const int32_t* path_rank;   // rank of every canonical label sequence of a path
+    // four edges (NULL below): ranks of the representative 5-paths, sorted
+    // leaf quadruples and 4-cycle readings, indexed by their tuple code
+    const int32_t* p5_rank;
+    const int32_t* q4_rank;
+    const int32_t* c4_rank;
     PatBase B;
 };
+
+constexpr int FSM_MAXV = 5;   // vertices of a pattern of at most four edges
 
 struct Emb {
     int32_t pid;
     int nv;
-    int32_t v[4];
-    int8_t orb[4];
+    int32_t v[FSM_MAXV];
+    int8_t orb[FSM_MAXV];
 };
 
 __device__ __forceinline__ void sort3(int32_t& a, int32_t& b, int32_t& c) {
@@ -230,6 +336,216 @@ __device__ __forceinline__ Emb classify_path(const FsmCtx& C, int32_t w0, int32_
     return E;
 }
 
+// ----------------------------------------------- four-edge classifiers
+//
+// Orbits are numbered by the smallest canonical position they contain.
+
+// 5-path w0 - w1 - w2 - w3 - w4
+__device__ __forceinline__ Emb classify_path5(const FsmCtx& C, const int32_t (&w)[5]) {
+    Emb E;
+    const int64_t L = C.B.L;
+    int32_t l[5];
+    for (int i = 0; i < 5; ++i) l[i] = C.lab[w[i]];
+    int64_t f = 0, r = 0;
+    for (int i = 0; i < 5; ++i) {
+        f = f * L + l[i];
+        r = r * L + l[4 - i];
+    }
+    E.pid = (int32_t)(C.B.p5 + C.p5_rank[f <= r ? f : r]);
+    E.nv = 5;
+    const bool rev = r < f;
+    for (int i = 0; i < 5; ++i) {
+        E.v[i] = w[i];
+        const int pos = rev ? 4 - i : i;
+        E.orb[i] = (int8_t)((f == r) ? (pos < 4 - pos ? pos : 4 - pos) : pos);
+    }
+    return E;
+}
+
+// 4-star: centre c, leaves q[0..3]
+__device__ __forceinline__ Emb classify_star4(const FsmCtx& C, int32_t c, const int32_t (&q)[4]) {
+    Emb E;
+    const int64_t L = C.B.L;
+    int32_t l[4];
+    for (int i = 0; i < 4; ++i) l[i] = C.lab[q[i]];
+    int32_t t[4] = {l[0], l[1], l[2], l[3]};
+    for (int i = 1; i < 4; ++i)
+        for (int j = i; j > 0 && t[j - 1] > t[j]; --j) { const int32_t x = t[j]; t[j] = t[j - 1]; t[j - 1] = x; }
+    const int64_t code = ((t[0] * L + t[1]) * L + t[2]) * L + t[3];
+    E.pid = (int32_t)(C.B.star4 + (int64_t)C.lab[c] * C.B.q4 + C.q4_rank[code]);
+    E.nv = 5;
+    E.v[0] = c;
+    E.orb[0] = 0;
+    for (int i = 0; i < 4; ++i) {
+        E.v[i + 1] = q[i];
+        int first = 0;
+        while (t[first] != l[i]) ++first;
+        E.orb[i + 1] = (int8_t)(1 + first);   // first sorted position with this label
+    }
+    return E;
+}
+
+// fork: c of degree 3, its leaves a and b, the middle m of its long leg and the end e
+__device__ __forceinline__ Emb classify_fork(const FsmCtx& C, int32_t c, int32_t a, int32_t b, int32_t m, int32_t e) {
+    Emb E;
+    const int64_t L = C.B.L;
+    const int32_t la = C.lab[a], lb = C.lab[b];
+    const int32_t x = min(la, lb), y = max(la, lb);
+    E.pid = (int32_t)(C.B.fork + (((int64_t)C.lab[c] * C.B.p2 + pair_rank(x, y, L)) * L + C.lab[m]) * L + C.lab[e]);
+    E.nv = 5;
+    E.v[0] = c; E.v[1] = a; E.v[2] = b; E.v[3] = m; E.v[4] = e;
+    E.orb[0] = 0;
+    E.orb[1] = (la == x) ? 1 : 2;
+    E.orb[2] = (lb == x) ? 1 : 2;
+    E.orb[3] = 3;
+    E.orb[4] = 4;
+    return E;
+}
+
+// 4-cycle w0 - w1 - w2 - w3 - w0
+__device__ __forceinline__ Emb classify_cycle4(const FsmCtx& C, const int32_t (&w)[4]) {
+    Emb E;
+    const int64_t L = C.B.L;
+    int32_t l[4];
+    for (int i = 0; i < 4; ++i) l[i] = C.lab[w[i]];
+    // reading (r, dir): position i holds vertex (r + i) mod 4, or (r - i) mod 4
+    int64_t best = -1;
+    for (int r = 0; r < 4; ++r)
+        for (int dir = 0; dir < 2; ++dir) {
+            int64_t code = 0;
+            for (int i = 0; i < 4; ++i) code = code * L + l[dir ? (r - i + 4) & 3 : (r + i) & 3];
+            if (best < 0 || code < best) best = code;
+        }
+    E.pid = (int32_t)(C.B.cyc + C.c4_rank[best]);
+    E.nv = 4;
+    for (int j = 0; j < 4; ++j) {
+        E.v[j] = w[j];
+        E.orb[j] = 4;
+    }
+    // a vertex's orbit: its smallest position over the readings that give the canonical tuple
+    for (int r = 0; r < 4; ++r)
+        for (int dir = 0; dir < 2; ++dir) {
+            int64_t code = 0;
+            for (int i = 0; i < 4; ++i) code = code * L + l[dir ? (r - i + 4) & 3 : (r + i) & 3];
+            if (code != best) continue;
+            for (int j = 0; j < 4; ++j) {
+                const int pos = dir ? (r - j + 4) & 3 : (j - r + 4) & 3;
+                if (pos < E.orb[j]) E.orb[j] = (int8_t)pos;
+            }
+        }
+    return E;
+}
+
+// paw: x of degree 3, its pendant y, the triangle's other vertices p and q
+__device__ __forceinline__ Emb classify_paw(const FsmCtx& C, int32_t x, int32_t y, int32_t p, int32_t q) {
+    Emb E;
+    const int64_t L = C.B.L;
+    const int32_t lp = C.lab[p], lq = C.lab[q];
+    const int32_t a = min(lp, lq), b = max(lp, lq);
+    E.pid = (int32_t)(C.B.paw + ((int64_t)C.lab[x] * L + C.lab[y]) * C.B.p2 + pair_rank(a, b, L));
+    E.nv = 4;
+    E.v[0] = x; E.v[1] = y; E.v[2] = p; E.v[3] = q;
+    E.orb[0] = 0;
+    E.orb[1] = 1;
+    E.orb[2] = (lp == a) ? 2 : 3;
+    E.orb[3] = (lq == a) ? 2 : 3;
+    return E;
+}
+
+// Pattern of a connected set of three or four edges (graph edge ids).  The
+// shape follows from the vertex count and the degrees inside the set; paths
+// and cycles are walked from an end or any vertex.
+__device__ __forceinline__ Emb classify_edges(const FsmCtx& C, const int32_t* es, int ne) {
+    int32_t vs[FSM_MAXV];
+    int deg[FSM_MAXV];
+    uint32_t adj[FSM_MAXV];
+    int nv = 0;
+    for (int i = 0; i < FSM_MAXV; ++i) { deg[i] = 0; adj[i] = 0u; vs[i] = -1; }
+    for (int k = 0; k < ne; ++k) {
+        const int32_t ends[2] = {C.esrc[es[k]], C.edst[es[k]]};
+        int at[2];
+        for (int h = 0; h < 2; ++h) {
+            int f = -1;
+            for (int i = 0; i < nv; ++i)
+                if (vs[i] == ends[h]) f = i;
+            if (f < 0 && nv < FSM_MAXV) { f = nv; vs[nv++] = ends[h]; }
+            at[h] = f < 0 ? 0 : f;
+            deg[at[h]]++;
+        }
+        adj[at[0]] |= 1u << at[1];
+        adj[at[1]] |= 1u << at[0];
+    }
+    int dmax = 0, imax = 0;
+    for (int i = 0; i < nv; ++i)
+        if (deg[i] > dmax) { dmax = deg[i]; imax = i; }
+    // the other end of a walk step from `cur` that does not go back to `prev`
+    auto step = [&](int cur, int prev) {
+        const uint32_t m = adj[cur] & ~(prev >= 0 ? 1u << prev : 0u);
+        return m ? __builtin_ctz(m) : -1;
+    };
+    if (ne == 3) {
+        if (nv == 3) return classify_triangle(C, vs[0], vs[1], vs[2]);
+        if (dmax == 3) {
+            int32_t lv[3];
+            int k = 0;
+            for (int i = 0; i < 4; ++i)
+                if (i != imax) lv[k++] = vs[i];
+            return classify_star(C, vs[imax], lv[0], lv[1], lv[2]);
+        }
+        int e0 = 0;
+        while (deg[e0] != 1) ++e0;
+        int w[4];
+        w[0] = e0;
+        w[1] = step(w[0], -1);
+        w[2] = step(w[1], w[0]);
+        w[3] = step(w[2], w[1]);
+        return classify_path(C, vs[w[0]], vs[w[1]], vs[w[2]], vs[w[3]]);
+    }
+    // four edges
+    if (nv == 5) {
+        if (dmax == 4) {
+            int32_t q[4];
+            int k = 0;
+            for (int i = 0; i < 5; ++i)
+                if (i != imax) q[k++] = vs[i];
+            return classify_star4(C, vs[imax], q);
+        }
+        if (dmax == 3) {
+            int leaves[2], k = 0, mid = -1;
+            for (int i = 0; i < 5; ++i)
+                if ((adj[imax] >> i) & 1u) {
+                    if (deg[i] == 1) leaves[k++] = i;
+                    else mid = i;
+                }
+            const int end = step(mid, imax);
+            return classify_fork(C, vs[imax], vs[leaves[0]], vs[leaves[1]], vs[mid], vs[end]);
+        }
+        int e0 = 0;
+        while (deg[e0] != 1) ++e0;
+        int w[5];
+        w[0] = e0;
+        w[1] = step(w[0], -1);
+        for (int i = 2; i < 5; ++i) w[i] = step(w[i - 1], w[i - 2]);
+        const int32_t path[5] = {vs[w[0]], vs[w[1]], vs[w[2]], vs[w[3]], vs[w[4]]};
+        return classify_path5(C, path);
+    }
+    if (dmax == 2) {
+        int w[4];
+        w[0] = 0;
+        w[1] = step(0, -1);
+        w[2] = step(w[1], w[0]);
+        w[3] = step(w[2], w[1]);
+        const int32_t cyc[4] = {vs[w[0]], vs[w[1]], vs[w[2]], vs[w[3]]};
+        return classify_cycle4(C, cyc);
+    }
+    int pend = 0;
+    while (deg[pend] != 1) ++pend;
+    int tri[2], k = 0;
+    for (int i = 0; i < 4; ++i)
+        if (i != imax && i != pend) tri[k++] = i;
+    return classify_paw(C, vs[imax], vs[pend], vs[tri[0]], vs[tri[1]]);
+}
+
 // ---------------------------------------------------------------- kernels
 
 __global__ void k_path_flags(int64_t L, uint32_t* __restrict__ flag) {
@@ -238,6 +554,37 @@ __global__ void k_path_flags(int64_t L, uint32_t* __restrict__ flag) {
         const int64_t a = x / (L * L * L), b = (x / (L * L)) % L, c = (x / L) % L, d = x % L;
         const int64_t rev = ((d * L + c) * L + b) * L + a;
         flag[x] = x <= rev ? 1u : 0u;
+    }
+}
+
+// representative flags of the table-ranked shapes of four edges (see
+// path_rep / sorted_rep / cycle_rep on the host)
+enum { REP_PATH5 = 0, REP_SORTED4 = 1, REP_CYCLE4 = 2 };
+
+__global__ void k_rep_flags(int64_t L, int kind, int64_t N, uint32_t* __restrict__ flag) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < N; x += (int64_t)gridDim.x * blockDim.x) {
+        const int n = kind == REP_PATH5 ? 5 : 4;
+        int64_t d[5];
+        int64_t y = x;
+        for (int i = n - 1; i >= 0; --i) { d[i] = y % L; y /= L; }
+        bool rep = true;
+        if (kind == REP_PATH5) {
+            for (int i = 0; i < n; ++i)
+                if (d[i] != d[n - 1 - i]) { rep = d[i] < d[n - 1 - i]; break; }
+        } else if (kind == REP_SORTED4) {
+            rep = d[0] <= d[1] && d[1] <= d[2] && d[2] <= d[3];
+        } else {
+            for (int r = 0; r < 4 && rep; ++r)
+                for (int dir = 0; dir < 2 && rep; ++dir)
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t c = dir ? d[(r - i + 4) & 3] : d[(r + i) & 3];
+                        if (c != d[i]) {
+                            rep = c > d[i];
+                            break;
+                        }
+                    }
+        }
+        flag[x] = rep ? 1u : 0u;
     }
 }
 
@@ -305,8 +652,11 @@ static unsigned hist_blocks(int64_t m) {
 __global__ void k_candidates(int64_t np, int64_t p_lo, const uint32_t* __restrict__ counts, PatBase B,
                              uint64_t sigma, uint32_t* __restrict__ flag) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = p + p_lo;   // dense index: triangles and stars have orbits of up to 3 vertices
-        const uint64_t maxorb = (q >= B.tri && q < B.path) || q >= B.star ? 3 : 2;
+        // dense index: triangles and 3-stars have orbits of up to 3 vertices,
+        // 4-stars and 4-cycles of up to 4
+        const int64_t q = p + p_lo;
+        const uint64_t maxorb = (q >= B.star4 && q < B.fork) || (q >= B.cyc && q < B.paw) ? 4
+                                : ((q >= B.tri && q < B.path) || (q >= B.star && q < B.p5) ? 3 : 2);
         flag[p] = (counts[p] > 0 && (uint64_t)counts[p] * maxorb >= sigma) ? 1u : 0u;
     }
 }
@@ -326,6 +676,7 @@ __global__ void k_slots(int64_t np, const uint32_t* __restrict__ flag, const uin
 struct Bits {
     uint32_t* bm;          // [slot - s_lo][orbit][word]
     int64_t words;         // words per bitmap
+    int norb;              // bitmaps per slot: 4, or 5 with patterns of four edges
     const int32_t* slot;   // pattern -> slot or -1
     int32_t s_lo, s_hi;    // slots of this group
     const int32_t* lrank;  // vertex -> its rank among the vertices of its label
@@ -334,7 +685,7 @@ struct Bits {
 __device__ __forceinline__ void set_bits(const Bits& Bt, const Emb& E) {
     const int32_t sl = Bt.slot[E.pid];
     if (sl < Bt.s_lo || sl >= Bt.s_hi) return;
-    uint32_t* base = Bt.bm + (int64_t)(sl - Bt.s_lo) * 4 * Bt.words;
+    uint32_t* base = Bt.bm + (int64_t)(sl - Bt.s_lo) * Bt.norb * Bt.words;
     // every vertex of an orbit has the orbit's label, so its bit is indexed
     // by its rank within that label (bitmaps of max-label-count bits)
     // Most embeddings meet bits that are set already (a domain holds at most
@@ -406,10 +757,17 @@ __global__ void k_fsm_l2(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, u
     }
 }
 
-// level 3 from frequent wedges, fused with Reduce: histogram or domain bits
-template <bool BITS>
+// Level 3 from frequent wedges.  L3_HIST / L3_BITS: fused with Reduce (a
+// histogram of patterns, or domain bits); L3_COUNT / L3_WRITE: the
+// materialised level of four-edge mining (children per parent, then
+// (e1, e2, e3, pattern) at the parent's offset).
+enum { L3_HIST = 0, L3_BITS = 1, L3_COUNT = 2, L3_WRITE = 3 };
+
+template <int MODE>
 __global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, const int32_t* __restrict__ e2s,
-                         uint32_t* __restrict__ counts, Bits Bt, unsigned long long* __restrict__ n_emb) {
+                         uint32_t* __restrict__ counts, Bits Bt, unsigned long long* __restrict__ n_emb,
+                         const uint64_t* __restrict__ start, int32_t* __restrict__ o1, int32_t* __restrict__ o2,
+                         int32_t* __restrict__ o3, int32_t* __restrict__ opid) {
     uint64_t local = 0, scanned = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t e1 = e1s[i], e2 = e2s[i];
@@ -418,40 +776,115 @@ __global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, c
         const int32_t s = (a == c || a == d) ? a : b;
         const int32_t o = (s == a) ? b : a;
         const int32_t t = (s == c) ? d : c;
-        if (!BITS) scanned += (uint64_t)(C.rp[s + 1] - C.rp[s] + C.rp[o + 1] - C.rp[o] + C.rp[t + 1] - C.rp[t]);
+        if (MODE == L3_HIST) scanned += (uint64_t)(C.rp[s + 1] - C.rp[s] + C.rp[o + 1] - C.rp[o] + C.rp[t + 1] - C.rp[t]);
+        uint64_t pos = MODE == L3_WRITE ? start[i] : 0;
+        uint32_t nchild = 0;
+        auto emit = [&](int32_t e3, const Emb& Em) {
+            ++local;
+            if (MODE == L3_HIST) atomicAdd(&counts[Em.pid], 1u);
+            if (MODE == L3_BITS) set_bits(Bt, Em);
+            if (MODE == L3_WRITE) {
+                o1[pos] = e1;
+                o2[pos] = e2;
+                o3[pos] = e3;
+                opid[pos] = Em.pid;
+                ++pos;
+            }
+            ++nchild;
+        };
         // edges at s: new leaf w (adjacent to e1 -> e > e2): star
         for (int64_t j = C.rp[s]; j < C.rp[s + 1]; ++j) {
             const int32_t w = C.col[j];
             if (w == o || w == t) continue;
             if (C.eid[j] <= e2) continue;
-            const Emb Em = classify_star(C, s, o, t, w);
-            ++local;
-            if (BITS) set_bits(Bt, Em); else atomicAdd(&counts[Em.pid], 1u);
+            if (MODE == L3_COUNT) { ++nchild; continue; }
+            emit(C.eid[j], classify_star(C, s, o, t, w));
         }
         // edges at o (adjacent to e1 -> e > e2): closing edge (triangle) or path w-o-s-t
         for (int64_t j = C.rp[o]; j < C.rp[o + 1]; ++j) {
             const int32_t w = C.col[j];
             if (w == s) continue;
             if (C.eid[j] <= e2) continue;
-            const Emb Em = (w == t) ? classify_triangle(C, s, o, t) : classify_path(C, w, o, s, t);
-            ++local;
-            if (BITS) set_bits(Bt, Em); else atomicAdd(&counts[Em.pid], 1u);
+            if (MODE == L3_COUNT) { ++nchild; continue; }
+            emit(C.eid[j], (w == t) ? classify_triangle(C, s, o, t) : classify_path(C, w, o, s, t));
         }
         // edges at t not touching e1 (only e > e1 needed): path o-s-t-w
         for (int64_t j = C.rp[t]; j < C.rp[t + 1]; ++j) {
             const int32_t w = C.col[j];
             if (w == s || w == o) continue;
             if (C.eid[j] <= e1) continue;
-            const Emb Em = classify_path(C, o, s, t, w);
-            ++local;
-            if (BITS) set_bits(Bt, Em); else atomicAdd(&counts[Em.pid], 1u);
+            if (MODE == L3_COUNT) { ++nchild; continue; }
+            emit(C.eid[j], classify_path(C, o, s, t, w));
+        }
+        if (MODE == L3_COUNT) counts[i] = nchild;
+    }
+    if (MODE == L3_HIST) {
+        local = wave_sum_u64(local);
+        scanned = wave_sum_u64(scanned);
+        if (lane() == 0 && local) atomicAdd(&n_emb[0], (unsigned long long)local);
+        if (lane() == 0 && scanned) atomicAdd(&n_emb[1], (unsigned long long)scanned);
+    }
+}
+
+// domain bits of stored level-3 entries
+__global__ void k_fsm_l3_bits_stored(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s,
+                                     const int32_t* __restrict__ e2s, const int32_t* __restrict__ e3s, Bits Bt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t es[3] = {e1s[i], e2s[i], e3s[i]};
+        set_bits(Bt, classify_edges(C, es, 3));
+    }
+}
+
+// Level 4 from frequent level-3 entries (g1, g2, g3 in greedy order), fused
+// with Reduce: every edge e at a vertex of the embedding, not in it, keeps
+// the greedy order iff e > g1, e > g2 when e touches g1, and e > g3 when e
+// touches g1 or g2.  An edge joining two vertices of the embedding is seen
+// from both ends and taken from the smaller one.
+template <bool BITS>
+__global__ void k_fsm_l4(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, const int32_t* __restrict__ e2s,
+                         const int32_t* __restrict__ e3s, uint32_t* __restrict__ counts, Bits Bt,
+                         unsigned long long* __restrict__ n_emb) {
+    uint64_t local = 0, scanned = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t es[4] = {e1s[i], e2s[i], e3s[i], 0};
+        int32_t vs[4];
+        int nv = 0;
+        for (int k = 0; k < 3; ++k) {
+            const int32_t ends[2] = {C.esrc[es[k]], C.edst[es[k]]};
+            for (int h = 0; h < 2; ++h) {
+                bool seen = false;
+                for (int q = 0; q < nv; ++q) seen |= vs[q] == ends[h];
+                if (!seen && nv < 4) vs[nv++] = ends[h];
+            }
+        }
+        const int32_t a1 = C.esrc[es[0]], b1 = C.edst[es[0]];
+        const int32_t a2 = C.esrc[es[1]], b2 = C.edst[es[1]];
+        for (int k = 0; k < nv; ++k) {
+            const int32_t x = vs[k];
+            if (!BITS) scanned += (uint64_t)(C.rp[x + 1] - C.rp[x]);
+            for (int64_t j = C.rp[x]; j < C.rp[x + 1]; ++j) {
+                const int32_t e = C.eid[j];
+                if (e <= es[0] || e == es[1] || e == es[2]) continue;
+                const int32_t w = C.col[j];
+                bool inside = false;
+                for (int q = 0; q < nv; ++q) inside |= vs[q] == w;
+                if (inside && w < x) continue;
+                const bool t1 = x == a1 || x == b1 || w == a1 || w == b1;
+                const bool t12 = t1 || x == a2 || x == b2 || w == a2 || w == b2;
+                if (t1 && e <= es[1]) continue;
+                if (t12 && e <= es[2]) continue;
+                es[3] = e;
+                const Emb Em = classify_edges(C, es, 4);
+                ++local;
+                if (BITS) set_bits(Bt, Em); else atomicAdd(&counts[Em.pid], 1u);
+            }
         }
     }
     if (!BITS) {
         local = wave_sum_u64(local);
         scanned = wave_sum_u64(scanned);
-        if (lane() == 0 && local) atomicAdd(&n_emb[0], (unsigned long long)local);
-        if (lane() == 0 && scanned) atomicAdd(&n_emb[1], (unsigned long long)scanned);
+        if (lane() == 0 && local) atomicAdd(&n_emb[2], (unsigned long long)local);
+        if (lane() == 0 && scanned) atomicAdd(&n_emb[3], (unsigned long long)scanned);
     }
 }
 
@@ -469,13 +902,15 @@ __global__ void k_fsm_l2_bits(FsmCtx C, int64_t m, const int32_t* __restrict__ e
 }
 
 // support of each slot of the group: the smallest non-empty orbit domain
-__global__ __launch_bounds__(256) void k_supports(const uint32_t* __restrict__ bm, int64_t words, int32_t s_lo,
-                                                  int32_t s_hi, uint64_t* __restrict__ sup_slot) {
-    __shared__ unsigned long long pop[4];
+// one wave per orbit bitmap (blockDim = norb waves)
+__global__ __launch_bounds__(FSM_MAXV * WAVE) void k_supports(const uint32_t* __restrict__ bm, int64_t words,
+                                                              int norb, int32_t s_lo, int32_t s_hi,
+                                                              uint64_t* __restrict__ sup_slot) {
+    __shared__ unsigned long long pop[FSM_MAXV];
     const int32_t sl = s_lo + blockIdx.x;
     if (sl >= s_hi) return;
     const int o = threadIdx.x / WAVE;
-    const uint32_t* base = bm + ((int64_t)(sl - s_lo) * 4 + o) * words;
+    const uint32_t* base = bm + ((int64_t)(sl - s_lo) * norb + o) * words;
     uint64_t c = 0;
     for (int64_t i = lane(); i < words; i += WAVE) c += (uint64_t)__popc(base[i]);
     c = wave_sum_u64(c);
@@ -483,7 +918,7 @@ __global__ __launch_bounds__(256) void k_supports(const uint32_t* __restrict__ b
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t best = 0;
-        for (int k = 0; k < 4; ++k)
+        for (int k = 0; k < norb; ++k)
             if (pop[k] && (best == 0 || pop[k] < best)) best = pop[k];
         sup_slot[sl] = best;
     }
@@ -530,17 +965,19 @@ static void reduce_level(pg_graph* g, FsmCtx& C, const int32_t* lrank, int64_t l
     uint64_t* sup_slot = push<uint64_t>(ar, std::max<int64_t>(ns, 1));
     if (ns > 0) {
         const int64_t words = (label_max + 31) / 32;
-        const uint64_t per_slot = (uint64_t)words * 4 * sizeof(uint32_t);
+        const int norb = C.B.total > C.B.p5 ? FSM_MAXV : 4;
+        const uint64_t per_slot = (uint64_t)words * norb * sizeof(uint32_t);
         const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
         const int64_t group = std::max<int64_t>(1, std::min<int64_t>(ns, (int64_t)(room / std::max<uint64_t>(per_slot, 1))));
-        uint32_t* bm = push<uint32_t>(ar, (size_t)group * 4 * words);
+        uint32_t* bm = push<uint32_t>(ar, (size_t)group * norb * words);
         for (int64_t g0 = 0; g0 < ns; g0 += group) {
             const int64_t g1 = std::min(ns, g0 + group);
-            fill_u32(bm, (g1 - g0) * 4 * words, 0, s);
-            Bits Bt{bm, words, slot, (int32_t)g0, (int32_t)g1, lrank};
+            fill_u32(bm, (g1 - g0) * norb * words, 0, s);
+            Bits Bt{bm, words, norb, slot, (int32_t)g0, (int32_t)g1, lrank};
             set_bits_pass(Bt);
             ProfScope ps("fsm_support", s, (double)(g1 - g0));
-            k_supports<<<(unsigned)(g1 - g0), 256, 0, s>>>(bm, words, (int32_t)g0, (int32_t)g1, sup_slot);
+            k_supports<<<(unsigned)(g1 - g0), norb * WAVE, 0, s>>>(bm, words, norb, (int32_t)g0, (int32_t)g1,
+                                                                   sup_slot);
             PG_HIP(hipGetLastError());
         }
     }
@@ -596,8 +1033,10 @@ static int64_t label_ranks(pg_graph* g, int32_t* lrank) {
 }
 
 void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* supports, size_t len, size_t* n_frequent) {
-    PG_REQUIRE(max_edges >= 1 && max_edges <= 3, PG_EUNSUPPORTED, "max_edges must be in [1, 3]");
+    PG_REQUIRE(max_edges >= 1 && max_edges <= 4, PG_EUNSUPPORTED, "max_edges must be in [1, 4]");
     PG_REQUIRE(g->n_labels > 0, PG_EINVAL, "FSM needs a labelled graph");
+    PG_REQUIRE(max_edges < 4 || g->n_labels <= FSM4_MAX_LABELS, PG_EUNSUPPORTED,
+               "patterns of four edges need at most 32 labels");
     build_motif_l1(g);
     PG_REQUIRE(g->ml1.n_edges < INT32_MAX, PG_EOVERFLOW, "FSM supports fewer than 2^31 edges");
     hipStream_t s = g->stream;
@@ -636,6 +1075,27 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
         ar.reset(mk);
     }
     C.path_rank = prank;
+    C.p5_rank = C.q4_rank = C.c4_rank = nullptr;
+    if (max_edges >= 4) {
+        // rank tables of the 5-path, 4-star and 4-cycle blocks: representative
+        // flags over all tuple codes, then their exclusive prefix sum
+        auto table = [&](int kind, int64_t N) {
+            int32_t* rank = push<int32_t>(ar, N);
+            const size_t mk = ar.mark();
+            uint32_t* f = push<uint32_t>(ar, N);
+            uint64_t* r = push<uint64_t>(ar, N + 1);
+            k_rep_flags<<<grid1(N), 256, 0, s>>>(L, kind, N, f);
+            PG_HIP(hipGetLastError());
+            scan_u32(f, N, r, ar, s);
+            k_u64_to_i32<<<grid1(N), 256, 0, s>>>(N, r, rank);
+            PG_HIP(hipGetLastError());
+            ar.reset(mk);
+            return rank;
+        };
+        C.p5_rank = table(REP_PATH5, L * L * L * L * L);
+        C.q4_rank = table(REP_SORTED4, L * L * L * L);
+        C.c4_rank = table(REP_CYCLE4, L * L * L * L);
+    }
     int32_t* lrank = push<int32_t>(ar, std::max<int64_t>(g->n, 1));
     const int64_t label_max = label_ranks(g, lrank);
     uint32_t* counts = push<uint32_t>(ar, np);
@@ -647,7 +1107,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
     unsigned long long* n_emb = reinterpret_cast<unsigned long long*>(push<uint64_t>(ar, 4));
     fill_u64(reinterpret_cast<uint64_t*>(n_emb), 4, 0, s);
 
-    int64_t n2_total = 0, m2_total = 0, l3_passes = 0;
+    int64_t n2_total = 0, m2_total = 0, l3_passes = 0, n3_stored = 0;
     // ---------------- level 1: every edge; Reduce; Filter
     int32_t* pid1 = push<int32_t>(ar, std::max<int64_t>(E, 1));
     {
@@ -713,32 +1173,99 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
             int32_t* fb = push<int32_t>(ar, std::max<int64_t>(m2, 1));
             k_compact2<<<grid1(n2), 256, 0, s>>>(n2, keep2, kpos2, a2, b2, fa, fb);
             PG_HIP(hipGetLastError());
-            // ---------------- level 3, fused with Reduce (never stored)
-            if (m2 > 0) {
-                ProfScope ps("fsm_l3_hist", s, (double)m2);
-                k_fsm_l3<false><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, counts, Bits{}, n_emb);
-                PG_HIP(hipGetLastError());
-            }
-            reduce_level(g, C, lrank, label_max, C.B.tri, C.B.total, counts, min_support, freq, sup_pat, [&](const Bits& Bt) {
+            if (max_edges == 3) {
+                // ---------------- level 3, fused with Reduce (never stored)
                 if (m2 > 0) {
-                    ProfScope ps("fsm_l3_bits", s, (double)m2);
-                    k_fsm_l3<true><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bt, nullptr);
+                    ProfScope ps("fsm_l3_hist", s, (double)m2);
+                    k_fsm_l3<L3_HIST><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, counts, Bits{}, n_emb, nullptr,
+                                                                nullptr, nullptr, nullptr, nullptr);
                     PG_HIP(hipGetLastError());
-                    ++l3_passes;   // one per group of candidate patterns
                 }
-            });
+                reduce_level(g, C, lrank, label_max, C.B.tri, C.B.total, counts, min_support, freq, sup_pat,
+                             [&](const Bits& Bt) {
+                    if (m2 > 0) {
+                        ProfScope ps("fsm_l3_bits", s, (double)m2);
+                        k_fsm_l3<L3_BITS><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bt, nullptr, nullptr,
+                                                                    nullptr, nullptr, nullptr, nullptr);
+                        PG_HIP(hipGetLastError());
+                        ++l3_passes;   // one per group of candidate patterns
+                    }
+                });
+            } else {
+                // ---------------- level 3 materialised: count / scan / write
+                uint32_t* c3 = push<uint32_t>(ar, std::max<int64_t>(m2, 1));
+                uint64_t* st3 = push<uint64_t>(ar, m2 + 1);
+                if (m2 > 0) {
+                    ProfScope ps("fsm_l3_count", s, (double)m2);
+                    k_fsm_l3<L3_COUNT><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, c3, Bits{}, nullptr, nullptr,
+                                                                 nullptr, nullptr, nullptr, nullptr);
+                    PG_HIP(hipGetLastError());
+                }
+                scan_u32(c3, m2, st3, ar, s);
+                const int64_t n3 = (int64_t)read_u64(st3 + m2, s);
+                PG_REQUIRE(n3 < INT32_MAX, PG_EOVERFLOW, "level 3 exceeds 2^31 embeddings");
+                n3_stored = n3;
+                int32_t* x3 = push<int32_t>(ar, std::max<int64_t>(n3, 1));
+                int32_t* y3 = push<int32_t>(ar, std::max<int64_t>(n3, 1));
+                int32_t* z3 = push<int32_t>(ar, std::max<int64_t>(n3, 1));
+                int32_t* p3 = push<int32_t>(ar, std::max<int64_t>(n3, 1));
+                if (m2 > 0) {
+                    ProfScope ps("fsm_l3_write", s, (double)n3);
+                    k_fsm_l3<L3_WRITE><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bits{}, nullptr, st3, x3,
+                                                                 y3, z3, p3);
+                    PG_HIP(hipGetLastError());
+                    k_hist<<<hist_blocks(n3), 256, 0, s>>>(n3, p3, counts, (int32_t)C.B.tri,
+                                                           (int32_t)(C.B.p5 - C.B.tri));
+                    PG_HIP(hipGetLastError());
+                }
+                reduce_level(g, C, lrank, label_max, C.B.tri, C.B.p5, counts, min_support, freq, sup_pat,
+                             [&](const Bits& Bt) {
+                    if (n3 > 0) {
+                        k_fsm_l3_bits_stored<<<grid1(n3), 256, 0, s>>>(C, n3, x3, y3, z3, Bt);
+                        PG_HIP(hipGetLastError());
+                    }
+                });
+                // Filter: frequent patterns of three edges
+                uint32_t* keep3 = push<uint32_t>(ar, std::max<int64_t>(n3, 1));
+                uint64_t* kpos3 = push<uint64_t>(ar, n3 + 1);
+                k_keep_flags<<<grid1(n3), 256, 0, s>>>(n3, p3, freq, keep3);
+                PG_HIP(hipGetLastError());
+                scan_u32(keep3, n3, kpos3, ar, s);
+                const int64_t m3 = (int64_t)read_u64(kpos3 + n3, s);
+                int32_t* fx = push<int32_t>(ar, std::max<int64_t>(m3, 1));
+                int32_t* fy = push<int32_t>(ar, std::max<int64_t>(m3, 1));
+                int32_t* fz = push<int32_t>(ar, std::max<int64_t>(m3, 1));
+                k_compact2<<<grid1(n3), 256, 0, s>>>(n3, keep3, kpos3, x3, y3, fx, fy);
+                PG_HIP(hipGetLastError());
+                k_compact2<<<grid1(n3), 256, 0, s>>>(n3, keep3, kpos3, z3, nullptr, fz, nullptr);
+                PG_HIP(hipGetLastError());
+                // ---------------- level 4, fused with Reduce (never stored)
+                if (m3 > 0) {
+                    ProfScope ps("fsm_l4_hist", s, (double)m3);
+                    k_fsm_l4<false><<<grid1(m3), 256, 0, s>>>(C, m3, fx, fy, fz, counts, Bits{}, n_emb);
+                    PG_HIP(hipGetLastError());
+                }
+                reduce_level(g, C, lrank, label_max, C.B.p5, C.B.total, counts, min_support, freq, sup_pat,
+                             [&](const Bits& Bt) {
+                    if (m3 > 0) {
+                        ProfScope ps("fsm_l4_bits", s, (double)m3);
+                        k_fsm_l4<true><<<grid1(m3), 256, 0, s>>>(C, m3, fx, fy, fz, nullptr, Bt, nullptr);
+                        PG_HIP(hipGetLastError());
+                    }
+                });
+            }
         }
     }
     std::vector<uint64_t> h((size_t)np);
-    uint64_t n3s[2] = {0, 0};
+    uint64_t n3s[4] = {0, 0, 0, 0};
     PG_HIP(hipMemcpyAsync(h.data(), sup_pat, sizeof(uint64_t) * np, hipMemcpyDeviceToHost, s));
     PG_HIP(hipMemcpyAsync(n3s, n_emb, sizeof(n3s), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
-    const uint64_t n3 = n3s[0];
+    const uint64_t n3 = max_edges == 4 ? (uint64_t)n3_stored : n3s[0];
     if (prof_on()) {
-        // embeddings generated at every level (levels 2 and 3 from the
+        // embeddings generated at every level (levels 2, 3 and 4 from the
         // filtered parents)
-        ProfScope ps("fsm_embeddings", s, (double)E + (double)n2_total + (double)n3);
+        ProfScope ps("fsm_embeddings", s, (double)E + (double)n2_total + (double)n3 + (double)n3s[2]);
         // algorithmic bytes of one domain-bit pass over level 3: per
         // parent its two edge ids, their four endpoints and three
         // row-pointer pairs (72 B); per scanned list element its vertex and

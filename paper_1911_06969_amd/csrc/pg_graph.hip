@@ -277,11 +277,11 @@ __global__ __launch_bounds__(256) void k_upper_write(int64_t n, const int64_t* _
     }
 }
 
-void build_motif_l1(pg_graph* g) {
-    if (g->ml1.built) return;
+void build_motif_l1(pg_graph* g, const MotifView& V) {
+    MotifL1& L = *V.ml1;
+    if (L.built) return;
     hipStream_t s = g->stream;
-    const int64_t n = g->n, m = g->nnz / 2;
-    MotifL1& L = g->ml1;
+    const int64_t n = V.n, m = V.nnz / 2;
     L.seg.reserve(sizeof(int64_t) * (n + 1));
     L.src.reserve(sizeof(int32_t) * std::max<int64_t>(m, 1));
     L.dst.reserve(sizeof(int32_t) * std::max<int64_t>(m, 1));
@@ -290,12 +290,10 @@ void build_motif_l1(pg_graph* g) {
     Arena tmp;
     tmp.buf.reserve(sizeof(uint64_t) * (size_t)(2 * ((n + 2047) / 2048) + 64) + (1 << 16));
     if (n > 0) {
-        k_upper_count<<<grid_for(n, 256), 256, 0, s>>>(n, g->rp.as<int64_t>(), g->col.as<int32_t>(),
-                                                       cnt.as<uint32_t>());
+        k_upper_count<<<grid_for(n, 256), 256, 0, s>>>(n, V.rp, V.col, cnt.as<uint32_t>());
         PG_HIP(hipGetLastError());
         scan_u32(cnt.as<uint32_t>(), n, L.seg.as<uint64_t>(), tmp, s);
-        k_upper_write<<<grid_for(n, 4), 256, 0, s>>>(n, g->rp.as<int64_t>(), g->col.as<int32_t>(),
-                                                     L.seg.as<uint64_t>(), L.src.as<int32_t>(),
+        k_upper_write<<<grid_for(n, 4), 256, 0, s>>>(n, V.rp, V.col, L.seg.as<uint64_t>(), L.src.as<int32_t>(),
                                                      L.dst.as<int32_t>());
         PG_HIP(hipGetLastError());
     } else {
@@ -304,6 +302,98 @@ void build_motif_l1(pg_graph* g) {
     PG_HIP(hipStreamSynchronize(s));
     L.n_edges = m;
     L.built = true;
+}
+
+void build_motif_l1(pg_graph* g) { build_motif_l1(g, motif_view(g, false)); }
+
+// ------------------------------------------------- renamed graph (motifs)
+//
+// New name of v = its position in the order of decreasing degree, ties by
+// increasing id.  Rows are the renamed neighbour lists, ascending.
+
+__global__ void k_desc_degree_keys(int64_t n, const int64_t* __restrict__ rp, uint64_t max_deg,
+                                   uint64_t* __restrict__ keys) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        keys[v] = ((max_deg - (uint64_t)(rp[v + 1] - rp[v])) << 32) | (uint64_t)v;
+}
+
+// degree of the vertex named r (for the row pointers)
+__global__ void k_renamed_degree(int64_t n, const uint64_t* __restrict__ sorted, const int64_t* __restrict__ rp,
+                                 uint32_t* __restrict__ deg) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)sorted[r];
+        deg[r] = (uint32_t)(rp[v + 1] - rp[v]);
+    }
+}
+
+// (name(v) << 32 | name(u)) for every directed entry (v, u), in input order
+__global__ __launch_bounds__(256) void k_renamed_edges(int64_t n, const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const int32_t* __restrict__ name,
+                                                       uint64_t* __restrict__ keys) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t v = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; v < n; v += waves) {
+        const uint64_t hv = (uint64_t)(uint32_t)name[v] << 32;
+        for (int64_t j = rp[v] + lane(); j < rp[v + 1]; j += WAVE) keys[j] = hv | (uint32_t)name[col[j]];
+    }
+}
+
+void build_motif_graph(pg_graph* g) {
+    MotifGraph& M = g->mg;
+    if (M.built) return;
+    hipStream_t s = g->stream;
+    const int64_t n = g->n, nnz = g->nnz;
+    M.n = n;
+    M.nnz = nnz;
+    M.max_deg = g->max_deg;
+    M.rp.reserve(sizeof(int64_t) * (n + 1));
+    M.col.reserve(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    DevBuf t1, t2, name, deg, hi;
+    const int64_t big = std::max<int64_t>(std::max(n, nnz), 1);
+    t1.reserve(sizeof(uint64_t) * big);
+    t2.reserve(sizeof(uint64_t) * big);
+    name.reserve(sizeof(int32_t) * std::max<int64_t>(n, 1));
+    deg.reserve(sizeof(uint32_t) * std::max<int64_t>(n, 1));
+    hi.reserve(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    Arena tmp;
+    tmp.buf.reserve(sizeof(uint64_t) * (size_t)(256 * ((big + 2047) / 2048) * 3 + (1 << 20)));
+    ProfScope ps("motif_rename", s, (double)nnz);
+    if (n > 0) {
+        uint64_t* keys = t1.as<uint64_t>();
+        k_desc_degree_keys<<<grid_for(n, 256), 256, 0, s>>>(n, g->rp.as<int64_t>(), (uint64_t)g->max_deg, keys);
+        PG_HIP(hipGetLastError());
+        const int db = std::max(1, bits_for((uint64_t)g->max_deg));
+        radix_sort_u64(keys, t2.as<uint64_t>(), n, 32, 32 + db, tmp, s);
+        k_rank_of<<<grid_for(n, 256), 256, 0, s>>>(n, keys, name.as<int32_t>());
+        PG_HIP(hipGetLastError());
+        k_renamed_degree<<<grid_for(n, 256), 256, 0, s>>>(n, keys, g->rp.as<int64_t>(), deg.as<uint32_t>());
+        PG_HIP(hipGetLastError());
+        scan_u32(deg.as<uint32_t>(), n, M.rp.as<uint64_t>(), tmp, s);
+        if (nnz > 0) {
+            uint64_t* ek = t1.as<uint64_t>();
+            k_renamed_edges<<<grid_for(n, 4), 256, 0, s>>>(n, g->rp.as<int64_t>(), g->col.as<int32_t>(),
+                                                           name.as<int32_t>(), ek);
+            PG_HIP(hipGetLastError());
+            const int nb = std::max(1, bits_for((uint64_t)(n - 1)));
+            radix_sort_u64(ek, t2.as<uint64_t>(), nnz, 0, nb, tmp, s);
+            radix_sort_u64(ek, t2.as<uint64_t>(), nnz, 32, 32 + nb, tmp, s);
+            k_split_low<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, ek, M.col.as<int32_t>(), hi.as<int32_t>());
+            PG_HIP(hipGetLastError());
+        }
+    } else {
+        fill_u64(M.rp.as<uint64_t>(), 1, 0, s);
+    }
+    PG_HIP(hipStreamSynchronize(s));
+    M.built = true;
+}
+
+MotifView motif_view(pg_graph* g, bool renamed) {
+    if (renamed) {
+        build_motif_graph(g);
+        MotifGraph& M = g->mg;
+        return MotifView{M.n, M.nnz, M.max_deg, M.rp.as<int64_t>(), M.col.as<int32_t>(), &M.ml1};
+    }
+    return MotifView{g->n, g->nnz, g->max_deg, g->rp.as<int64_t>(), g->col.as<int32_t>(), &g->ml1};
 }
 
 }  // namespace pg

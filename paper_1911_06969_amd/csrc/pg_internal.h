@@ -149,6 +149,27 @@ struct MotifL1 {
     DevBuf hub_bits;         // uint32[n_hubs][hub_words]
 };
 
+// The graph with its vertices renamed by decreasing degree (ties by id),
+// for the 4-motif path.  Motif counts do not depend on vertex names; under
+// this naming the smallest vertex of an embedding (its first vertex in the
+// canonical order) is its highest-degree one, so the hub lists are the ones
+// shared by many embeddings.
+struct MotifGraph {
+    bool built = false;
+    int64_t n = 0, nnz = 0, max_deg = 0;
+    DevBuf rp;               // int64[n+1]
+    DevBuf col;              // int32[nnz], ascending per row
+    MotifL1 ml1;
+};
+
+// The CSR a motif pipeline runs on: the input graph or the renamed one.
+struct MotifView {
+    int64_t n, nnz, max_deg;
+    const int64_t* rp;
+    const int32_t* col;
+    MotifL1* ml1;
+};
+
 }  // namespace pg
 
 struct pg_graph {
@@ -159,6 +180,7 @@ struct pg_graph {
     pg::DevBuf rp, col, labels;
     pg::Dag dag;
     pg::MotifL1 ml1;
+    pg::MotifGraph mg;
     uint64_t budget = 0;     // bytes for materialised levels
     bool force_generic = false;   // cliques: skip the sibling-mask path
     pg::Arena arena;
@@ -201,6 +223,9 @@ int64_t round_items(const int64_t* seg, int64_t p_lo, int64_t n_seg, int per, Ar
                     uint64_t** items, int64_t total = -1, uint64_t* count_dev = nullptr);
 int64_t round_items(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
                     uint64_t** items, int64_t total = -1, uint64_t* count_dev = nullptr);
+// The same over the segments with cmin <= children < cmax only.
+int64_t round_items_between(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, int64_t cmin, int64_t cmax,
+                            Arena& a, hipStream_t s, uint64_t** items);
 
 // ------------------------------------------------------------- pipelines
 
@@ -208,6 +233,9 @@ void graph_load(pg_graph* g, int64_t n, int64_t nnz, const int64_t* rp, const in
                 const int32_t* labels, int32_t n_labels, unsigned flags);
 void build_dag(pg_graph* g);
 void build_motif_l1(pg_graph* g);
+void build_motif_l1(pg_graph* g, const MotifView& v);
+void build_motif_graph(pg_graph* g);
+MotifView motif_view(pg_graph* g, bool renamed);
 uint64_t count_cliques(pg_graph* g, int k);
 uint64_t list_cliques(pg_graph* g, int k, int32_t* out, uint64_t capacity);
 void count_motifs(pg_graph* g, int k, uint64_t* counts);

@@ -43,7 +43,7 @@ constexpr int MO_THREADS = 128;
 constexpr int MO_WAVES = MO_THREADS / WAVE;
 constexpr int MO_STAGE = 512;     // adjacency lists up to this long are staged in LDS
 constexpr int MO_CMAX = 512;      // common-neighbour lists up to this long live in LDS
-constexpr int MO5_WAVES_PER_CU = 32;   // k = 5 last level: latency-bound lanes, more waves in flight
+constexpr int MO5_WAVES_PER_CU = 32;   // k = 5 last level: at most this many waves per CU (latency-bound lanes)
 
 enum { ML1_COUNT = 0, ML1_WRITE = 1, ML1_LAST3 = 2 };
 
@@ -604,6 +604,283 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
     }
 }
 
+// --------------------------------------- last level, k = 4, many children
+//
+// L1 entries (v0, v1) with many children are taken by whole workgroups.  The
+// workgroup marks the lists of v0 and v1 above v0 in a map in LDS with two
+// bits per vertex (bit 0: u ~ v0, bit 1: u ~ v1), so testing a candidate u
+// of a child's list against both lists is one LDS read.  The marks stay
+// while consecutive items share v0 (only v1's are redone) or the whole entry
+// (a long entry is cut into items of MM_CHILDREN children).  Per entry the
+// workgroup also records, for every position j of v1's list above v0, how
+// many of the elements before j are adjacent to v0 (cum), which gives the
+// common neighbours of v0 and v1 up to any child v2 with one lookup.
+//
+// Each wave takes 64 children, one per lane: the lane finds where v2's list
+// passes v0 and the ranks of v2 in the lists of v0 and v1.  Children with
+// fewer than 64 candidates are streamed by their own lane (four loads in
+// flight); longer ones by the whole wave, 256 candidates per step, counted
+// with ballots.  The counts per adjacency mask and range then go through
+// the same canonical rule and pattern table as in k_motif_last4.
+constexpr int MM_THREADS = 512;
+constexpr int MM_WAVES = MM_THREADS / WAVE;
+constexpr int MM_CHILDREN = MM_WAVES * WAVE;   // children per item
+constexpr int64_t MM_HEAVY = 256;              // entries with at least this many children use the map
+
+__device__ __forceinline__ uint32_t map_bits(const uint32_t* map, int32_t u) {
+    return (map[(uint32_t)u >> 4] >> (((uint32_t)u & 15u) << 1)) & 3u;
+}
+
+// Adds this entry's (r = 0: candidates u <= v2, r = 1: above v2) counts to
+// the pattern counters.  k: [0, 1] u ~ v0 and v2, [2, 3] u ~ v1 and v2,
+// [4, 5] all three, [6] |A2' up to v2|; I*: list sizes per range.
+__device__ __forceinline__ void motif4_classify(uint64_t (&acc)[6], const uint32_t (&k)[7], int32_t len2,
+                                                const int32_t (&I0)[2], const int32_t (&I1)[2],
+                                                const int32_t (&I01)[2], int32_t v1, int32_t v2, int code) {
+    const int a02 = code & 1, a12 = (code >> 1) & 1;
+    const int p = a02 ? 0 : 1;
+    const int32_t I2[2] = {(int32_t)k[6], len2 - (int32_t)k[6]};
+    int32_t N[2][8];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int32_t i02 = (int32_t)k[0 + r], i12 = (int32_t)k[2 + r], i012 = (int32_t)k[4 + r];
+        N[r][0] = 0;
+        N[r][7] = i012;
+        N[r][3] = I01[r] - i012;
+        N[r][5] = i02 - i012;
+        N[r][6] = i12 - i012;
+        N[r][1] = I0[r] - I01[r] - i02 + i012;
+        N[r][2] = I1[r] - I01[r] - i12 + i012;
+        N[r][4] = I2[r] - i02 - i12 + i012;
+    }
+    const int r1 = v1 > v2 ? 1 : 0, m1 = 1 | (a12 ? 4 : 0), m2 = a02 | (a12 << 1);
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) N[r][m] -= (int32_t)((r == r1 && m == m1) + (r == 0 && m == m2));
+    const int ebits = 1 | (a02 << 1) | (a12 << 2);
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+        const int sbit = (m & 1) ? 0 : ((m & 2) ? 1 : 2);
+        if (sbit < p) continue;
+        const int64_t c = (sbit == p) ? (int64_t)N[1][m] : (int64_t)N[0][m] + N[1][m];
+        const int pid = c_lut4.v[ebits | (m << 3)];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) acc[q] += (pid == q) ? (uint64_t)c : 0ull;
+    }
+}
+
+template <int LOGV>
+__global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int32_t* __restrict__ cum_all,
+                                                                int64_t cum_stride) {
+    constexpr int WORDS = (1 << LOGV) / 16;
+    __shared__ uint32_t map[WORDS];
+    __shared__ int64_t s_next[2];
+    __shared__ uint32_t s_tot[MM_WAVES];
+    const int w = threadIdx.x / WAVE;
+    int32_t* cum = cum_all + (int64_t)blockIdx.x * cum_stride;
+    const int32_t* __restrict__ col = A.col;
+    for (int i = threadIdx.x; i < WORDS; i += MM_THREADS) map[i] = 0;
+    // the marked lists: A0' = col[m0b, m0e), A1' = col[m1b, m1e)
+    int32_t mv0 = -1, mv1 = -1;
+    int64_t m0b = 0, m0e = 0, m1b = 0, m1e = 0;
+    int32_t nc = 0;
+    uint64_t acc[6] = {0, 0, 0, 0, 0, 0};
+    uint64_t streamed = 0, n_in = 0, marked = 0;
+    QueueCursor cur = queue_start();
+    while (true) {
+        __syncthreads();   // every wave is done with the previous chunk's s_next
+        if (w == 0) {
+            int64_t e = 0;
+            const int64_t f = queue_next(A.Q, cur, e);
+            if (lane() == 0) {
+                s_next[0] = f;
+                s_next[1] = e;
+            }
+        }
+        __syncthreads();
+        const int64_t first = s_next[0], last = s_next[1];
+        if (first < 0) break;
+        for (int64_t j = first; j < last; ++j) {
+            const uint64_t item = (uint64_t)uniform64((int64_t)A.items[j]);
+            const int64_t p = item_seg(item);
+            const int32_t xa = (int32_t)item_round(item) * MM_CHILDREN;
+            const int64_t b = uniform64((int64_t)(A.seg2[p] - A.seg2_base));
+            const int32_t s = uniform((int32_t)(A.seg2[p + 1] - A.seg2[p]));
+            if (xa >= s) continue;
+            const int32_t v0 = uniform(A.l1_src[p]), v1 = uniform(A.l1_dst[p]);
+            if (v0 != mv0 || v1 != mv1) {
+                const int64_t r0 = uniform64(A.rp[v0]), r1 = uniform64(A.rp[v0 + 1]);
+                const int64_t q0 = uniform64(A.rp[v1]), q1 = uniform64(A.rp[v1 + 1]);
+                const int64_t a0b = uniform64(upper_bound(col, r0, r1, v0));
+                const int64_t a1b = uniform64(upper_bound(col, q0, q1, v0));
+                __syncthreads();   // the previous entry's children are counted
+                if (v0 != mv0) {
+                    for (int64_t t = m0b + threadIdx.x; t < m0e; t += MM_THREADS) map[(uint32_t)col[t] >> 4] = 0u;
+                    for (int64_t t = m1b + threadIdx.x; t < m1e; t += MM_THREADS) map[(uint32_t)col[t] >> 4] = 0u;
+                    __syncthreads();
+                    for (int64_t t = a0b + threadIdx.x; t < r1; t += MM_THREADS) {
+                        const uint32_t u = (uint32_t)col[t];
+                        atomicOr(&map[u >> 4], 1u << ((u & 15u) << 1));
+                    }
+                    marked += (uint64_t)(r1 - a0b);
+                } else {
+                    for (int64_t t = m1b + threadIdx.x; t < m1e; t += MM_THREADS) {
+                        const uint32_t u = (uint32_t)col[t];
+                        atomicAnd(&map[u >> 4], ~(2u << ((u & 15u) << 1)));
+                    }
+                }
+                __syncthreads();
+                for (int64_t t = a1b + threadIdx.x; t < q1; t += MM_THREADS) {
+                    const uint32_t u = (uint32_t)col[t];
+                    atomicOr(&map[u >> 4], 2u << ((u & 15u) << 1));
+                }
+                marked += (uint64_t)(q1 - a1b);
+                __syncthreads();
+                // cum over A1' in MM_WAVES slices: counts, then positions
+                const int32_t d1p = (int32_t)(q1 - a1b);
+                const int32_t per = (d1p + MM_WAVES - 1) / MM_WAVES;
+                const int32_t sb = min(w * per, d1p), se = min(sb + per, d1p);
+                uint32_t c = 0;
+                for (int32_t t0 = sb; t0 < se; t0 += WAVE) {
+                    const int32_t t = t0 + lane();
+                    const bool h = t < se && (map_bits(map, col[a1b + (t < se ? t : sb)]) & 1u);
+                    c += (uint32_t)popc64(ballot(h));
+                }
+                if (lane() == 0) s_tot[w] = c;
+                __syncthreads();
+                uint32_t base = 0, total = 0;
+                for (int k = 0; k < MM_WAVES; ++k) {
+                    const uint32_t tk = s_tot[k];
+                    base += k < w ? tk : 0u;
+                    total += tk;
+                }
+                for (int32_t t0 = sb; t0 < se; t0 += WAVE) {
+                    const int32_t t = t0 + lane();
+                    const bool h = t < se && (map_bits(map, col[a1b + (t < se ? t : sb)]) & 1u);
+                    const uint64_t B = ballot(h);
+                    if (t < se) cum[t] = (int32_t)(base + (uint32_t)popc64(B & lanemask_lt()));
+                    base += (uint32_t)popc64(B);
+                }
+                if (threadIdx.x == 0) cum[d1p] = (int32_t)total;
+                __syncthreads();
+                mv0 = v0;
+                mv1 = v1;
+                m0b = a0b;
+                m0e = r1;
+                m1b = a1b;
+                m1e = q1;
+                nc = (int32_t)total;
+            }
+            // this wave's children [xw, xe)
+            const int32_t xw = xa + w * WAVE;
+            const int32_t xe = min(xa + MM_CHILDREN, s);
+            if (xw >= xe) continue;
+            const int32_t x = xw + lane();
+            const bool valid = x < xe;
+            int32_t v2 = 0, code = 0;
+            int64_t lo2 = 0, s1 = 0;
+            int32_t I0[2] = {0, 0}, I1[2] = {0, 0}, I01[2] = {0, 0};
+            if (valid) {
+                v2 = A.vid2[b + x];
+                code = A.code2[b + x];
+                const int64_t s0 = A.rp[v2];
+                s1 = A.rp[v2 + 1];
+                lo2 = upper_bound(col, s0, s1, v0);
+                const int64_t u0 = upper_bound(col, m0b, m0e, v2);
+                const int64_t u1 = upper_bound(col, m1b, m1e, v2);
+                I0[0] = (int32_t)(u0 - m0b);
+                I0[1] = (int32_t)(m0e - u0);
+                I1[0] = (int32_t)(u1 - m1b);
+                I1[1] = (int32_t)(m1e - u1);
+                I01[0] = cum[u1 - m1b];
+                I01[1] = nc - I01[0];
+            }
+            const int32_t len = (int32_t)(s1 - lo2);
+            uint32_t k[7] = {0, 0, 0, 0, 0, 0, 0};
+            // short children: the lane streams its own list, four loads at a time
+            {
+                const bool mine = valid && len < WAVE;
+                int64_t t = lo2;
+                const int64_t te = mine ? s1 : lo2;
+                while (ballot(t < te)) {
+                    int32_t u[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) u[q] = col[t + q < te ? t + q : 0];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool vq = t + q < te;
+                        const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
+                        const uint32_t lo = (vq && u[q] <= v2) ? 1u : 0u, hi = (vq && u[q] > v2) ? 1u : 0u;
+                        const uint32_t b0 = bits & 1u, b1 = (bits >> 1) & 1u;
+                        k[0] += b0 & lo;
+                        k[1] += b0 & hi;
+                        k[2] += b1 & lo;
+                        k[3] += b1 & hi;
+                        k[4] += b0 & b1 & lo;
+                        k[5] += b0 & b1 & hi;
+                        k[6] += lo;
+                    }
+                    t += 4;
+                }
+            }
+            // long children: the whole wave streams each list, 256 candidates per step
+            uint64_t longm = ballot(valid && len >= WAVE);
+            while (longm) {
+                const int xi = __builtin_ctzll(longm);
+                longm &= longm - 1;
+                const int32_t cv2 = readlane(v2, xi);
+                const int64_t l = (int64_t)readlane64((uint64_t)lo2, xi);
+                const int64_t h = (int64_t)readlane64((uint64_t)s1, xi);
+                uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+                for (int64_t t0 = l; t0 < h; t0 += 4 * WAVE) {
+                    int32_t u[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int64_t t = t0 + q * WAVE + lane();
+                        u[q] = col[t < h ? t : l];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool vq = t0 + q * WAVE + lane() < h;
+                        const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
+                        const uint64_t L = ballot(vq && u[q] <= cv2);
+                        const uint64_t B0 = ballot(bits & 1u), B1 = ballot(bits & 2u);
+                        const uint64_t B01 = B0 & B1;
+                        c[0] += (uint32_t)popc64(B0 & L);
+                        c[1] += (uint32_t)popc64(B0 & ~L);
+                        c[2] += (uint32_t)popc64(B1 & L);
+                        c[3] += (uint32_t)popc64(B1 & ~L);
+                        c[4] += (uint32_t)popc64(B01 & L);
+                        c[5] += (uint32_t)popc64(B01 & ~L);
+                        c[6] += (uint32_t)popc64(L);
+                    }
+                }
+                if (lane() == xi) {
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) k[q] = c[q];
+                }
+            }
+            if (valid) {
+                streamed += (uint64_t)len;
+                n_in += 1;
+                motif4_classify(acc, k, len, I0, I1, I01, v1, v2, code);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const uint64_t v = wave_sum_u64(acc[c]);
+        if (lane() == 0 && v) atomicAdd(&A.out[c], (unsigned long long)v);
+    }
+    const uint64_t st = wave_sum_u64(streamed), ni = wave_sum_u64(n_in);
+    if (lane() == 0) {
+        if (st) atomicAdd(&A.out[9], (unsigned long long)st);
+        if (ni) atomicAdd(&A.out[10], (unsigned long long)ni);
+        if (w == 0 && marked) atomicAdd(&A.out[11], (unsigned long long)marked);
+    }
+}
+
 // ------------------------------------------------------- last level, k = 5
 //
 // Five vertices: a pattern is the 10-bit mask of adjacent position pairs,
@@ -844,16 +1121,16 @@ struct MotifRun {
     int blocks;
 };
 
-static MotifArgs base_args(pg_graph* g) {
+static MotifArgs base_args(const MotifView& V) {
     MotifArgs A{};
-    A.rp = g->rp.as<int64_t>();
-    A.col = g->col.as<int32_t>();
-    A.l1_seg = g->ml1.seg.as<int64_t>();
-    A.l1_src = g->ml1.src.as<int32_t>();
-    A.l1_dst = g->ml1.dst.as<int32_t>();
-    A.hub_id = g->ml1.hub_id.as<int32_t>();
-    A.hub_bits = g->ml1.hub_bits.as<uint32_t>();
-    A.hub_words = g->ml1.hub_words;
+    A.rp = V.rp;
+    A.col = V.col;
+    A.l1_seg = V.ml1->seg.as<int64_t>();
+    A.l1_src = V.ml1->src.as<int32_t>();
+    A.l1_dst = V.ml1->dst.as<int32_t>();
+    A.hub_id = V.ml1->hub_id.as<int32_t>();
+    A.hub_bits = V.ml1->hub_bits.as<uint32_t>();
+    A.hub_words = V.ml1->hub_words;
     return A;
 }
 
@@ -874,13 +1151,13 @@ __global__ __launch_bounds__(256) void k_hub_rows(int64_t n_hubs, const int32_t*
 // Dense adjacency rows for the vertices whose lists are too long to stage in
 // LDS (degree > MO_STAGE), within a memory cap (the highest degrees first
 // when the cap binds).
-static void build_hubs(pg_graph* g) {
-    MotifL1& L = g->ml1;
+static void build_hubs(pg_graph* g, const MotifView& V) {
+    MotifL1& L = *V.ml1;
     if (L.hubs_built) return;
     hipStream_t s = g->stream;
-    const int64_t n = g->n;
+    const int64_t n = V.n;
     std::vector<int64_t> hrp((size_t)n + 1);
-    PG_HIP(hipMemcpyAsync(hrp.data(), g->rp.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipMemcpyAsync(hrp.data(), V.rp, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     const int64_t words = (n + 31) / 32;
     const uint64_t cap = std::min<uint64_t>(uint64_t(2) << 30, std::max<uint64_t>(g->budget / 8, 1));
@@ -906,7 +1183,7 @@ static void build_hubs(pg_graph* g) {
         PG_HIP(hipMemcpyAsync(hl.p, hubs.data(), sizeof(int32_t) * hubs.size(), hipMemcpyHostToDevice, s));
         fill_u32(L.hub_bits.as<uint32_t>(), L.n_hubs * words, 0, s);
         k_hub_rows<<<(unsigned)std::min<int64_t>((L.n_hubs + 3) / 4, 4096), 256, 0, s>>>(
-            L.n_hubs, hl.as<int32_t>(), g->rp.as<int64_t>(), g->col.as<int32_t>(), words, L.hub_bits.as<uint32_t>());
+            L.n_hubs, hl.as<int32_t>(), V.rp, V.col, words, L.hub_bits.as<uint32_t>());
         PG_HIP(hipGetLastError());
         PG_HIP(hipStreamSynchronize(s));
     }
@@ -977,11 +1254,54 @@ static int motif_classes(int k) {
     return k == 3 ? 2 : (k == 4 ? 6 : 21);
 }
 
+// Launch shape of the map kernel: the smallest map (2^logv vertices) that
+// holds the graph, and as many workgroups as fit on the device at once.
+struct MapLaunch {
+    int logv = 0;        // 0: the graph is too large for a map in LDS
+    int blocks = 0;
+    int32_t* cum = nullptr;
+    int64_t cum_stride = 0;
+};
+
+static MapLaunch plan_map(int64_t n) {
+    MapLaunch M;
+    int logv = 16;
+    while (logv <= 19 && (int64_t(1) << logv) < n) ++logv;
+    if (logv > 19) return M;
+    M.logv = logv;
+    int per_cu = 0;
+    hipError_t e = hipSuccess;
+    switch (logv) {
+        case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_motif_last4_map<16>, MM_THREADS, 0); break;
+        case 17: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_motif_last4_map<17>, MM_THREADS, 0); break;
+        case 18: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_motif_last4_map<18>, MM_THREADS, 0); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_motif_last4_map<19>, MM_THREADS, 0); break;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    M.blocks = device_info().n_cu * std::max(1, per_cu);
+    return M;
+}
+
+static void launch_map(const MapLaunch& M, const MotifArgs& L, hipStream_t s) {
+    switch (M.logv) {
+        case 16: k_motif_last4_map<16><<<M.blocks, MM_THREADS, 0, s>>>(L, M.cum, M.cum_stride); break;
+        case 17: k_motif_last4_map<17><<<M.blocks, MM_THREADS, 0, s>>>(L, M.cum, M.cum_stride); break;
+        case 18: k_motif_last4_map<18><<<M.blocks, MM_THREADS, 0, s>>>(L, M.cum, M.cum_stride); break;
+        default: k_motif_last4_map<19><<<M.blocks, MM_THREADS, 0, s>>>(L, M.cum, M.cum_stride); break;
+    }
+    PG_HIP(hipGetLastError());
+}
+
 void count_motifs(pg_graph* g, int k, uint64_t* counts) {
     PG_REQUIRE(k >= 3 && k <= 5, PG_EUNSUPPORTED, "motif size must be 3, 4 or 5");
-    build_motif_l1(g);
-    build_hubs(g);
-    const int64_t E = g->ml1.n_edges;
+    // k = 4 runs on the graph renamed by decreasing degree
+    const MotifView V = motif_view(g, k == 4);
+    build_motif_l1(g, V);
+    build_hubs(g, V);
+    const int64_t E = V.ml1->n_edges;
     const int nc = motif_classes(k);
     for (int i = 0; i < nc; ++i) counts[i] = 0;
     if (E == 0) return;
@@ -997,13 +1317,23 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
     R.qctr = reinterpret_cast<unsigned long long*>(small + 32);
     fill_u64(small, 32, 0, s);
     // k = 5: lanes wait on dependent searches, so more waves per CU hide them
-    const int blocks5 = (int)(grid_waves(MO5_WAVES_PER_CU) / MO_WAVES);
+    // k = 5: as many workgroups per CU as its LDS and registers let reside,
+    // up to MO5_WAVES_PER_CU waves
+    int blocks5 = (int)(grid_waves(MO5_WAVES_PER_CU) / MO_WAVES);
+    if (k == 5) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_motif_last5, MO_THREADS, 0) == hipSuccess &&
+            per_cu > 0)
+            blocks5 = device_info().n_cu * std::min(per_cu, MO5_WAVES_PER_CU / MO_WAVES);
+        else
+            (void)hipGetLastError();
+    }
     int8_t* lut5 = nullptr;
     if (k == 5) {
         lut5 = push<int8_t>(ar, 1024);
         PG_HIP(hipMemcpyAsync(lut5, lut5_host().v, 1024, hipMemcpyHostToDevice, s));
     }
-    MotifArgs A = base_args(g);
+    MotifArgs A = base_args(V);
     A.x_lo = 0;
     A.x_hi = E;
     if (k == 3) {
@@ -1018,6 +1348,14 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
         const uint64_t total = read_u64(start + E, s);
         const int64_t scratch_per_wave = std::max<int64_t>(g->max_deg, 1);
         int32_t* scratch = push<int32_t>(ar, (size_t)(R.waves * scratch_per_wave));
+        MapLaunch map;
+        if (k == 4) {
+            map = plan_map(V.n);
+            if (map.logv > 0) {
+                map.cum_stride = V.max_deg + 1;
+                map.cum = push<int32_t>(ar, (size_t)map.blocks * (size_t)map.cum_stride);
+            }
+        }
         const uint64_t per = 5;   // vid + code per L2 entry
         const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
         const uint64_t cap = std::max<uint64_t>(room / per, (uint64_t)(2 * g->max_deg + 1));
@@ -1066,13 +1404,27 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
             L.scratch_per_wave = scratch_per_wave;
             const size_t mk = ar.mark();
             uint64_t* items = nullptr;
-            const int64_t m = round_items(start, c0, c1 - c0, WAVE, ar, s, &items);
+            // k = 4: entries with many children go to the map kernel, the
+            // others to the per-wave kernel
+            const int64_t light_max = (k == 4 && map.logv > 0) ? MM_HEAVY : INT64_MAX;
+            const int64_t m = round_items_between(start, c0, c1 - c0, WAVE, 0, light_max, ar, s, &items);
             if (m > 0) {
                 set_queue(R, L, items, m);
                 ProfScope ps("motif_last", s, 0.0);
                 if (k == 4) k_motif_last4<<<R.blocks, MO_THREADS, 0, s>>>(L);
                 else k_motif_last5<<<blocks5, MO_THREADS, 0, s>>>(L, lut5);
                 PG_HIP(hipGetLastError());
+            }
+            if (light_max != INT64_MAX) {
+                uint64_t* hitems = nullptr;
+                const int64_t mh = round_items_between(start, c0, c1 - c0, MM_CHILDREN, light_max, INT64_MAX, ar, s,
+                                                       &hitems);
+                if (mh > 0) {
+                    set_queue(R, L, hitems, mh);
+                    L.Q.chunk = std::max<int64_t>(1, std::min<int64_t>(8, mh / ((int64_t)map.blocks * 4)));
+                    ProfScope ps("motif_last_map", s, 0.0);
+                    launch_map(map, L, s);
+                }
             }
             ar.reset(mk);
         }
@@ -1082,10 +1434,13 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
     PG_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < nc; ++i) counts[i] = h[i];
     if (prof_on() && k == 4) {
-        // algorithmic bytes of the fused last level: per input embedding the
-        // SoA entry (5 B), the three row-pointer pairs (48 B) and one 4-byte
-        // probe per intersection item
+        // algorithmic bytes of the fused last level.  Per-wave kernel: per
+        // input embedding the SoA entry (5 B), the three row-pointer pairs
+        // (48 B) and one 4-byte probe per intersection item.  Map kernel: per
+        // input embedding the SoA entry and v2's row-pointer pair (21 B) and
+        // 4 B per candidate of its list; 4 B per list element marked.
         ProfScope ps("motif_last_work", s, 53.0 * (double)h[7] + 4.0 * (double)h[6]);
+        ProfScope pm("motif_last_map_work", s, 21.0 * (double)h[10] + 4.0 * (double)(h[9] + h[11]));
     }
     if (prof_on() && k == 5) {
         // k = 5: per level-2 entry its SoA entry and a row-pointer pair

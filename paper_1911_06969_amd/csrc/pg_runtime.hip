@@ -231,13 +231,15 @@ void fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
 
 // ------------------------------------------------------------ round items
 
+// rounds of `per` children of each segment whose child count lies in
+// [cmin, cmax); other segments get none
 template <class T>
-__global__ void k_round_counts(const T* __restrict__ seg, int64_t p_lo, int64_t n_seg, int per,
-                               uint32_t* __restrict__ rounds) {
+__global__ void k_round_counts(const T* __restrict__ seg, int64_t p_lo, int64_t n_seg, int per, int64_t cmin,
+                               int64_t cmax, uint32_t* __restrict__ rounds) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_seg;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = (int64_t)(seg[p_lo + i + 1] - seg[p_lo + i]);
-        rounds[i] = (uint32_t)((c + per - 1) / per);
+        rounds[i] = (c >= cmin && c < cmax) ? (uint32_t)((c + per - 1) / per) : 0u;
     }
 }
 
@@ -254,7 +256,8 @@ __global__ void k_round_emit(int64_t p_lo, int64_t n_seg, const uint64_t* __rest
 
 template <class T>
 static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int per, int64_t total, Arena& a,
-                                hipStream_t s, uint64_t** items, uint64_t* count_dev) {
+                                hipStream_t s, uint64_t** items, uint64_t* count_dev, int64_t cmin = 0,
+                                int64_t cmax = INT64_MAX) {
     *items = nullptr;
     if (n_seg <= 0) {
         if (count_dev) fill_u64(count_dev, 1, 0, s);
@@ -270,7 +273,7 @@ static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int p
         const size_t mk = a.mark();
         uint32_t* rounds = push<uint32_t>(a, n_seg);
         uint64_t* pos = push<uint64_t>(a, n_seg + 1);
-        k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds);
+        k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, cmin, cmax, rounds);
         PG_HIP(hipGetLastError());
         scan_u32(rounds, n_seg, pos, a, s);
         k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos, out, (uint64_t)cap, count_dev);
@@ -289,7 +292,7 @@ static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int p
     const size_t mk = a.mark();
     uint32_t* rounds = push<uint32_t>(a, n_seg);
     uint64_t* pos = push<uint64_t>(a, n_seg + 1);
-    k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds);
+    k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, cmin, cmax, rounds);
     PG_HIP(hipGetLastError());
     scan_u32(rounds, n_seg, pos, a, s);
     const int64_t m = (int64_t)read_u64(pos + n_seg, s);
@@ -299,7 +302,7 @@ static int64_t round_items_impl(const T* seg, int64_t p_lo, int64_t n_seg, int p
     const size_t mk2 = a.mark();
     uint32_t* rounds2 = push<uint32_t>(a, n_seg);
     uint64_t* pos2 = push<uint64_t>(a, n_seg + 1);
-    k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, rounds2);
+    k_round_counts<T><<<blocks, 256, 0, s>>>(seg, p_lo, n_seg, per, cmin, cmax, rounds2);
     PG_HIP(hipGetLastError());
     scan_u32(rounds2, n_seg, pos2, a, s);
     k_round_emit<<<blocks, 256, 0, s>>>(p_lo, n_seg, pos2, out, (uint64_t)m, count_dev);
@@ -317,6 +320,11 @@ int64_t round_items(const int64_t* seg, int64_t p_lo, int64_t n_seg, int per, Ar
 int64_t round_items(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, Arena& a, hipStream_t s,
                     uint64_t** items, int64_t total, uint64_t* count_dev) {
     return round_items_impl(seg, p_lo, n_seg, per, total, a, s, items, count_dev);
+}
+
+int64_t round_items_between(const uint64_t* seg, int64_t p_lo, int64_t n_seg, int per, int64_t cmin, int64_t cmax,
+                            Arena& a, hipStream_t s, uint64_t** items) {
+    return round_items_impl(seg, p_lo, n_seg, per, -1, a, s, items, nullptr, cmin, cmax);
 }
 
 uint64_t read_u64(const uint64_t* dev, hipStream_t s) {

@@ -21,10 +21,13 @@ SPLITS = (2.5e5, 1e6, 4e6, 1.6e7)
 GRID_PER_CU = (1, 2, 4)
 
 
-def tune(batch_handle, ids: np.ndarray, n_cu: int, k: int = 4, repeats: int = 2, log=None):
+def tune(batch_handle, ids: np.ndarray, n_cu: int, k: int = 4, repeats: int = 2, log=None,
+         blocks=BLOCKS, splits=SPLITS, grid_per_cu=GRID_PER_CU):
+    """Grid search; leaves the fastest parameters set on the batch and
+    returns (best, table)."""
     best = None
     table = []
-    for bt, sp, gpc in itertools.product(BLOCKS, SPLITS, GRID_PER_CU):
+    for bt, sp, gpc in itertools.product(blocks, splits, grid_per_cu):
         binding.pg_batch_set_params(batch_handle, bt, sp, gpc * n_cu)
         binding.pg_batch_count_motifs(batch_handle, k, ids)   # warm-up
         t = time.perf_counter()

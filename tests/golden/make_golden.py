@@ -4,7 +4,10 @@ library).  Run from the repository root:
 
     python tests/golden/make_golden.py [section ...]
 
-Sections: triangle_rmat_s14, clique_rmat_s21, motif_rmat_s18, fsm_er_500k.
+Sections: triangle_rmat_s14, clique_rmat_s21, motif_rmat_s18, fsm_er_500k,
+motif_batch_100k, and rmat_sweep_s20 .. rmat_sweep_s25 (the weak-scaling
+graphs: R-MAT with edge factor 10, seed 7; triangles at every scale,
+4-cliques up to scale 23).
 """
 import hashlib
 import json
@@ -64,6 +67,23 @@ def sec_fsm():
     return out
 
 
+def sec_sweep(scale):
+    """The weak-scaling sweep's graph of 2^scale vertices (edge factor 10,
+    seed 7): triangles, and 4-cliques up to scale 23."""
+    def run():
+        t = time.time()
+        g = synth.rmat(scale, 10, seed=7)
+        out = {"n": g.n, "edges": g.n_edges}
+        print(f"sweep scale {scale}: graph in {time.time() - t:.1f}s", flush=True)
+        ks = (3, 4) if scale <= 23 else (3,)
+        for k in ks:
+            t = time.time()
+            out[f"k{k}"] = oracle.clique_count(g, k)
+            print(f"sweep scale {scale} k={k}: {out[f'k{k}']} in {time.time() - t:.1f}s", flush=True)
+        return out
+    return run
+
+
 _BATCH = None
 
 
@@ -95,6 +115,8 @@ SECTIONS = {
     "motif_rmat_s18": sec_motif,
     "fsm_er_500k": sec_fsm,
 }
+for _sc in range(20, 26):
+    SECTIONS[f"rmat_sweep_s{_sc}"] = sec_sweep(_sc)
 
 
 def main(names):
@@ -102,7 +124,8 @@ def main(names):
     if os.path.exists(OUT):
         with open(OUT) as f:
             data = json.load(f)
-    for name in names or SECTIONS:
+    # the sweep sections are written only when named (hours of CPU at the top scales)
+    for name in names or [n for n in SECTIONS if not n.startswith("rmat_sweep")]:
         t = time.time()
         data[name] = SECTIONS[name]()
         print(name, f"{time.time() - t:.1f}s", flush=True)

@@ -81,7 +81,7 @@ def test_fsm_pattern_count_matches_format(lib):
     assert binding.pg_fsm_num_patterns(3, 16) == 49080
     assert binding.pg_fsm_num_patterns(1, 16) == 136
     assert binding.pg_fsm_num_patterns(2, 16) == 136 + 16 * 136
-    assert binding.pg_fsm_num_patterns(4, 16) == 0
+    assert binding.pg_fsm_num_patterns(5, 16) == 0
 
 
 def test_fsm_pattern_keys_decode_the_dense_index(lib):
@@ -92,3 +92,20 @@ def test_fsm_pattern_keys_decode_the_dense_index(lib):
     for i, (shape, lab) in enumerate(brute.pattern_table(3, L)):
         got_shape, got_lab = binding.pg_fsm_pattern_key(i, 3, L)
         assert (got_shape, tuple(got_lab)) == (shape, tuple(lab))
+
+
+def test_fsm_four_edge_index(lib):
+    """Patterns of up to four edges: the index size equals the oracle's
+    enumeration for several label counts, and the decoder walks the
+    enumerated table of the oracle's brute-force module."""
+    import oracle
+    from oracle import brute
+    for L in (1, 2, 3, 5, 16, 32):
+        assert binding.pg_fsm_num_patterns(4, L) == oracle.fsm_num_patterns(4, L), L
+    assert binding.pg_fsm_num_patterns(4, 33) == 0
+    L = 3
+    table = brute.pattern_table(4, L)
+    assert len(table) == binding.pg_fsm_num_patterns(4, L)
+    for i, (shape, lab) in enumerate(table):
+        got_shape, got_lab = binding.pg_fsm_pattern_key(i, 4, L)
+        assert (got_shape, tuple(got_lab)) == (shape, tuple(lab)), i

@@ -98,8 +98,15 @@ def test_rejects_unlabelled_and_bad_sizes(torch):
     g.n_labels = 1
     with binding.Graph.from_csr(g) as G:
         with pytest.raises(binding.PgError) as e:
-            binding.pg_fsm(G.h, 4, 1, 1)
+            binding.pg_fsm(G.h, 5, 1, 1)
         assert e.value.code == binding.PG_EUNSUPPORTED
+    g.labels = (np.arange(g.n) % 33).astype(np.int32)
+    g.n_labels = 33
+    with binding.Graph.from_csr(g) as G:
+        # four edges need at most 32 labels
+        with pytest.raises(binding.PgError) as e:
+            binding.pg_fsm(G.h, 4, 1, 33)
+        assert e.value.code in (binding.PG_EUNSUPPORTED, binding.PG_EINVAL)
 
 
 @pytest.mark.slow
@@ -114,3 +121,54 @@ def test_fsm_er_config(torch):
     assert int(sup.sum()) == want["sum"]
     assert [int(sup[i]) for i in want["sample_index"]] == want["sample_support"]
     assert hashlib.sha256(sup.astype(np.uint64).tobytes()).hexdigest() == want["sha256"]
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_four_edges_against_injective_maps(torch, seed):
+    """Patterns of four edges (5-path, 4-star, fork, 4-cycle, paw) on tiny
+    graphs: supports by definition from injective maps."""
+    rng = np.random.default_rng(900 + seed)
+    L = int(rng.integers(1, 4))
+    g = synth.gnp_small(int(rng.integers(5, 10)), float(rng.uniform(0.25, 0.7)), 50 + seed, n_labels=L)
+    for sigma in (0, 1, 2, 3):
+        want = brute.fsm(g, 4, sigma)
+        say(f"fsm4 brute seed={seed} n={g.n} L={L} sigma={sigma}")
+        assert np.array_equal(gpu_fsm(g, 4, sigma), want), (seed, sigma)
+
+
+def test_four_edge_shapes_one_by_one(torch):
+    """Each four-edge shape alone with distinct and with equal labels: its
+    pattern's support is the smallest orbit's domain."""
+    shapes = {
+        "path5": [(0, 1), (1, 2), (2, 3), (3, 4)],
+        "star4": [(0, 1), (0, 2), (0, 3), (0, 4)],
+        "fork": [(0, 1), (0, 2), (0, 3), (3, 4)],
+        "cycle4": [(0, 1), (1, 2), (2, 3), (3, 0)],
+        "paw": [(0, 1), (0, 2), (0, 3), (2, 3)],
+    }
+    for name, edges in shapes.items():
+        n = 1 + max(max(e) for e in edges)
+        for labels in (np.zeros(n, np.int32), np.arange(n, dtype=np.int32) % 3):
+            L = int(labels.max()) + 1
+            g = synth.from_edges(n, edges)
+            g = synth.CSR(g.row_ptr, g.col, labels, L)
+            want = brute.fsm(g, 4, 1)
+            assert np.array_equal(gpu_fsm(g, 4, 1), want), (name, labels)
+
+
+@pytest.mark.parametrize("n,p,L,sigma", [(1500, 6 / 1499, 3, 40), (2500, 0.002, 4, 5), (500, 0.016, 2, 60)])
+def test_four_edges_er_against_oracle(torch, n, p, L, sigma):
+    g = synth.erdos_renyi(n, p, seed=61, n_labels=L)
+    want = oracle.fsm(g, 4, sigma)
+    say("fsm4 er", n, L, sigma, int((want > 0).sum()))
+    assert np.array_equal(gpu_fsm(g, 4, sigma), want)
+
+
+def test_four_edges_power_law_and_small_budget(torch):
+    """A skewed graph (hub lists, many embeddings per pattern) and a budget
+    that forces the level-4 domain bitmaps into several groups."""
+    g = synth.rmat(8, 2, seed=62)
+    g = synth.CSR(g.row_ptr, g.col, synth.random_labels(g.n, 3, 63), 3)
+    want = oracle.fsm(g, 4, 20)
+    assert np.array_equal(gpu_fsm(g, 4, 20), want)
+    assert np.array_equal(gpu_fsm(g, 4, 20, budget=1 << 20), want)

@@ -102,3 +102,41 @@ def test_bench_workload_against_esu(torch):
     got = gpu_motifs(g)
     assert got == [int(x) for x in oracle.motif_esu(g, 5)]
     assert sum(got) > 4 * 10**8
+
+
+def test_hub_lists_beyond_the_stage(torch):
+    """Hubs of degree above 256, whose lists are not staged in LDS: a star of
+    300 leaves with the hub first (v0) and last (v1) in vertex order, and a
+    complete bipartite K_{2,300} (two hubs sharing every neighbour), against
+    closed forms."""
+    star = _class_of([(0, 1), (0, 2), (0, 3), (0, 4)])
+    k23 = _class_of([(a, b) for a in (0, 1) for b in (2, 3, 4)])
+    s = synth.star(300)
+    one = [0] * 21
+    one[star] = comb(300, 4)
+    assert gpu_motifs(s) == one
+    perm = np.arange(s.n)
+    perm[0], perm[-1] = perm[-1], perm[0]          # hub named 300
+    assert gpu_motifs(synth.relabel(s, perm)) == one
+    a, b = 2, 300
+    want = [0] * 21
+    want[star] = a * comb(b, 4) + b * comb(a, 4)
+    want[k23] = comb(a, 2) * comb(b, 3) + comb(a, 3) * comb(b, 2)
+    assert gpu_motifs(synth.complete_multipartite([a, b])) == want
+
+
+@pytest.mark.slow
+def test_sparse_graph_with_hub_against_esu(torch):
+    """A sparse G(n, p) with one added hub of degree 270 (lists of v0, v1
+    and mixed staged/unstaged pairs), class by class against the oracle's
+    ESU."""
+    base = synth.erdos_renyi(3000, 3.0 / 2999, seed=21)
+    rng = np.random.default_rng(22)
+    hub = base.n
+    nbrs = np.sort(rng.choice(base.n, 270, replace=False))
+    edges = [(int(u), int(v)) for u in range(base.n) for v in base.col[base.row_ptr[u]:base.row_ptr[u + 1]] if u < v]
+    edges += [(int(v), hub) for v in nbrs]
+    g = synth.from_edges(base.n + 1, edges)
+    say("motif5 sparse + hub 270")
+    want = [int(x) for x in oracle.motif_esu(g, 5)]
+    assert gpu_motifs(g) == want

@@ -141,3 +141,35 @@ def test_binary_search_connectivity_example(torch):
     assert gpu_motifs(g, 4) == [0, 0, 0, 1, 0, 0]
     assert gpu_motifs(g, 4) == [int(x) for x in brute.motif_counts(g, 4)]
     assert gpu_motifs(g, 3) == [int(x) for x in brute.motif_counts(g, 3)]
+
+
+@pytest.mark.parametrize("n_total", [60_000, 70_000, 200_000, 300_000, 600_000])
+def test_map_kernel_sizes(torch, n_total):
+    """4-motifs on graphs whose vertex count selects each size of the
+    workgroup's two-bit vertex map (up to 2^16, 2^17, 2^18, 2^19 vertices)
+    and one beyond it (per-wave kernel only): a hub of degree 3000, a dense
+    random block and isolated vertices, against the closed form."""
+    parts = [synth.star(3000), synth.erdos_renyi(700, 0.4, seed=11), synth.rmat(11, 8, seed=5)]
+    used = sum(p.n for p in parts)
+    g = synth.disjoint_union(*parts, synth.empty(n_total - used))
+    assert g.n == n_total
+    want = [int(x) for x in closed_form.motif4(g)]
+    say("map sizes", n_total, want)
+    assert gpu_motifs(g, 4) == want
+
+
+def test_map_kernel_shared_hub_and_threshold(torch):
+    """Entries just below and above the many-children threshold (255, 256
+    and 257 leaves beyond a shared pair), a complete bipartite K_{2,300}
+    (two hubs sharing every neighbour) and a budget small enough to cut the
+    level-2 list into many chunks."""
+    parts = [synth.complete_multipartite([2, 300])]
+    for leaves in (255, 256, 257, 513):
+        parts.append(synth.star(leaves))
+    g = synth.disjoint_union(*parts, synth.erdos_renyi(700, 0.5, seed=9))
+    want = [int(x) for x in closed_form.motif4(g)]
+    a, b = 2, 300
+    kab = [0, a * comb(b, 3) + b * comb(a, 3), comb(a, 2) * comb(b, 2), 0, 0, 0]
+    assert [int(x) for x in closed_form.motif4(parts[0])] == kab
+    assert gpu_motifs(g, 4) == want
+    assert gpu_motifs(g, 4, budget=1 << 20) == want

@@ -95,3 +95,33 @@ def test_admission_respects_footprint_budget(loaded):
         srv.close()
     assert st.max_inflight_bytes <= max(budget, int(fp.max()))
     assert np.array_equal(st.results, eager[ids])
+
+
+def test_autotuner_grid_keeps_counts(torch, loaded):
+    """The autotuner over a 2 x 2 grid (workgroup size x grid size) leaves
+    its best parameters on the batch; counts are unchanged for direct calls
+    and for a slot that re-captures its launch with them."""
+    from paper_1911_06969_amd import tune
+    b, h, eager, _ = loaded
+    ids = np.arange(0, b.n_graphs, 3)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    rows = []
+    slot = binding.pg_batch_slot_create(h, 128)
+    try:
+        before = binding.pg_batch_slot_submit(slot, 4, ids[:100])
+        assert np.array_equal(binding.pg_batch_slot_wait(slot, before), eager[ids[:100]])
+        best, table = tune.tune(h, ids, n_cu, repeats=1, log=rows.append, blocks=(128, 512), splits=(2.5e5,),
+                                grid_per_cu=(1, 3))
+        assert len(table) == 4 and best in table
+        say("tuned", best)
+        assert np.array_equal(binding.pg_batch_count_motifs(h, 4, ids), eager[ids])
+        n = binding.pg_batch_slot_submit(slot, 4, ids[100:228])
+        assert np.array_equal(binding.pg_batch_slot_wait(slot, n), eager[ids[100:228]])
+        # parameters that differ from the tuned ones, then the slot again
+        binding.pg_batch_set_params(h, 64, 1e5, 7)
+        n = binding.pg_batch_slot_submit(slot, 4, ids[:50])
+        assert np.array_equal(binding.pg_batch_slot_wait(slot, n), eager[ids[:50]])
+        assert np.array_equal(binding.pg_batch_count_motifs(h, 4, ids), eager[ids])
+    finally:
+        binding.pg_batch_slot_free(slot)
+        binding.pg_batch_set_params(h, 256, 4e6, 2 * n_cu)
