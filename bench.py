@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="clique4",
                     choices=["clique4", "clique5", "motif4", "motif3", "motif5", "tc", "fsm", "copy", "tune-batch",
-                             "rmat-sweep"],
+                             "rmat-sweep", "serve"],
                     help="copy: a plain 1 GiB device-to-device copy, the known-size reference "
                          "for scaling HBM counters; rmat-sweep: triangles and 4-cliques on R-MAT "
                          "graphs of 2^20 .. 2^25 vertices, average degree 20 (weak scaling)")
@@ -53,7 +53,9 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 4-motif, batched and served measurements")
     ap.add_argument("--plain-sample", type=int, default=2000)
-    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-requests", type=int, default=200000)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=1024)
     ap.add_argument("--cpu-sample-seconds", type=float, default=15.0)
     ap.add_argument("--tuning", default=os.path.join(ROOT, "profiles", "batch_tuning.json"),
                     help="batch-kernel parameters picked by the autotuner (applied when present)")
@@ -144,6 +146,30 @@ def cpu_baseline_motif5(g, want_seconds: float = 10.0):
     }
 
 
+def cpu_baseline_fsm(n_sample: int = 200_000):
+    """The oracle's edge-subset enumeration with domain sets, patterns of up
+    to 3 edges, unfiltered, on a smaller graph of the same recipe (labelled
+    G(n, p) with average degree 8 and 16 labels): domain supports do not
+    split over parts of a graph, so the sample is a whole graph of n_sample
+    vertices.  The embeddings it enumerates are the unit."""
+    from oracle import fsm_supports_all, max_threads
+    from paper_1911_06969_amd import synth
+    g = synth.erdos_renyi(n_sample, 8.0 / (n_sample - 1), seed=4, n_labels=16)
+    t = time.perf_counter()
+    _, cnt = fsm_supports_all(g, 3)
+    dt = time.perf_counter() - t
+    found = int(cnt.sum())
+    return {
+        "value": found / dt,
+        "unit": "embeddings/s",
+        "cores": max_threads(),
+        "kind": "oracle",
+        "sample": f"labelled G(n,p) n={n_sample}, average degree 8, 16 labels, seed 4 (the workload's recipe at "
+                  f"{100 * n_sample / 500000:.0f}% of its vertices): {found} embeddings of 1-3 edges with domain "
+                  f"sets in {dt:.1f} s",
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -196,43 +222,83 @@ def main():
     if w == "rmat-sweep":
         rmat_sweep(args, binding, synth, stream)
         return
+    if w == "serve":
+        print(json.dumps({"workload": "serve", "batch": measure_batch_and_serve(args)}), flush=True)
+        return
+    line = measure(w, args, args.steps, args.warmup, not args.no_cpu_baseline, stream)
+    secondary = {}
+    if w == "clique4" and not args.no_secondary:
+        for sw, steps in (("motif4", 2), ("clique5", 3), ("tc", 20), ("motif3", 5), ("fsm", 3)):
+            note("secondary:", sw)
+            sec = measure(sw, args, steps, 1, not args.no_cpu_baseline, stream)
+            secondary[sw] = {k: sec[k] for k in ("config", "value", "unit", "ms_per_step", "steps", "result",
+                                                 "roofline", "cpu_baseline", "kernels") if k in sec}
+        note("secondary: batched graphs, plain sample, serving")
+        secondary["batch"] = measure_batch_and_serve(args)
+    out = {
+        "metric": METRIC,
+        "value": line["value"],
+        "unit": line["unit"],
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": line["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": line["data"],
+        "config": line["config"],
+        "result": line["result"],
+        "roofline": line["roofline"],
+        "cpu_baseline": line["cpu_baseline"],
+        "preprocess": line["preprocess"],
+        "kernels": line["kernels"],
+        "secondary": secondary or None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def workload_of(w, synth):
+    """(graph, one step, description) of a named workload."""
     if w == "fsm":
         g = synth.fsm_er()
-        run = lambda G: G.fsm(3, 1000)[1]  # noqa: E731
-        dominant, work_key = "fsm_l3_bits", "fsm_l3_bits_work"
-        workload = {"workload": "frequent subgraph mining up to 3 edges, sigma 1000, labelled G(n,p) "
-                                "n=500,000, average degree 8, 16 labels, seed 4",
-                    "vertices": g.n, "edges": g.n_edges}
-    elif w in ("clique4", "clique5"):
+        return g, (lambda G: G.fsm(3, 1000)[1]), {
+            "workload": "frequent subgraph mining up to 3 edges, sigma 1000, labelled G(n,p) n=500,000, "
+                        "average degree 8, 16 labels, seed 4", "vertices": g.n, "edges": g.n_edges}
+    if w in ("clique4", "clique5"):
         g = synth.clique_rmat()
         k = 4 if w == "clique4" else 5
-        run = lambda G: G.cliques(k)  # noqa: E731
-        dominant, work_key = "clique_last", "clique_last_work"
-        workload = {"workload": f"{k}-clique counting, R-MAT scale 21 (2,097,152 vertices), edge factor 13, "
-                                f"a=0.57 b=0.19 c=0.19, degree-ordered DAG, int32 CSR, seed 2",
-                    "k": k, "vertices": g.n, "edges": g.n_edges}
-    elif w == "motif5":
+        return g, (lambda G: G.cliques(k)), {
+            "workload": f"{k}-clique counting, R-MAT scale 21 (2,097,152 vertices), edge factor 13, "
+                        f"a=0.57 b=0.19 c=0.19, degree-ordered DAG, int32 CSR, seed 2",
+            "k": k, "vertices": g.n, "edges": g.n_edges}
+    if w == "motif5":
         n = 100_000
         g = synth.erdos_renyi(n, 8.0 / (n - 1), seed=12)
-        k = 5
-        run = lambda G: G.motifs(5)  # noqa: E731
-        dominant, work_key = "motif_last", "motif_last_work"
-        workload = {"workload": "5-motif counting, G(n,p) n=100,000, average degree 8, seed 12",
-                    "k": 5, "vertices": g.n, "edges": g.n_edges}
-    elif w == "tc":
+        return g, (lambda G: G.motifs(5)), {"workload": "5-motif counting, G(n,p) n=100,000, average degree 8, "
+                                                        "seed 12", "k": 5, "vertices": g.n, "edges": g.n_edges}
+    if w == "tc":
         g = synth.triangle_rmat()
-        k = 3
-        run = lambda G: G.cliques(3)  # noqa: E731
-        dominant, work_key = "clique_last", "clique_last_work"
-        workload = {"workload": "triangle counting, R-MAT scale 14, edge factor 8, seed 1",
-                    "k": 3, "vertices": g.n, "edges": g.n_edges}
-    else:
-        g = synth.motif_rmat()
-        k = 4 if w == "motif4" else 3
-        run = lambda G: G.motifs(k)  # noqa: E731
-        dominant, work_key = "motif_last", "motif_last_work"
-        workload = {"workload": f"{k}-motif counting, R-MAT scale 18 (262,144 vertices), edge factor 8, "
-                                f"undirected int32 CSR, seed 3", "k": k, "vertices": g.n, "edges": g.n_edges}
+        return g, (lambda G: G.cliques(3)), {"workload": "triangle counting, R-MAT scale 14, edge factor 8, seed 1",
+                                             "k": 3, "vertices": g.n, "edges": g.n_edges}
+    g = synth.motif_rmat()
+    k = 4 if w == "motif4" else 3
+    return g, (lambda G: G.motifs(k)), {
+        "workload": f"{k}-motif counting, R-MAT scale 18 (262,144 vertices), edge factor 8, undirected int32 CSR, "
+                    f"seed 3", "k": k, "vertices": g.n, "edges": g.n_edges}
+
+
+def measure(w, args, steps, warmup, cpu_leg, stream):
+    """Times `steps` steps of workload w on the resident graph, with the
+    dominant kernel's roofline from HIP events and, when asked, the oracle
+    on a bounded sample of the same workload."""
+    import numpy as np
+    import torch
+
+    from paper_1911_06969_amd import binding, synth
+    g, run, workload = workload_of(w, synth)
+    k = workload.get("k")
 
     note("workload", w, "graph ready:", g.n, "vertices")
     # preprocessing, excluded from the timed steps and reported beside them:
@@ -244,14 +310,14 @@ def main():
     torch.cuda.synchronize()
     t_first = time.perf_counter()
     result = None
-    for i in range(args.warmup):
+    for i in range(warmup):
         result = run(G)
         if i == 0:
             torch.cuda.synchronize()
             t_first_end = time.perf_counter()
     torch.cuda.synchronize()
     preprocess = {"load_ms": round(1000 * (t_first - t_load), 2)}
-    if args.warmup > 0:
+    if warmup > 0:
         preprocess["first_call_ms"] = round(1000 * (t_first_end - t_first), 2)
     note("warm-up done")
 
@@ -259,92 +325,69 @@ def main():
     binding.pg_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         result = run(G)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     binding.pg_profile_enable(False)
-    note(f"timed {args.steps} steps in {elapsed:.3f} s")
+    note(f"{w}: timed {steps} steps in {elapsed:.3f} s")
 
     found = int(np.sum(result)) if not isinstance(result, int) else result
     if w == "fsm":
         # embeddings generated per step (all levels); result = frequent patterns
         emb = binding.pg_profile_query("fsm_embeddings")
         workload["frequent_patterns"] = result
-        found = int(emb[2] / args.steps) if emb else 0
-    ms_per_step = 1000.0 * elapsed / args.steps
-    value = found * args.steps / elapsed
+        found = int(emb[2] / steps) if emb else 0
+    ms_per_step = 1000.0 * elapsed / steps
+    value = found * steps / elapsed
 
     roofline = None
     kernels = {}
     for name in binding.pg_profile_list():
         q = binding.pg_profile_query(name)
         if q and not name.endswith("_work"):
-            kernels[name] = {"ms_per_step": q[0] / args.steps, "launches_per_step": q[1] / args.steps}
+            kernels[name] = {"ms_per_step": q[0] / steps, "launches_per_step": q[1] / steps}
     # the dominant kernel is the one with the largest time per step that
     # records its algorithmic bytes
     with_work = [n for n in kernels if binding.pg_profile_query(n + "_work")]
     if with_work:
         dominant = max(with_work, key=lambda n: kernels[n]["ms_per_step"])
-        work_key = dominant + "_work"
-    prof = binding.pg_profile_query(dominant)
-    work = binding.pg_profile_query(work_key)
-    if prof and work and prof[1] > 0:
-        avg_s = prof[0] / 1000.0 / prof[1]
-        bytes_per_launch = work[2] / prof[1]
-        achieved = bytes_per_launch / avg_s / 1e9
-        traffic = None
-        if os.path.exists(args.traffic):
-            with open(args.traffic) as f:
-                t = json.load(f)
-            entry = t.get(w)
-            if entry and entry.get("kernel_source_sha") == kernel_source_sha(w):
-                traffic = entry["bytes_per_launch"]
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                    "kernel": dominant, "avg_launch_ms": round(1000 * avg_s, 3),
-                    "algorithmic_bytes_per_launch": bytes_per_launch}
+        prof = binding.pg_profile_query(dominant)
+        work = binding.pg_profile_query(dominant + "_work")
+        if prof and work and prof[1] > 0:
+            avg_s = prof[0] / 1000.0 / prof[1]
+            bytes_per_launch = work[2] / prof[1]
+            achieved = bytes_per_launch / avg_s / 1e9
+            traffic = None
+            if os.path.exists(args.traffic):
+                with open(args.traffic) as f:
+                    t = json.load(f)
+                entry = t.get(w)
+                if entry and entry.get("kernel") == dominant and entry.get("kernel_source_sha") == kernel_source_sha(w):
+                    traffic = entry["bytes_per_launch"]
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "kernel": dominant, "avg_launch_ms": round(1000 * avg_s, 3),
+                        "algorithmic_bytes_per_launch": bytes_per_launch}
 
     cpu = None
-    if not args.no_cpu_baseline:
-        note("cpu baseline (oracle)")
+    if cpu_leg:
+        note("cpu baseline (oracle)", w)
         if w.startswith("clique") or w == "tc":
             cpu = cpu_baseline_cliques(g, k, args.cpu_sample_seconds)
         elif w == "motif5":
             cpu = cpu_baseline_motif5(g, args.cpu_sample_seconds)
         elif w.startswith("motif"):
             cpu = cpu_baseline_motifs(g, k)
-
+        elif w == "fsm":
+            cpu = cpu_baseline_fsm()
     G.close()
-    secondary = {}
-    if w == "clique4" and not args.no_secondary:
-        note("secondary: 4-motif")
-        secondary["motif4"] = measure_motif4()
-        note("secondary: batched graphs, plain sample, serving")
-        secondary["batch"] = measure_batch_and_serve(args)
-
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "embeddings/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic (seeded G(n,p))" if w in ("fsm", "motif5") else "synthetic (seeded R-MAT)",
-        "config": workload,
+    return {
+        "config": workload, "value": value, "unit": "embeddings/s", "ms_per_step": ms_per_step, "steps": steps,
         "result": found if isinstance(result, int) else [int(x) for x in result],
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "preprocess": preprocess,
-        "kernels": kernels,
-        "secondary": secondary or None,
+        "data": "synthetic (seeded G(n,p))" if w in ("fsm", "motif5") else "synthetic (seeded R-MAT)",
+        "roofline": roofline, "cpu_baseline": cpu, "preprocess": preprocess, "kernels": kernels,
     }
-    print(json.dumps(line), flush=True)
 
 
 def rmat_sweep(args, binding, synth, stream):
@@ -379,25 +422,6 @@ def rmat_sweep(args, binding, synth, stream):
     print(json.dumps({"workload": "R-MAT weak-scaling sweep: triangles and 4-cliques, edge factor 10 "
                                   "(average degree 20), a=0.57 b=0.19 c=0.19, seed 7",
                       "data": "synthetic (seeded R-MAT)", "rows": rows}), flush=True)
-
-
-def measure_motif4(steps: int = 2):
-    """4-motif counting on the R-MAT scale-18 graph (embeddings/s)."""
-    import torch
-
-    from paper_1911_06969_amd import binding, synth
-    g = synth.motif_rmat()
-    with binding.Graph.from_csr(g, stream=torch.cuda.current_stream()) as G:
-        res = G.motifs(4)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(steps):
-            res = G.motifs(4)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t) / steps
-    total = int(sum(int(x) for x in res))
-    return {"workload": "4-motif counting, R-MAT scale 18, edge factor 8, seed 3", "embeddings": total,
-            "ms_per_step": 1000 * dt, "embeddings_per_s": total / dt}
 
 
 def measure_batch_and_serve(args):
@@ -465,7 +489,7 @@ def measure_batch_and_serve(args):
         out["batched_over_plain_same_kernel"] = out["batched_graphs_per_s"] / out["plain_same_kernel_graphs_per_s"]
         # serving: Poisson arrivals at fractions of the batched capacity
         fp = serve.graph_footprints(b.voff, b.row_ptr)
-        srv = serve.Server(h, fp, n_slots=4, max_batch=1024, budget_bytes=8 << 30)
+        srv = serve.Server(h, fp, n_slots=args.serve_slots, max_batch=args.serve_batch, budget_bytes=8 << 30)
         loads = []
         try:
             cap = out["batched_graphs_per_s"]
@@ -476,8 +500,9 @@ def measure_batch_and_serve(args):
                 note(f"served load {rho}: p50 {st.p50_ms:.2f} ms p99 {st.p99_ms:.2f} ms")
                 assert np.array_equal(st.results, counts[ids]), "served counts differ from the batched run"
                 loads.append({"offered_load": rho, "offered_rate": rho * cap, "requests": st.n_requests,
-                              "throughput": st.throughput, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
-                              "mean_batch": st.mean_batch})
+                              "throughput": st.throughput, "served_over_offered": st.throughput / (rho * cap),
+                              "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "mean_batch": st.mean_batch,
+                              "seconds": st.elapsed_s})
         finally:
             srv.close()
         out["serving"] = loads

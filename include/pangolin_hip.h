@@ -49,6 +49,7 @@ typedef struct pg_batch pg_batch;   /* opaque, many small graphs, device residen
 
 /* flags for pg_graph_load_csr / pg_batch_load */
 #define PG_DEVICE_PTRS 1u   /* the CSR arrays are device pointers */
+#define PG_CANONICALIZE 2u  /* pg_graph_load_csr only: make the CSR canonical on the device */
 
 #define PG_KMAX 8           /* largest clique size */
 
@@ -64,10 +65,15 @@ typedef struct pg_batch pg_batch;   /* opaque, many small graphs, device residen
  *   col_idx   int32[nnz], neighbours of v at row_ptr[v] .. row_ptr[v+1]-1
  *   labels    int32[n] vertex labels in [0, n_labels), or NULL (unlabelled)
  *   n_labels  number of labels (0 when labels == NULL), at most 64
- *   flags     PG_DEVICE_PTRS or 0
+ *   flags     PG_DEVICE_PTRS and/or PG_CANONICALIZE, or 0
  *   stream    hipStream_t for all work on this graph, or NULL (null stream)
  *   out       receives the handle
- * The CSR is validated on the device; a violation returns PG_EINVAL.
+ * The CSR is validated on the device; a violation returns PG_EINVAL.  With
+ * PG_CANONICALIZE the library first rebuilds the rows on the device as the
+ * symmetric closure of the entries, sorted ascending, without self-loops
+ * and duplicates (the input itself is not modified); row_ptr must still be
+ * non-decreasing from 0 to nnz and every id in [0, n), else PG_EINVAL.
+ * pg_graph_info then reports the canonical nnz.
  */
 int pg_graph_load_csr(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                       const int32_t* labels, int32_t n_labels, unsigned flags, void* stream,

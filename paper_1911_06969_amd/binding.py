@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpangolin_hip.so")
 
 PG_OK, PG_EINVAL, PG_ENOMEM, PG_EUNSUPPORTED, PG_EDEVICE, PG_EOVERFLOW = 0, -1, -2, -3, -4, -5
 PG_DEVICE_PTRS = 1
+PG_CANONICALIZE = 2
 PG_KMAX = 8
 PG_BATCH_MAX_VERTICES = 512
 
@@ -89,7 +90,43 @@ def load_library(path: str | None = None):
         if name not in ("pg_fsm_num_patterns", "pg_last_error", "pg_version"):
             f.restype = cint
     _lib = lib
+    if os.environ.get("PG_ALLOCATOR", "torch") == "torch":
+        use_torch_allocator()
     return lib
+
+
+_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_torch_hooks = None
+
+
+def use_torch_allocator() -> bool:
+    """Routes the library's device allocations through torch's caching
+    allocator (pg_set_allocator), so that graphs, levels and batches share
+    torch's memory pool.  Done by load_library unless PG_ALLOCATOR=hip; a
+    no-op without a GPU.  Returns whether the hooks are installed."""
+    global _torch_hooks
+    try:
+        import torch
+    except ImportError:
+        return False
+    if not torch.cuda.is_available():
+        return False
+
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:
+            return None
+
+    def free(p, ctx):
+        torch.cuda.caching_allocator_delete(int(p))
+
+    hooks = (_ALLOC(alloc), _FREE(free))
+    if _lib.pg_set_allocator(hooks[0], hooks[1], None) != PG_OK:
+        return False
+    _torch_hooks = hooks   # the callbacks must outlive every allocation
+    return True
 
 
 def _check(rc: int):
@@ -125,9 +162,10 @@ def _stream_ptr(stream):
 
 # ---------------------------------------------------------------- graphs
 
-def pg_graph_load_csr(row_ptr, col_idx, labels=None, n_labels: int = 0, stream=None):
+def pg_graph_load_csr(row_ptr, col_idx, labels=None, n_labels: int = 0, stream=None, canonicalize: bool = False):
     """Loads a CSR graph (numpy host arrays or torch GPU tensors).  Returns
-    the opaque handle."""
+    the opaque handle.  canonicalize: PG_CANONICALIZE (the library sorts,
+    symmetrises and drops loops and duplicates)."""
     lib = load_library()
     dev = _is_torch(row_ptr)
     keep = []
@@ -147,6 +185,8 @@ def pg_graph_load_csr(row_ptr, col_idx, labels=None, n_labels: int = 0, stream=N
             lab, plab = _host(labels, np.int32)
             keep.append(lab)
         flags = 0
+    if canonicalize:
+        flags |= PG_CANONICALIZE
     out = ctypes.c_void_p()
     _check(lib.pg_graph_load_csr(n, nnz, prp, pcol, plab, n_labels if labels is not None else 0, flags,
                                  _stream_ptr(stream), ctypes.byref(out)))
@@ -364,13 +404,17 @@ def pg_profile_list() -> list:
 class Graph:
     """Owns a pg_graph handle."""
 
-    def __init__(self, row_ptr, col_idx, labels=None, n_labels: int = 0, stream=None):
+    def __init__(self, row_ptr, col_idx, labels=None, n_labels: int = 0, stream=None, canonicalize: bool = False):
         self.n_labels = n_labels if labels is not None else 0
-        self.h = pg_graph_load_csr(row_ptr, col_idx, labels, n_labels, stream)
+        self.h = pg_graph_load_csr(row_ptr, col_idx, labels, n_labels, stream, canonicalize)
 
     @classmethod
-    def from_csr(cls, g, stream=None):
-        return cls(g.row_ptr, g.col, g.labels, g.n_labels, stream)
+    def from_csr(cls, g, stream=None, canonicalize: bool = False):
+        return cls(g.row_ptr, g.col, g.labels, g.n_labels, stream, canonicalize)
+
+    def info(self):
+        """(vertices, directed entries, maximum degree)."""
+        return pg_graph_info(self.h)
 
     def cliques(self, k: int) -> int:
         return pg_count_cliques(self.h, k)

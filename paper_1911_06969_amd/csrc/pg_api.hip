@@ -82,7 +82,7 @@ int pg_graph_load_csr(int64_t n, int64_t nnz, const int64_t* row_ptr, const int3
                       const int32_t* labels, int32_t n_labels, unsigned flags, void* stream, pg_graph** out) {
     return guarded([&] {
         PG_REQUIRE(out != nullptr, PG_EINVAL, "out is NULL");
-        PG_REQUIRE((flags & ~PG_DEVICE_PTRS) == 0, PG_EINVAL, "unknown flag");
+        PG_REQUIRE((flags & ~(PG_DEVICE_PTRS | PG_CANONICALIZE)) == 0, PG_EINVAL, "unknown flag");
         require_device();
         pg_graph* g = new pg_graph();
         g->stream = static_cast<hipStream_t>(stream);

@@ -1143,6 +1143,173 @@ __global__ void k_heavy_lists(int64_t n, const int64_t* __restrict__ rp, const i
     }
 }
 
+// ------------------------------------------------ heavy roots, k = 3 and 4
+//
+// Roots of out-degree D above BM_MAXD (up to HM_MAXD) keep their sibling
+// rows in device memory: row i of root r is the set of positions j of
+// out(r) whose vertex is an out-neighbour of out(r)[i] (all above i), in
+// W = ceil(D / 64) words.  The triangles at r are the rows' set bits; its
+// 4-cliques are the popcounts of row i AND row j over every set bit j of
+// row i (bits of row j lie above j, so each 4-clique is counted once).
+constexpr int HM_MAXD = 8192;
+constexpr int HM_WMAX = HM_MAXD / 64;    // row words at most (two per lane)
+constexpr int HM_THREADS = 256;
+constexpr int HM_WAVES = HM_THREADS / WAVE;
+constexpr int HM_BLOCK = 64;             // rows per work item
+
+struct HmArgs {
+    XcdQueue Q;
+    const uint64_t* items;        // (heavy root index, block of HM_BLOCK rows)
+    const int32_t* hroot;
+    const uint64_t* hoff;
+    const int64_t* rp;            // DAG
+    const int32_t* col;
+    uint64_t* rows;               // row words; NULL: triangles only
+    unsigned long long* stats;    // [0] += cliques, [5] += out-list elements streamed, [6] += row pairs
+};
+
+// heavy root flags and sizes: out-degree, and row words D * W
+__global__ void k_heavy_flags(int64_t n, const int64_t* __restrict__ rp, uint32_t* __restrict__ flag) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        flag[r] = (rp[r + 1] - rp[r] > BM_MAXD) ? 1u : 0u;
+}
+
+__global__ void k_heavy_fill(int64_t n, const int64_t* __restrict__ rp, const uint64_t* __restrict__ pos,
+                             int32_t* __restrict__ hroot, uint32_t* __restrict__ hdeg, uint64_t* __restrict__ hw) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        if (pos[r + 1] > pos[r]) {
+            const int64_t d = rp[r + 1] - rp[r];
+            hroot[pos[r]] = (int32_t)r;
+            hdeg[pos[r]] = (uint32_t)d;
+            hw[pos[r]] = (uint64_t)d * (uint64_t)((d + 63) >> 6);
+        }
+}
+
+// Rows: a workgroup stages out(r) in LDS for an item; each wave builds rows
+// of the item's block, all lanes streaming out(v) (cut at out(r)'s last
+// vertex) and searching each element among out(r)'s later positions.
+__global__ __launch_bounds__(HM_THREADS) void k_heavy_rows(HmArgs A) {
+    __shared__ int32_t S[HM_MAXD];
+    __shared__ unsigned long long row[HM_WAVES][HM_WMAX];
+    __shared__ int64_t s_next[2];
+    const int w = threadIdx.x / WAVE;
+    for (int k = lane(); k < HM_WMAX; k += WAVE) row[w][k] = 0ull;
+    uint64_t found = 0, streamed = 0;
+    QueueCursor cur = queue_start();
+    while (true) {
+        __syncthreads();
+        if (w == 0) {
+            int64_t e = 0;
+            const int64_t f = queue_next(A.Q, cur, e);
+            if (lane() == 0) {
+                s_next[0] = f;
+                s_next[1] = e;
+            }
+        }
+        __syncthreads();
+        const int64_t first = s_next[0], last = s_next[1];
+        if (first < 0) break;
+        for (int64_t jt = first; jt < last; ++jt) {
+            const uint64_t item = A.items[jt];
+            const int64_t h = item_seg(item);
+            const int32_t r = A.hroot[h];
+            const int64_t b = A.rp[r];
+            const int32_t D = (int32_t)(A.rp[r + 1] - b);
+            const int32_t W = (D + 63) >> 6;
+            __syncthreads();   // the previous item's searches are done
+            for (int k = threadIdx.x; k < D; k += HM_THREADS) S[k] = A.col[b + k];
+            __syncthreads();
+            const int32_t s_last = S[D - 1];
+            const int32_t i0 = (int32_t)item_round(item) * HM_BLOCK;
+            const int32_t i1 = min(i0 + HM_BLOCK, D);
+            uint64_t* R = A.rows ? A.rows + A.hoff[h] : nullptr;
+            for (int32_t i = i0 + w; i < i1; i += HM_WAVES) {
+                const int32_t v = S[i];
+                const int64_t lo = A.rp[v];
+                const int64_t hi = upper_bound(A.col, lo, A.rp[v + 1], s_last);
+                streamed += (uint64_t)(hi - lo);
+                for (int64_t t0 = lo; t0 < hi; t0 += WAVE) {
+                    const int64_t t = t0 + lane();
+                    if (t < hi) {
+                        const int32_t u = A.col[t];
+                        const int32_t j = (int32_t)lower_bound(S, (int64_t)i + 1, (int64_t)D, u);
+                        if (j < D && S[j] == u) atomicOr(&row[w][j >> 6], 1ull << (j & 63));
+                    }
+                }
+                wave_sync();
+                for (int k = lane(); k < W; k += WAVE) {
+                    const unsigned long long x = row[w][k];
+                    found += (uint64_t)__popcll(x);
+                    if (R) R[(int64_t)i * W + k] = x;
+                    row[w][k] = 0ull;
+                }
+                wave_sync();
+            }
+        }
+    }
+    found = wave_sum_u64(found);
+    if (lane() == 0) {
+        if (!A.rows && found) atomicAdd(&A.stats[0], (unsigned long long)found);
+        if (streamed) atomicAdd(&A.stats[5], (unsigned long long)streamed);
+    }
+}
+
+// 4-cliques: a wave takes an item and, row by row, holds row i in
+// registers (lane l: words l and l + 64), walks its set bits j in order and
+// adds popcount(row i AND row j); row j's words below j's own are zero and
+// are not read.  Four rows j are loaded before their popcounts are taken.
+__global__ __launch_bounds__(HM_THREADS) void k_heavy_last(HmArgs A) {
+    uint64_t acc = 0, pairs = 0;
+    QueueCursor cur = queue_start();
+    int64_t it_end = 0;
+    for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
+        for (int64_t jt = it; jt < it_end; ++jt) {
+            const uint64_t item = (uint64_t)uniform64((int64_t)A.items[jt]);
+            const int64_t h = item_seg(item);
+            const int32_t r = uniform(A.hroot[h]);
+            const int32_t D = uniform((int32_t)(A.rp[r + 1] - A.rp[r]));
+            const int32_t W = (D + 63) >> 6;
+            const uint64_t* R = A.rows + uniform64((int64_t)A.hoff[h]);
+            const int32_t i0 = (int32_t)item_round(item) * HM_BLOCK;
+            const int32_t i1 = min(i0 + HM_BLOCK, D);
+            for (int32_t i = i0; i < i1; ++i) {
+                const uint64_t* ri = R + (int64_t)i * W;
+                const uint64_t a0 = lane() < W ? ri[lane()] : 0ull;
+                const uint64_t a1 = lane() + WAVE < W ? ri[lane() + WAVE] : 0ull;
+                for (int32_t wd = i >> 6; wd < W; ++wd) {
+                    uint64_t bits = wd < WAVE ? readlane64(a0, wd) : readlane64(a1, wd - WAVE);
+                    while (bits) {
+                        int32_t js[4];
+                        int nj = 0;
+                        while (bits && nj < 4) {
+                            js[nj++] = wd * 64 + __builtin_ctzll(bits);
+                            bits &= bits - 1;
+                        }
+                        uint64_t b0[4], b1[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const bool on = q < nj;
+                            const uint64_t* rj = R + (int64_t)(on ? js[q] : i) * W;
+                            const int32_t low = on ? (js[q] >> 6) : W;   // words below are zero
+                            b0[q] = (lane() >= low && lane() < W) ? rj[lane()] : 0ull;
+                            b1[q] = (lane() + WAVE >= low && lane() + WAVE < W) ? rj[lane() + WAVE] : 0ull;
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc += (uint64_t)(__popcll(a0 & b0[q]) + __popcll(a1 & b1[q]));
+                        pairs += (uint64_t)nj;
+                    }
+                }
+            }
+        }
+    }
+    acc = wave_sum_u64(acc);
+    if (lane() == 0) {
+        if (acc) atomicAdd(&A.stats[0], (unsigned long long)acc);
+        if (pairs) atomicAdd(&A.stats[6], (unsigned long long)pairs);
+    }
+}
+
 static unsigned grid_threads(int64_t items) {
     int64_t b = (items + 255) / 256;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)device_info().n_cu * 32));
@@ -1269,7 +1436,7 @@ static void build_mask_plan(pg_graph* g) {
     // (round_items' bound), and the scans' tile sums
     const int64_t cap = E / WAVE + n + 1;
     Arena ar;
-    ar.buf.reserve(sizeof(uint64_t) * (size_t)(6 * (n + 1) + cap + 16 * ((n + 2047) / 2048)) + (size_t(1) << 20));
+    ar.buf.reserve(sizeof(uint64_t) * (size_t)(9 * (n + 1) + cap + 16 * ((n + 2047) / 2048)) + (size_t(1) << 20));
     P.moff.reserve(sizeof(uint64_t) * (n + 1));
     uint64_t* moff = P.moff.as<uint64_t>();
     uint64_t* lseg = push<uint64_t>(ar, n + 1);
@@ -1310,12 +1477,72 @@ static void build_mask_plan(pg_graph* g) {
     P.item.reserve(sizeof(uint64_t) * std::max<int64_t>(m, 1));
     if (m > 0)
         PG_HIP(hipMemcpyAsync(P.item.as<uint64_t>(), items, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
+    // heavy roots for the wide rows: their list, row-word offsets and items
+    // of HM_BLOCK rows
+    P.n_heavy = P.hwords = P.hitems = 0;
+    if (e_heavy > 0) {
+        uint32_t* flag = push<uint32_t>(ar, n);
+        uint64_t* pos = push<uint64_t>(ar, n + 1);
+        k_heavy_flags<<<grid_threads(n), 256, 0, s>>>(n, rp, flag);
+        PG_HIP(hipGetLastError());
+        scan_u32(flag, n, pos, ar, s);
+        const int64_t nh = (int64_t)read_u64(pos + n, s);
+        P.hroot.reserve(sizeof(int32_t) * std::max<int64_t>(nh, 1));
+        P.hoff.reserve(sizeof(uint64_t) * (nh + 1));
+        uint32_t* hdeg = push<uint32_t>(ar, std::max<int64_t>(nh, 1));
+        uint64_t* hw = push<uint64_t>(ar, std::max<int64_t>(nh, 1));
+        uint64_t* hseg = push<uint64_t>(ar, nh + 1);
+        k_heavy_fill<<<grid_threads(n), 256, 0, s>>>(n, rp, pos, P.hroot.as<int32_t>(), hdeg, hw);
+        PG_HIP(hipGetLastError());
+        scan_u32(hdeg, nh, hseg, ar, s);
+        scan_u64(hw, nh, P.hoff.as<uint64_t>(), ar, s);
+        uint64_t* hitems = nullptr;
+        const int64_t mh = round_items(hseg, 0, nh, HM_BLOCK, ar, s, &hitems);
+        P.hitem.reserve(sizeof(uint64_t) * std::max<int64_t>(mh, 1));
+        if (mh > 0)
+            PG_HIP(hipMemcpyAsync(P.hitem.as<uint64_t>(), hitems, sizeof(uint64_t) * mh, hipMemcpyDeviceToDevice, s));
+        P.n_heavy = nh;
+        P.hitems = mh;
+        P.hwords = (int64_t)read_u64(P.hoff.as<uint64_t>() + nh, s);
+    }
     PG_HIP(hipStreamSynchronize(s));
     P.words = words;
     P.windows = nw;
     P.items = m;
     P.heavy_edges = e_heavy;
     P.built = true;
+}
+
+// Triangles (k = 3) or 4-cliques (k = 4) at the heavy roots through wide
+// rows; the count goes to stats[0].
+static void heavy_masks(CliqueRun& R, const MaskPlan& P) {
+    pg_graph* g = R.g;
+    hipStream_t s = R.s;
+    Arena& ar = g->arena;
+    HmArgs A{};
+    A.items = P.hitem.as<uint64_t>();
+    A.hroot = P.hroot.as<int32_t>();
+    A.hoff = P.hoff.as<uint64_t>();
+    A.rp = g->dag.rp.as<int64_t>();
+    A.col = g->dag.col.as<int32_t>();
+    A.stats = R.stats;
+    A.rows = R.k == 4 ? push<uint64_t>(ar, (size_t)std::max<int64_t>(P.hwords, 1)) : nullptr;
+    A.Q.n_items = P.hitems;
+    A.Q.chunk = 1;
+    if (P.hitems == 0) return;
+    fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, s);
+    A.Q.next = R.qctr;
+    {
+        ProfScope ps("clique_heavy_rows", s, (double)P.n_heavy);
+        k_heavy_rows<<<(unsigned)(4 * device_info().n_cu), HM_THREADS, 0, s>>>(A);
+        PG_HIP(hipGetLastError());
+    }
+    if (R.k == 4) {
+        fill_u64(reinterpret_cast<uint64_t*>(R.qctr), Q_WORDS, 0, s);
+        ProfScope ps("clique_heavy_last", s, (double)P.n_heavy);
+        k_heavy_last<<<(unsigned)(8 * device_info().n_cu), HM_THREADS, 0, s>>>(A);
+        PG_HIP(hipGetLastError());
+    }
 }
 
 // Returns the number of level-2 entries: the triangles, which are the
@@ -1463,8 +1690,15 @@ uint64_t count_cliques(pg_graph* g, int k) {
         const MaskPlan& P = g->dag.plan;
         if (P.heavy_edges > 0) {
             const size_t mk = ar.mark();
-            extend_level(R, 1, reinterpret_cast<const int64_t*>(P.hrp.as<uint64_t>()), 0, 0, g->n,
-                         P.hcol.as<int32_t>(), 0, P.heavy_edges);
+            // k = 3, 4: wide rows in device memory when every heavy root
+            // fits them and they fit the budget; otherwise the general kernels
+            const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
+            if (k <= 4 && g->dag.max_out <= HM_MAXD && (k == 3 || (uint64_t)P.hwords * 8 <= room / 2)) {
+                heavy_masks(R, P);
+            } else {
+                extend_level(R, 1, reinterpret_cast<const int64_t*>(P.hrp.as<uint64_t>()), 0, 0, g->n,
+                             P.hcol.as<int32_t>(), 0, P.heavy_edges);
+            }
             ar.reset(mk);
         }
         n2 = count_cliques4_masks(g, R);

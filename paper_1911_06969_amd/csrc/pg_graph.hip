@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, int64_t nnz, const 
                                                   const int32_t* __restrict__ col,
                                                   const int32_t* __restrict__ labels, int32_t n_labels,
                                                   unsigned* __restrict__ flags,
-                                                  unsigned long long* __restrict__ max_deg) {
+                                                  unsigned long long* __restrict__ max_deg, bool bounds_only) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
     unsigned bad = 0;
     uint64_t dmax = 0;
@@ -45,6 +45,7 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, int64_t nnz, const 
                 bad |= BAD_RANGE;
                 continue;
             }
+            if (bounds_only) continue;
             if (u == v) bad |= BAD_LOOP;
             if (j > r0 && col[j - 1] >= u) bad |= BAD_ORDER;
             const int64_t q0 = rp[u], q1 = rp[u + 1];
@@ -55,6 +56,109 @@ __global__ __launch_bounds__(256) void k_validate(int64_t n, int64_t nnz, const 
     }
     if (bad) atomicOr(flags, bad);
     if (dmax) atomicMax(max_deg, (unsigned long long)dmax);
+}
+
+static int bits_for(uint64_t x) {
+    int b = 0;
+    while (b < 64 && (x >> b) != 0) ++b;
+    return b;
+}
+
+static unsigned grid_for(int64_t items, int per_block) {
+    int64_t b = (items + per_block - 1) / per_block;
+    b = std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)device_info().n_cu * 32));
+    return (unsigned)b;
+}
+
+// ------------------------------------------------------- canonical CSR
+//
+// PG_CANONICALIZE: the rows are rebuilt as the sorted, duplicate-free,
+// loop-free neighbour lists of the symmetric closure: every entry (v, u)
+// with u != v gives the keys (v, u) and (u, v); the keys are sorted and
+// repeated ones dropped.  Row bounds and vertex ids must be valid already.
+
+constexpr uint64_t NO_EDGE = ~0ull;
+
+__global__ void k_canon_keys(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                             uint64_t* __restrict__ keys) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t v = blockIdx.x * (int64_t)(blockDim.x / WAVE) + threadIdx.x / WAVE; v < n; v += waves)
+        for (int64_t j = rp[v] + lane(); j < rp[v + 1]; j += WAVE) {
+            const uint64_t u = (uint32_t)col[j];
+            const bool loop = u == (uint64_t)v;
+            keys[2 * j] = loop ? NO_EDGE : ((uint64_t)v << 32) | u;
+            keys[2 * j + 1] = loop ? NO_EDGE : (u << 32) | (uint64_t)v;
+        }
+}
+
+__global__ void k_canon_keep(int64_t m, const uint64_t* __restrict__ keys, uint32_t* __restrict__ keep) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        keep[i] = (keys[i] != NO_EDGE && (i == 0 || keys[i - 1] != keys[i])) ? 1u : 0u;
+}
+
+__global__ void k_canon_write(int64_t m, const uint64_t* __restrict__ keys, const uint32_t* __restrict__ keep,
+                              const uint64_t* __restrict__ pos, int32_t* __restrict__ col,
+                              uint32_t* __restrict__ deg) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        if (keep[i]) {
+            col[pos[i]] = (int32_t)(uint32_t)keys[i];
+            atomicAdd(&deg[keys[i] >> 32], 1u);
+        }
+}
+
+static void canonicalize(pg_graph* g) {
+    hipStream_t s = g->stream;
+    const int64_t n = g->n, nnz = g->nnz;
+    DevBuf scratch;
+    scratch.reserve(256);
+    unsigned* dflags = scratch.as<unsigned>();
+    unsigned long long* dmax = reinterpret_cast<unsigned long long*>(scratch.as<char>() + 64);
+    fill_u32(dflags, 1, 0, s);
+    fill_u64(reinterpret_cast<uint64_t*>(dmax), 1, 0, s);
+    if (n > 0) {
+        const int64_t blocks = std::min<int64_t>((n + 3) / 4, (int64_t)device_info().n_cu * 16);
+        k_validate<<<(unsigned)blocks, 256, 0, s>>>(n, nnz, g->rp.as<int64_t>(), g->col.as<int32_t>(), nullptr, 0,
+                                                    dflags, dmax, true);
+        PG_HIP(hipGetLastError());
+    }
+    unsigned hf = 0;
+    PG_HIP(hipMemcpyAsync(&hf, dflags, sizeof(hf), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    if (n == 0 && nnz != 0) hf |= BAD_ROWPTR;
+    PG_REQUIRE(hf == 0, PG_EINVAL,
+               std::string("invalid CSR (canonicalising needs valid row bounds and vertex ids):") +
+                   ((hf & BAD_ROWPTR) ? " row_ptr not monotone or not ending at nnz;" : "") +
+                   ((hf & BAD_RANGE) ? " neighbour id out of range;" : ""));
+    if (nnz == 0) return;
+    const int64_t m = 2 * nnz;
+    DevBuf keys, tmp, keep, pos, deg;
+    keys.reserve(sizeof(uint64_t) * m);
+    tmp.reserve(sizeof(uint64_t) * m);
+    keep.reserve(sizeof(uint32_t) * m);
+    pos.reserve(sizeof(uint64_t) * (m + 1));
+    deg.reserve(sizeof(uint32_t) * std::max<int64_t>(n, 1));
+    Arena ar;
+    ar.buf.reserve(sizeof(uint64_t) * (size_t)(256 * ((m + 2047) / 2048) * 3 + (1 << 20)));
+    k_canon_keys<<<grid_for(n, 4), 256, 0, s>>>(n, g->rp.as<int64_t>(), g->col.as<int32_t>(), keys.as<uint64_t>());
+    PG_HIP(hipGetLastError());
+    const int nb = std::max(1, bits_for((uint64_t)(n - 1)));
+    radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), m, 0, nb, ar, s);
+    radix_sort_u64(keys.as<uint64_t>(), tmp.as<uint64_t>(), m, 32, 32 + nb, ar, s);
+    k_canon_keep<<<grid_for(m, 256), 256, 0, s>>>(m, keys.as<uint64_t>(), keep.as<uint32_t>());
+    PG_HIP(hipGetLastError());
+    scan_u32(keep.as<uint32_t>(), m, pos.as<uint64_t>(), ar, s);
+    const int64_t nnz2 = (int64_t)read_u64(pos.as<uint64_t>() + m, s);
+    fill_u32(deg.as<uint32_t>(), n, 0, s);
+    DevBuf col2;
+    col2.reserve(sizeof(int32_t) * std::max<int64_t>(nnz2, 1));
+    k_canon_write<<<grid_for(m, 256), 256, 0, s>>>(m, keys.as<uint64_t>(), keep.as<uint32_t>(), pos.as<uint64_t>(),
+                                                   col2.as<int32_t>(), deg.as<uint32_t>());
+    PG_HIP(hipGetLastError());
+    scan_u32(deg.as<uint32_t>(), n, g->rp.as<uint64_t>(), ar, s);
+    PG_HIP(hipStreamSynchronize(s));
+    std::swap(g->col.p, col2.p);
+    std::swap(g->col.bytes, col2.bytes);
+    g->nnz = nnz2;
 }
 
 void graph_load(pg_graph* g, int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
@@ -77,6 +181,10 @@ void graph_load(pg_graph* g, int64_t n, int64_t nnz, const int64_t* rp, const in
         g->labels.reserve(sizeof(int32_t) * std::max<int64_t>(n, 1));
         if (n) PG_HIP(hipMemcpyAsync(g->labels.p, labels, sizeof(int32_t) * n, kind, s));
     }
+    if (flags & PG_CANONICALIZE) {
+        canonicalize(g);
+        nnz = g->nnz;
+    }
     DevBuf scratch;
     scratch.reserve(256);
     unsigned* dflags = scratch.as<unsigned>();
@@ -87,7 +195,7 @@ void graph_load(pg_graph* g, int64_t n, int64_t nnz, const int64_t* rp, const in
         ProfScope ps("validate", s, (double)nnz);
         k_validate<<<(unsigned)blocks, 256, 0, s>>>(n, nnz, g->rp.as<int64_t>(), g->col.as<int32_t>(),
                                                     labels ? g->labels.as<int32_t>() : nullptr, n_labels,
-                                                    dflags, dmax);
+                                                    dflags, dmax, false);
         PG_HIP(hipGetLastError());
     }
     unsigned hf = 0;
@@ -174,18 +282,6 @@ __global__ void k_split_low(int64_t m, const uint64_t* __restrict__ keys, int32_
         low[i] = (int32_t)(uint32_t)keys[i];
         high[i] = (int32_t)(uint32_t)(keys[i] >> 32);
     }
-}
-
-static int bits_for(uint64_t x) {
-    int b = 0;
-    while (b < 64 && (x >> b) != 0) ++b;
-    return b;
-}
-
-static unsigned grid_for(int64_t items, int per_block) {
-    int64_t b = (items + per_block - 1) / per_block;
-    b = std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)device_info().n_cu * 32));
-    return (unsigned)b;
 }
 
 void build_dag(pg_graph* g) {

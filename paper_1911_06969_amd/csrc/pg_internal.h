@@ -123,6 +123,13 @@ struct MaskPlan {
     DevBuf wfirst;           // int64[windows+1]: first root of each window; wfirst[windows] = n
     DevBuf hrp;              // uint64[n+1]: heavy roots' out-lists in hcol (empty for light roots)
     DevBuf hcol;             // int32[heavy_edges]
+    // heavy roots through wide rows in device memory (k <= 4)
+    int64_t n_heavy = 0;     // heavy roots
+    int64_t hwords = 0;      // their row words in all
+    int64_t hitems = 0;      // work items (heavy root, block of rows)
+    DevBuf hroot;            // int32[n_heavy]: the heavy roots (DAG ranks), ascending
+    DevBuf hoff;             // uint64[n_heavy+1]: first row word of each
+    DevBuf hitem;            // uint64[hitems]
 };
 
 struct Dag {

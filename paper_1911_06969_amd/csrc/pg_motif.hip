@@ -616,8 +616,9 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
 // many of the elements before j are adjacent to v0 (cum), which gives the
 // common neighbours of v0 and v1 up to any child v2 with one lookup.
 //
-// Each wave takes 64 children, one per lane: the lane finds where v2's list
-// passes v0 and the ranks of v2 in the lists of v0 and v1.  Children with
+// Each wave takes 64 children, one per lane: the lane finds the ranks of
+// v2 in the lists of v0 and v1 (in v0's list by position for the children
+// that are A0's elements above v1).  Children with
 // fewer than 64 candidates are streamed by their own lane (four loads in
 // flight); longer ones by the whole wave, 256 candidates per step, counted
 // with ballots.  The counts per adjacency mask and range then go through
@@ -626,6 +627,7 @@ constexpr int MM_THREADS = 512;
 constexpr int MM_WAVES = MM_THREADS / WAVE;
 constexpr int MM_CHILDREN = MM_WAVES * WAVE;   // children per item
 constexpr int64_t MM_HEAVY = 256;              // entries with at least this many children use the map
+constexpr int MM_G = 8;                        // 64-candidate chunks loaded at once by a wave
 
 __device__ __forceinline__ uint32_t map_bits(const uint32_t* map, int32_t u) {
     return (map[(uint32_t)u >> 4] >> (((uint32_t)u & 15u) << 1)) & 3u;
@@ -633,13 +635,13 @@ __device__ __forceinline__ uint32_t map_bits(const uint32_t* map, int32_t u) {
 
 // Adds this entry's (r = 0: candidates u <= v2, r = 1: above v2) counts to
 // the pattern counters.  k: [0, 1] u ~ v0 and v2, [2, 3] u ~ v1 and v2,
-// [4, 5] all three, [6] |A2' up to v2|; I*: list sizes per range.
-__device__ __forceinline__ void motif4_classify(uint64_t (&acc)[6], const uint32_t (&k)[7], int32_t len2,
+// [4, 5] all three, [6, 7] v2's list per range; I*: list sizes per range.
+__device__ __forceinline__ void motif4_classify(uint64_t (&acc)[6], const uint32_t (&k)[8],
                                                 const int32_t (&I0)[2], const int32_t (&I1)[2],
                                                 const int32_t (&I01)[2], int32_t v1, int32_t v2, int code) {
     const int a02 = code & 1, a12 = (code >> 1) & 1;
     const int p = a02 ? 0 : 1;
-    const int32_t I2[2] = {(int32_t)k[6], len2 - (int32_t)k[6]};
+    const int32_t I2[2] = {(int32_t)k[6], (int32_t)k[7]};
     int32_t N[2][8];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -684,7 +686,7 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
     // the marked lists: A0' = col[m0b, m0e), A1' = col[m1b, m1e)
     int32_t mv0 = -1, mv1 = -1;
     int64_t m0b = 0, m0e = 0, m1b = 0, m1e = 0;
-    int32_t nc = 0;
+    int32_t nc = 0, mna = 0;   // |A0' ∩ A1'|; |A0 above v1| (the first children, in A0's order)
     uint64_t acc[6] = {0, 0, 0, 0, 0, 0};
     uint64_t streamed = 0, n_in = 0, marked = 0;
     QueueCursor cur = queue_start();
@@ -771,6 +773,7 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                 m1b = a1b;
                 m1e = q1;
                 nc = (int32_t)total;
+                mna = (int32_t)(r1 - uniform64(upper_bound(col, a0b, r1, v1)));
             }
             // this wave's children [xw, xe)
             const int32_t xw = xa + w * WAVE;
@@ -787,7 +790,8 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                 const int64_t s0 = A.rp[v2];
                 s1 = A.rp[v2 + 1];
                 lo2 = upper_bound(col, s0, s1, v0);
-                const int64_t u0 = upper_bound(col, m0b, m0e, v2);
+                // the first mna children are A0's elements above v1, in order
+                const int64_t u0 = x < mna ? m0e - mna + x + 1 : upper_bound(col, m0b, m0e, v2);
                 const int64_t u1 = upper_bound(col, m1b, m1e, v2);
                 I0[0] = (int32_t)(u0 - m0b);
                 I0[1] = (int32_t)(m0e - u0);
@@ -796,8 +800,9 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                 I01[0] = cum[u1 - m1b];
                 I01[1] = nc - I01[0];
             }
+            // candidates: v2's list above v0
             const int32_t len = (int32_t)(s1 - lo2);
-            uint32_t k[7] = {0, 0, 0, 0, 0, 0, 0};
+            uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             // short children: the lane streams its own list, four loads at a time
             {
                 const bool mine = valid && len < WAVE;
@@ -820,51 +825,72 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                         k[4] += b0 & b1 & lo;
                         k[5] += b0 & b1 & hi;
                         k[6] += lo;
+                        k[7] += hi;
                     }
                     t += 4;
                 }
             }
-            // long children: the whole wave streams each list, 256 candidates per step
+            // long children: the wave streams their lists as one sequence of
+            // 64-candidate chunks, MM_G chunks (of one or several children)
+            // loaded before any is counted; each chunk's counts go to the
+            // lane of its child
             uint64_t longm = ballot(valid && len >= WAVE);
-            while (longm) {
-                const int xi = __builtin_ctzll(longm);
-                longm &= longm - 1;
-                const int32_t cv2 = readlane(v2, xi);
-                const int64_t l = (int64_t)readlane64((uint64_t)lo2, xi);
-                const int64_t h = (int64_t)readlane64((uint64_t)s1, xi);
-                uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
-                for (int64_t t0 = l; t0 < h; t0 += 4 * WAVE) {
-                    int32_t u[4];
+            int cxi = -1;
+            int64_t ct = 0, ch = 0;   // the current child's next chunk and end (wave-uniform)
+            auto next_child = [&]() {
+                cxi = -1;
+                if (longm) {
+                    cxi = __builtin_ctzll(longm);
+                    longm &= longm - 1;
+                    ct = (int64_t)readlane64((uint64_t)lo2, cxi);
+                    ch = (int64_t)readlane64((uint64_t)s1, cxi);
+                }
+            };
+            next_child();
+            while (cxi >= 0) {
+                int qx[MM_G];
+                int64_t qt[MM_G], qh[MM_G];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int64_t t = t0 + q * WAVE + lane();
-                        u[q] = col[t < h ? t : l];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const bool vq = t0 + q * WAVE + lane() < h;
-                        const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
-                        const uint64_t L = ballot(vq && u[q] <= cv2);
-                        const uint64_t B0 = ballot(bits & 1u), B1 = ballot(bits & 2u);
-                        const uint64_t B01 = B0 & B1;
-                        c[0] += (uint32_t)popc64(B0 & L);
-                        c[1] += (uint32_t)popc64(B0 & ~L);
-                        c[2] += (uint32_t)popc64(B1 & L);
-                        c[3] += (uint32_t)popc64(B1 & ~L);
-                        c[4] += (uint32_t)popc64(B01 & L);
-                        c[5] += (uint32_t)popc64(B01 & ~L);
-                        c[6] += (uint32_t)popc64(L);
+                for (int q = 0; q < MM_G; ++q) {
+                    qx[q] = cxi < 0 ? 0 : cxi;
+                    qt[q] = cxi < 0 ? 0 : ct;
+                    qh[q] = cxi < 0 ? 0 : ch;
+                    if (cxi >= 0) {
+                        ct += WAVE;
+                        if (ct >= ch) next_child();
                     }
                 }
-                if (lane() == xi) {
+                int32_t u[MM_G];
 #pragma unroll
-                    for (int q = 0; q < 7; ++q) k[q] = c[q];
+                for (int q = 0; q < MM_G; ++q) {
+                    const int64_t t = qt[q] + lane();
+                    u[q] = col[t < qh[q] ? t : 0];
+                }
+#pragma unroll
+                for (int q = 0; q < MM_G; ++q) {
+                    if (qt[q] >= qh[q]) continue;   // an unused slot of the last group
+                    const bool vq = qt[q] + lane() < qh[q];
+                    const int32_t cv2 = readlane(v2, qx[q]);
+                    const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
+                    const uint64_t Lo = ballot(vq && u[q] <= cv2);
+                    const uint64_t Hi = ballot(vq && u[q] > cv2);
+                    const uint64_t B0 = ballot(bits & 1u), B1 = ballot(bits & 2u);
+                    const uint64_t B01 = B0 & B1;
+                    const bool me = lane() == qx[q];
+                    k[0] += me ? (uint32_t)popc64(B0 & Lo) : 0u;
+                    k[1] += me ? (uint32_t)popc64(B0 & Hi) : 0u;
+                    k[2] += me ? (uint32_t)popc64(B1 & Lo) : 0u;
+                    k[3] += me ? (uint32_t)popc64(B1 & Hi) : 0u;
+                    k[4] += me ? (uint32_t)popc64(B01 & Lo) : 0u;
+                    k[5] += me ? (uint32_t)popc64(B01 & Hi) : 0u;
+                    k[6] += me ? (uint32_t)popc64(Lo) : 0u;
+                    k[7] += me ? (uint32_t)popc64(Hi) : 0u;
                 }
             }
             if (valid) {
                 streamed += (uint64_t)len;
                 n_in += 1;
-                motif4_classify(acc, k, len, I0, I1, I01, v1, v2, code);
+                motif4_classify(acc, k, I0, I1, I01, v1, v2, code);
             }
         }
     }

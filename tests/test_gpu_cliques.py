@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import brute
+from oracle import brute, closed_form
 from paper_1911_06969_amd import binding, synth
 from tests.gpu_common import golden, gpu_or_skip, say
 
@@ -42,9 +42,10 @@ def test_complete_graphs(torch):
 def test_mask_row_width_limit(torch):
     """K_769: the lowest-ranked vertex has DAG out-degree 768, the most the
     sibling masks take (12-word rows, the deepest search of the count pass);
-    in K_770 that vertex (out-degree 769) is a heavy root, counted by the
-    general kernels, and the rest by the masks.  K_130 takes 3-word rows
-    through the deeper mask levels.  Every count against C(n, k)."""
+    in K_770 that vertex (out-degree 769) is a heavy root, counted through
+    wide rows in device memory, and the rest by the masks.  K_130 takes
+    3-word rows through the deeper mask levels.  Every count against
+    C(n, k)."""
     for n, ks in ((769, (3, 4)), (770, (3, 4)), (130, (3, 4, 5, 6))):
         say("K", n)
         assert gpu_cliques(synth.complete(n), ks) == [comb(n, k) for k in ks]
@@ -52,14 +53,61 @@ def test_mask_row_width_limit(torch):
 
 def test_heavy_and_light_roots(torch):
     """K_780 beside an R-MAT graph: the 12 lowest-ranked vertices of K_780
-    have DAG out-degrees 779 .. 768, so 11 roots are heavy (general
-    kernels) and all others light (sibling masks); the counts add up."""
+    have DAG out-degrees 779 .. 768, so 11 roots are heavy (wide rows) and
+    all others light (sibling masks); the counts add up."""
     k_part = synth.complete(780)
     r_part = synth.rmat(11, 16, seed=8)
     g = synth.disjoint_union(k_part, r_part)
     ks = (3, 4)
     want = [comb(780, k) + oracle.clique_count(r_part, k) for k in ks]
     assert gpu_cliques(g, ks) == want
+
+
+def test_wide_rows_for_heavy_roots(torch):
+    """Heavy roots of out-degree up to 2099 (rows of up to 33 words, both
+    register halves of a lane) beside an R-MAT graph: triangles and
+    4-cliques through the wide rows equal C(n, k) plus the oracle's count;
+    on a smaller pair the general kernels alone agree."""
+    parts = [synth.complete(1300), synth.complete(2100), synth.rmat(12, 16, seed=9)]
+    g = synth.disjoint_union(*parts)
+    ks = (3, 4)
+    want = [comb(1300, k) + comb(2100, k) + oracle.clique_count(parts[2], k) for k in ks]
+    say("wide rows", want)
+    assert gpu_cliques(g, ks) == want
+    small = synth.disjoint_union(synth.complete(900), synth.rmat(10, 8, seed=9))
+    with binding.Graph.from_csr(small) as G:
+        masks = [G.cliques(k) for k in ks]
+        G.set_option(binding.PG_OPT_CLIQUE_MASKS, 0)
+        assert [G.cliques(k) for k in ks] == masks
+
+
+def test_wide_rows_under_a_small_budget(torch):
+    """When the heavy roots' rows do not fit half the budget, they take the
+    general kernels: same counts."""
+    g = synth.disjoint_union(synth.complete(900), synth.rmat(10, 8, seed=10))
+    want = [comb(900, k) + oracle.clique_count(synth.rmat(10, 8, seed=10), k) for k in (3, 4)]
+    with binding.Graph.from_csr(g) as G:
+        G.set_memory_budget(1 << 20)
+        assert [G.cliques(k) for k in (3, 4)] == want
+
+
+@pytest.mark.slow
+def test_rmat_weak_scaling_sweep(torch):
+    """The weak-scaling graphs (R-MAT, edge factor 10, seed 7, 2^20 .. 2^25
+    vertices): triangles at every scale and 4-cliques up to scale 23,
+    against the oracle's counts."""
+    gold = golden("full_configs.json")
+    for sc in range(20, 26):
+        want = gold[f"rmat_sweep_s{sc}"]
+        g = synth.rmat(sc, 10, seed=7)
+        assert (g.n, g.n_edges) == (want["n"], want["edges"])
+        with binding.Graph.from_csr(g) as G:
+            for k in (3, 4):
+                if f"k{k}" in want:
+                    got = G.cliques(k)
+                    say(f"sweep scale {sc} k={k}: {got}")
+                    assert got == want[f"k{k}"], (sc, k)
+        del g
 
 
 def test_empty_and_edge_cases(torch):
@@ -252,3 +300,52 @@ def test_every_graph_on_five_vertices(torch):
                 assert total == len(rows)
                 assert _row_sets(rows) == brute.clique_list(g, k)
 
+
+
+def _messy(g, rng):
+    """The same edges as a CSR with one direction of some edges missing,
+    duplicated entries, self-loops and unsorted rows."""
+    rows = []
+    for v in range(g.n):
+        nb = [int(u) for u in g.col[g.row_ptr[v]:g.row_ptr[v + 1]] if u > v or rng.random() < 0.5]
+        nb += [int(u) for u in rng.choice(nb, size=min(len(nb), 2))] if nb else []
+        if rng.random() < 0.2:
+            nb.append(v)
+        rng.shuffle(nb)
+        rows.append(nb)
+    rp = np.zeros(g.n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.array([u for r in rows for u in r], np.int32)
+    return rp, col
+
+
+def test_canonicalize_rebuilds_the_csr(torch):
+    """PG_CANONICALIZE: an unsorted, partly one-directional CSR with
+    duplicates and loops loads as the canonical CSR of its symmetric closure
+    (entry count as the definition gives it), and mines like it."""
+    rng = np.random.default_rng(31)
+    g = synth.rmat(10, 8, seed=31)
+    rp, col = _messy(g, rng)
+    with pytest.raises(binding.PgError) as e:
+        binding.Graph(rp, col)
+    assert e.value.code == binding.PG_EINVAL
+    # the symmetric closure of the entries, without loops, by definition
+    pairs = {(min(v, int(u)), max(v, int(u))) for v in range(g.n) for u in col[rp[v]:rp[v + 1]] if int(u) != v}
+    with binding.Graph(rp, col, canonicalize=True) as G:
+        n, nnz, dmax = G.info()
+        assert (n, nnz) == (g.n, 2 * len(pairs))
+        assert nnz == g.col.shape[0] and dmax == int(np.diff(g.row_ptr).max())
+        assert [G.cliques(k) for k in (3, 4)] == [oracle.clique_count(g, k) for k in (3, 4)]
+        assert [int(x) for x in G.motifs(4)] == [int(x) for x in closed_form.motif4(g)]
+    # a clean CSR is unchanged by it; ids or row bounds out of range still fail
+    with binding.Graph.from_csr(g, canonicalize=True) as G:
+        assert G.info()[1] == g.col.shape[0]
+        assert G.cliques(3) == oracle.clique_count(g, 3)
+    bad = col.copy()
+    bad[0] = g.n
+    with pytest.raises(binding.PgError) as e:
+        binding.Graph(rp, bad, canonicalize=True)
+    assert e.value.code == binding.PG_EINVAL
+    with pytest.raises(binding.PgError) as e:
+        binding.Graph(np.array([0, 5, 3], np.int64), np.zeros(5, np.int32), canonicalize=True)
+    assert e.value.code == binding.PG_EINVAL

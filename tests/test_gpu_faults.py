@@ -63,3 +63,20 @@ def test_allocator_hook_refusals_leak_nothing(torch):
     finally:
         left[0] = None
         assert lib.pg_set_allocator(None, None, None) == binding.PG_OK
+
+
+def test_default_allocator_is_torch(torch):
+    """The binding routes device memory through torch's caching allocator:
+    a loaded graph and its first mining call grow torch's allocated bytes,
+    and closing the graph gives them back."""
+    binding.load_library()
+    assert binding.use_torch_allocator()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    g = synth.rmat(11, 8, seed=13)
+    with binding.Graph.from_csr(g) as G:
+        assert G.cliques(4) == oracle.clique_count(g, 4)
+        during = torch.cuda.memory_allocated()
+    torch.cuda.synchronize()
+    assert during > before + 4 * g.col.shape[0]
+    assert torch.cuda.memory_allocated() == before
