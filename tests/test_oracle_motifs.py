@@ -113,6 +113,18 @@ def test_esu_closed_form_rmat():
         assert np.array_equal(e, c)
 
 
+def test_esu_closed_form_rmat_scale14():
+    """ESU = closed form on R-MAT graphs of 2^14 vertices: 3-motifs at edge
+    factor 2, 4-motifs at edge factor 1 (hubs of degree ~560), class by
+    class."""
+    g = synth.rmat(14, 2, seed=23)
+    assert np.array_equal(oracle.motif_esu(g, 3), closed_form.motif3(g))
+    g = synth.rmat(14, 1, seed=24)
+    e = oracle.motif_esu(g, 4)
+    assert e.sum() > 10 ** 7
+    assert np.array_equal(e, closed_form.motif4(g))
+
+
 def test_relabel_invariance():
     g = synth.rmat(8, 8, seed=22)
     h = synth.relabel(g, np.random.default_rng(5).permutation(g.n))
