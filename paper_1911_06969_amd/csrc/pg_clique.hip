@@ -551,7 +551,6 @@ struct BmArgs {
 // Every step issues its loads (after the final step they repeat its first
 // element), so the number of loads in flight is known at compile time and
 // the search waits for its own step's data only.
-constexpr int BUF_WORD3 = 0x00020000;    // raw 32-bit buffer access, gfx9 family
 
 template <int LG>
 __device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left, const int32_t* S, int32_t x,

@@ -152,6 +152,10 @@ __device__ __forceinline__ bool member_u(P a, int32_t n, int32_t key) {
     }
 }
 
+// Word 3 of a buffer resource for raw 32-bit loads (gfx9 family): with a
+// record count in bytes, lanes past it read 0.
+constexpr int BUF_WORD3 = 0x00020000;
+
 // ---------------------------------------------------------- work queues
 //
 // Items [0, n_items) are split into Q_PARTS contiguous ranges, one per die,

@@ -611,7 +611,10 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
 // bits per vertex (bit 0: u ~ v0, bit 1: u ~ v1), so testing a candidate u
 // of a child's list against both lists is one LDS read.  The marks stay
 // while consecutive items share v0 (only v1's are redone) or the whole entry
-// (a long entry is cut into items of MM_CHILDREN children).  Per entry the
+// (a long entry is cut into items of MM_CHILDREN children).  The waves take
+// an item's children 64 at a time from a counter in LDS, so a wave that
+// drew children with long lists does not hold the others at the next
+// entry's barrier for more than one such group.  Per entry the
 // workgroup also records, for every position j of v1's list above v0, how
 // many of the elements before j are adjacent to v0 (cum), which gives the
 // common neighbours of v0 and v1 up to any child v2 with one lookup.
@@ -625,7 +628,7 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_last4(MotifArgs A) {
 // the same canonical rule and pattern table as in k_motif_last4.
 constexpr int MM_THREADS = 512;
 constexpr int MM_WAVES = MM_THREADS / WAVE;
-constexpr int MM_CHILDREN = MM_WAVES * WAVE;   // children per item
+constexpr int MM_CHILDREN = 4096;              // children per item, taken by the waves 64 at a time
 constexpr int64_t MM_HEAVY = 256;              // entries with at least this many children use the map
 constexpr int MM_G = 8;                        // 64-candidate chunks loaded at once by a wave
 
@@ -679,6 +682,7 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
     __shared__ uint32_t map[WORDS];
     __shared__ int64_t s_next[2];
     __shared__ uint32_t s_tot[MM_WAVES];
+    __shared__ int32_t s_grab;
     const int w = threadIdx.x / WAVE;
     int32_t* cum = cum_all + (int64_t)blockIdx.x * cum_stride;
     const int32_t* __restrict__ col = A.col;
@@ -711,12 +715,13 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
             const int32_t s = uniform((int32_t)(A.seg2[p + 1] - A.seg2[p]));
             if (xa >= s) continue;
             const int32_t v0 = uniform(A.l1_src[p]), v1 = uniform(A.l1_dst[p]);
+            __syncthreads();   // every wave is done with the previous item's children
+            if (threadIdx.x == 0) s_grab = 0;
             if (v0 != mv0 || v1 != mv1) {
                 const int64_t r0 = uniform64(A.rp[v0]), r1 = uniform64(A.rp[v0 + 1]);
                 const int64_t q0 = uniform64(A.rp[v1]), q1 = uniform64(A.rp[v1 + 1]);
                 const int64_t a0b = uniform64(upper_bound(col, r0, r1, v0));
                 const int64_t a1b = uniform64(upper_bound(col, q0, q1, v0));
-                __syncthreads();   // the previous entry's children are counted
                 if (v0 != mv0) {
                     for (int64_t t = m0b + threadIdx.x; t < m0e; t += MM_THREADS) map[(uint32_t)col[t] >> 4] = 0u;
                     for (int64_t t = m1b + threadIdx.x; t < m1e; t += MM_THREADS) map[(uint32_t)col[t] >> 4] = 0u;
@@ -775,123 +780,129 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                 nc = (int32_t)total;
                 mna = (int32_t)(r1 - uniform64(upper_bound(col, a0b, r1, v1)));
             }
-            // this wave's children [xw, xe)
-            const int32_t xw = xa + w * WAVE;
-            const int32_t xe = min(xa + MM_CHILDREN, s);
-            if (xw >= xe) continue;
-            const int32_t x = xw + lane();
-            const bool valid = x < xe;
-            int32_t v2 = 0, code = 0;
-            int64_t lo2 = 0, s1 = 0;
-            int32_t I0[2] = {0, 0}, I1[2] = {0, 0}, I01[2] = {0, 0};
-            if (valid) {
-                v2 = A.vid2[b + x];
-                code = A.code2[b + x];
-                const int64_t s0 = A.rp[v2];
-                s1 = A.rp[v2 + 1];
-                lo2 = upper_bound(col, s0, s1, v0);
-                // the first mna children are A0's elements above v1, in order
-                const int64_t u0 = x < mna ? m0e - mna + x + 1 : upper_bound(col, m0b, m0e, v2);
-                const int64_t u1 = upper_bound(col, m1b, m1e, v2);
-                I0[0] = (int32_t)(u0 - m0b);
-                I0[1] = (int32_t)(m0e - u0);
-                I1[0] = (int32_t)(u1 - m1b);
-                I1[1] = (int32_t)(m1e - u1);
-                I01[0] = cum[u1 - m1b];
-                I01[1] = nc - I01[0];
-            }
-            // candidates: v2's list above v0
-            const int32_t len = (int32_t)(s1 - lo2);
-            uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            // short children: the lane streams its own list, four loads at a time
-            {
-                const bool mine = valid && len < WAVE;
-                int64_t t = lo2;
-                const int64_t te = mine ? s1 : lo2;
-                while (ballot(t < te)) {
-                    int32_t u[4];
+            __syncthreads();   // the counter is reset (and the marks are in place)
+            const int32_t xend = min(xa + MM_CHILDREN, s);
+            while (true) {
+                // the wave's next 64 children [xw, xe)
+                int32_t g = 0;
+                if (lane() == 0) g = atomicAdd(&s_grab, 1);
+                const int32_t xw = xa + uniform(bcast(g, 0)) * WAVE;
+                if (xw >= xend) break;
+                const int32_t xe = min(xw + WAVE, xend);
+                const int32_t x = xw + lane();
+                const bool valid = x < xe;
+                int32_t v2 = 0, code = 0;
+                int64_t lo2 = 0, s1 = 0;
+                int32_t I0[2] = {0, 0}, I1[2] = {0, 0}, I01[2] = {0, 0};
+                if (valid) {
+                    v2 = A.vid2[b + x];
+                    code = A.code2[b + x];
+                    const int64_t s0 = A.rp[v2];
+                    s1 = A.rp[v2 + 1];
+                    lo2 = upper_bound(col, s0, s1, v0);
+                    // the first mna children are A0's elements above v1, in order
+                    const int64_t u0 = x < mna ? m0e - mna + x + 1 : upper_bound(col, m0b, m0e, v2);
+                    const int64_t u1 = upper_bound(col, m1b, m1e, v2);
+                    I0[0] = (int32_t)(u0 - m0b);
+                    I0[1] = (int32_t)(m0e - u0);
+                    I1[0] = (int32_t)(u1 - m1b);
+                    I1[1] = (int32_t)(m1e - u1);
+                    I01[0] = cum[u1 - m1b];
+                    I01[1] = nc - I01[0];
+                }
+                // candidates: v2's list above v0
+                const int32_t len = (int32_t)(s1 - lo2);
+                uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                // short children: the lane streams its own list, four loads at a time
+                {
+                    const bool mine = valid && len < WAVE;
+                    int64_t t = lo2;
+                    const int64_t te = mine ? s1 : lo2;
+                    while (ballot(t < te)) {
+                        int32_t u[4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) u[q] = col[t + q < te ? t + q : 0];
+                        for (int q = 0; q < 4; ++q) u[q] = col[t + q < te ? t + q : 0];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const bool vq = t + q < te;
+                        for (int q = 0; q < 4; ++q) {
+                            const bool vq = t + q < te;
+                            const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
+                            const uint32_t lo = (vq && u[q] <= v2) ? 1u : 0u, hi = (vq && u[q] > v2) ? 1u : 0u;
+                            const uint32_t b0 = bits & 1u, b1 = (bits >> 1) & 1u;
+                            k[0] += b0 & lo;
+                            k[1] += b0 & hi;
+                            k[2] += b1 & lo;
+                            k[3] += b1 & hi;
+                            k[4] += b0 & b1 & lo;
+                            k[5] += b0 & b1 & hi;
+                            k[6] += lo;
+                            k[7] += hi;
+                        }
+                        t += 4;
+                    }
+                }
+                // long children: the wave streams their lists as one sequence of
+                // 64-candidate chunks, MM_G chunks (of one or several children)
+                // loaded before any is counted; each chunk's counts go to the
+                // lane of its child
+                uint64_t longm = ballot(valid && len >= WAVE);
+                int cxi = -1;
+                int64_t ct = 0, ch = 0;   // the current child's next chunk and end (wave-uniform)
+                auto next_child = [&]() {
+                    cxi = -1;
+                    if (longm) {
+                        cxi = __builtin_ctzll(longm);
+                        longm &= longm - 1;
+                        ct = (int64_t)readlane64((uint64_t)lo2, cxi);
+                        ch = (int64_t)readlane64((uint64_t)s1, cxi);
+                    }
+                };
+                next_child();
+                while (cxi >= 0) {
+                    int qx[MM_G];
+                    int64_t qt[MM_G], qh[MM_G];
+#pragma unroll
+                    for (int q = 0; q < MM_G; ++q) {
+                        qx[q] = cxi < 0 ? 0 : cxi;
+                        qt[q] = cxi < 0 ? 0 : ct;
+                        qh[q] = cxi < 0 ? 0 : ch;
+                        if (cxi >= 0) {
+                            ct += WAVE;
+                            if (ct >= ch) next_child();
+                        }
+                    }
+                    int32_t u[MM_G];
+#pragma unroll
+                    for (int q = 0; q < MM_G; ++q) {
+                        const int64_t t = qt[q] + lane();
+                        u[q] = col[t < qh[q] ? t : 0];
+                    }
+#pragma unroll
+                    for (int q = 0; q < MM_G; ++q) {
+                        if (qt[q] >= qh[q]) continue;   // an unused slot of the last group
+                        const bool vq = qt[q] + lane() < qh[q];
+                        const int32_t cv2 = readlane(v2, qx[q]);
                         const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
-                        const uint32_t lo = (vq && u[q] <= v2) ? 1u : 0u, hi = (vq && u[q] > v2) ? 1u : 0u;
-                        const uint32_t b0 = bits & 1u, b1 = (bits >> 1) & 1u;
-                        k[0] += b0 & lo;
-                        k[1] += b0 & hi;
-                        k[2] += b1 & lo;
-                        k[3] += b1 & hi;
-                        k[4] += b0 & b1 & lo;
-                        k[5] += b0 & b1 & hi;
-                        k[6] += lo;
-                        k[7] += hi;
-                    }
-                    t += 4;
-                }
-            }
-            // long children: the wave streams their lists as one sequence of
-            // 64-candidate chunks, MM_G chunks (of one or several children)
-            // loaded before any is counted; each chunk's counts go to the
-            // lane of its child
-            uint64_t longm = ballot(valid && len >= WAVE);
-            int cxi = -1;
-            int64_t ct = 0, ch = 0;   // the current child's next chunk and end (wave-uniform)
-            auto next_child = [&]() {
-                cxi = -1;
-                if (longm) {
-                    cxi = __builtin_ctzll(longm);
-                    longm &= longm - 1;
-                    ct = (int64_t)readlane64((uint64_t)lo2, cxi);
-                    ch = (int64_t)readlane64((uint64_t)s1, cxi);
-                }
-            };
-            next_child();
-            while (cxi >= 0) {
-                int qx[MM_G];
-                int64_t qt[MM_G], qh[MM_G];
-#pragma unroll
-                for (int q = 0; q < MM_G; ++q) {
-                    qx[q] = cxi < 0 ? 0 : cxi;
-                    qt[q] = cxi < 0 ? 0 : ct;
-                    qh[q] = cxi < 0 ? 0 : ch;
-                    if (cxi >= 0) {
-                        ct += WAVE;
-                        if (ct >= ch) next_child();
+                        const uint64_t Lo = ballot(vq && u[q] <= cv2);
+                        const uint64_t Hi = ballot(vq && u[q] > cv2);
+                        const uint64_t B0 = ballot(bits & 1u), B1 = ballot(bits & 2u);
+                        const uint64_t B01 = B0 & B1;
+                        const bool me = lane() == qx[q];
+                        k[0] += me ? (uint32_t)popc64(B0 & Lo) : 0u;
+                        k[1] += me ? (uint32_t)popc64(B0 & Hi) : 0u;
+                        k[2] += me ? (uint32_t)popc64(B1 & Lo) : 0u;
+                        k[3] += me ? (uint32_t)popc64(B1 & Hi) : 0u;
+                        k[4] += me ? (uint32_t)popc64(B01 & Lo) : 0u;
+                        k[5] += me ? (uint32_t)popc64(B01 & Hi) : 0u;
+                        k[6] += me ? (uint32_t)popc64(Lo) : 0u;
+                        k[7] += me ? (uint32_t)popc64(Hi) : 0u;
                     }
                 }
-                int32_t u[MM_G];
-#pragma unroll
-                for (int q = 0; q < MM_G; ++q) {
-                    const int64_t t = qt[q] + lane();
-                    u[q] = col[t < qh[q] ? t : 0];
+                if (valid) {
+                    streamed += (uint64_t)len;
+                    n_in += 1;
+                    motif4_classify(acc, k, I0, I1, I01, v1, v2, code);
                 }
-#pragma unroll
-                for (int q = 0; q < MM_G; ++q) {
-                    if (qt[q] >= qh[q]) continue;   // an unused slot of the last group
-                    const bool vq = qt[q] + lane() < qh[q];
-                    const int32_t cv2 = readlane(v2, qx[q]);
-                    const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
-                    const uint64_t Lo = ballot(vq && u[q] <= cv2);
-                    const uint64_t Hi = ballot(vq && u[q] > cv2);
-                    const uint64_t B0 = ballot(bits & 1u), B1 = ballot(bits & 2u);
-                    const uint64_t B01 = B0 & B1;
-                    const bool me = lane() == qx[q];
-                    k[0] += me ? (uint32_t)popc64(B0 & Lo) : 0u;
-                    k[1] += me ? (uint32_t)popc64(B0 & Hi) : 0u;
-                    k[2] += me ? (uint32_t)popc64(B1 & Lo) : 0u;
-                    k[3] += me ? (uint32_t)popc64(B1 & Hi) : 0u;
-                    k[4] += me ? (uint32_t)popc64(B01 & Lo) : 0u;
-                    k[5] += me ? (uint32_t)popc64(B01 & Hi) : 0u;
-                    k[6] += me ? (uint32_t)popc64(Lo) : 0u;
-                    k[7] += me ? (uint32_t)popc64(Hi) : 0u;
-                }
-            }
-            if (valid) {
-                streamed += (uint64_t)len;
-                n_in += 1;
-                motif4_classify(acc, k, I0, I1, I01, v1, v2, code);
-            }
+            }   // groups of 64 children
         }
     }
 #pragma unroll
