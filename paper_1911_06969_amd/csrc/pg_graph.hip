@@ -443,7 +443,10 @@ void build_motif_graph(pg_graph* g) {
     M.nnz = nnz;
     M.max_deg = g->max_deg;
     M.rp.reserve(sizeof(int64_t) * (n + 1));
-    M.col.reserve(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+    // 64 zeroed entries past the end, so a wave may read a whole 64-entry
+    // chunk from any list start
+    M.col.reserve(sizeof(int32_t) * (nnz + WAVE));
+    PG_HIP(hipMemsetAsync(M.col.as<int32_t>() + nnz, 0, sizeof(int32_t) * WAVE, s));
     DevBuf t1, t2, name, deg, hi;
     const int64_t big = std::max<int64_t>(std::max(n, nnz), 1);
     t1.reserve(sizeof(uint64_t) * big);

@@ -631,6 +631,7 @@ constexpr int MM_WAVES = MM_THREADS / WAVE;
 constexpr int MM_CHILDREN = 4096;              // children per item, taken by the waves 64 at a time
 constexpr int64_t MM_HEAVY = 256;              // entries with at least this many children use the map
 constexpr int MM_G = 8;                        // 64-candidate chunks loaded at once by a wave
+constexpr int32_t MM_LONG = 1024;              // children with this many candidates are streamed by the whole wave
 
 __device__ __forceinline__ uint32_t map_bits(const uint32_t* map, int32_t u) {
     return (map[(uint32_t)u >> 4] >> (((uint32_t)u & 15u) << 1)) & 3u;
@@ -813,90 +814,132 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                 // candidates: v2's list above v0
                 const int32_t len = (int32_t)(s1 - lo2);
                 uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                // short children: the lane streams its own list, four loads at a time
+                // children with fewer than MM_LONG candidates: the lane streams
+                // its own list, four candidates (one 16-byte load) at a time.  The
+                // children of an entry come in the order of their names, which is
+                // the order of decreasing degree, so the lists of a group of 64
+                // are of similar lengths.  A candidate u falls in one of eight
+                // classes (u above v2 or not, times its two map bits); the lane
+                // counts them in the eight bytes of a 64-bit word, one class bit
+                // per candidate, and moves the bytes to 32-bit counts every 63
+                // rounds (at most 252 per byte).  Lanes past the list take vertex
+                // 0 (no bits, not above v2): its class is never read.
                 {
-                    const bool mine = valid && len < WAVE;
-                    int64_t t = lo2;
-                    const int64_t te = mine ? s1 : lo2;
-                    while (ballot(t < te)) {
-                        int32_t u[4];
+                    const int32_t te = (valid && len < MM_LONG) ? len : 0;
+                    const int32_t nit = (te + 3) >> 2;
+                    const int32_t* cp = col + lo2;
+                    uint32_t n8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                    int32_t i = 0;
+                    // the next block is loaded before the current one is counted
+                    // (a block at most four past the list's last one: within the
+                    // zeroed tail)
+                    int32_t nu[4];
+                    __builtin_memcpy(nu, cp, 16);
+                    while (ballot(i < nit)) {
+                        uint64_t acc = 0;
+                        const int32_t stop = i + 63;
+                        do {
+                            if (i < nit) {
+                                int32_t u[4] = {nu[0], nu[1], nu[2], nu[3]};
+                                __builtin_memcpy(nu, cp + 4 * (i + 1), 16);
+                                const int32_t r = te - 4 * i;
+                                u[1] = r > 1 ? u[1] : 0;
+                                u[2] = r > 2 ? u[2] : 0;
+                                u[3] = r > 3 ? u[3] : 0;
+                                uint32_t mw[4];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) u[q] = col[t + q < te ? t + q : 0];
+                                for (int q = 0; q < 4; ++q) mw[q] = map[(uint32_t)u[q] >> 4];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const bool vq = t + q < te;
-                            const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
-                            const uint32_t lo = (vq && u[q] <= v2) ? 1u : 0u, hi = (vq && u[q] > v2) ? 1u : 0u;
-                            const uint32_t b0 = bits & 1u, b1 = (bits >> 1) & 1u;
-                            k[0] += b0 & lo;
-                            k[1] += b0 & hi;
-                            k[2] += b1 & lo;
-                            k[3] += b1 & hi;
-                            k[4] += b0 & b1 & lo;
-                            k[5] += b0 & b1 & hi;
-                            k[6] += lo;
-                            k[7] += hi;
-                        }
-                        t += 4;
+                                for (int q = 0; q < 4; ++q) {
+                                    const uint32_t bits = (mw[q] >> (((uint32_t)u[q] & 15u) << 1)) & 3u;
+                                    const uint32_t sh = (bits << 3) | (u[q] > v2 ? 32u : 0u);
+                                    acc += 1ull << sh;
+                                }
+                            }
+                            ++i;
+                        } while (i < stop && ballot(i < nit));
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) n8[c] += (uint32_t)(acc >> (8 * c)) & 255u;
                     }
+                    // class c = 4 * above + bits; bit 0: u ~ v0, bit 1: u ~ v1
+                    k[0] += n8[1] + n8[3];
+                    k[1] += n8[5] + n8[7];
+                    k[2] += n8[2] + n8[3];
+                    k[3] += n8[6] + n8[7];
+                    k[4] += n8[3];
+                    k[5] += n8[7];
+                    k[7] += n8[4] + n8[5] + n8[6] + n8[7];
                 }
                 // long children: the wave streams their lists as one sequence of
                 // 64-candidate chunks, MM_G chunks (of one or several children)
-                // loaded before any is counted; each chunk's counts go to the
-                // lane of its child
-                uint64_t longm = ballot(valid && len >= WAVE);
+                // loaded before any is counted.  A chunk is read from a uniform
+                // base with one lane offset (the column array has a zeroed tail of
+                // 64 entries, so the lanes past a list read in bounds) and those
+                // lanes then take vertex 0, which is never marked and lies below
+                // every v2; all map words of the group are read before any is
+                // used.  A chunk adds to its child's lane the candidates above v2
+                // and, per range, those adjacent to v0, to v1 and to both; the
+                // candidates at or below v2 follow from the list length.
+                uint64_t longm = ballot(valid && len >= MM_LONG);
                 int cxi = -1;
-                int64_t ct = 0, ch = 0;   // the current child's next chunk and end (wave-uniform)
+                const int32_t* cb = col;   // the current child's list (wave-uniform)
+                int32_t co = 0, cl = 0;    // its next chunk and length
+                int32_t cv2 = 0;
                 auto next_child = [&]() {
                     cxi = -1;
                     if (longm) {
                         cxi = __builtin_ctzll(longm);
                         longm &= longm - 1;
-                        ct = (int64_t)readlane64((uint64_t)lo2, cxi);
-                        ch = (int64_t)readlane64((uint64_t)s1, cxi);
+                        cb = col + (int64_t)readlane64((uint64_t)lo2, cxi);
+                        cl = readlane(len, cxi);
+                        cv2 = readlane(v2, cxi);
+                        co = 0;
                     }
                 };
                 next_child();
                 while (cxi >= 0) {
                     int qx[MM_G];
-                    int64_t qt[MM_G], qh[MM_G];
+                    int32_t qn[MM_G], qv[MM_G];
+                    const int32_t* qp[MM_G];
 #pragma unroll
                     for (int q = 0; q < MM_G; ++q) {
-                        qx[q] = cxi < 0 ? 0 : cxi;
-                        qt[q] = cxi < 0 ? 0 : ct;
-                        qh[q] = cxi < 0 ? 0 : ch;
+                        qx[q] = cxi;
+                        qn[q] = cxi < 0 ? 0 : min(WAVE, cl - co);
+                        qp[q] = cxi < 0 ? col : cb + co;
+                        qv[q] = cv2;
                         if (cxi >= 0) {
-                            ct += WAVE;
-                            if (ct >= ch) next_child();
+                            co += WAVE;
+                            if (co >= cl) next_child();
                         }
                     }
                     int32_t u[MM_G];
 #pragma unroll
+                    for (int q = 0; q < MM_G; ++q) u[q] = qp[q][lane()];
+                    uint32_t mw[MM_G];
+#pragma unroll
                     for (int q = 0; q < MM_G; ++q) {
-                        const int64_t t = qt[q] + lane();
-                        u[q] = col[t < qh[q] ? t : 0];
+                        u[q] = lane() < qn[q] ? u[q] : 0;
+                        mw[q] = map[(uint32_t)u[q] >> 4];
                     }
 #pragma unroll
                     for (int q = 0; q < MM_G; ++q) {
-                        if (qt[q] >= qh[q]) continue;   // an unused slot of the last group
-                        const bool vq = qt[q] + lane() < qh[q];
-                        const int32_t cv2 = readlane(v2, qx[q]);
-                        const uint32_t bits = vq ? map_bits(map, u[q]) : 0u;
-                        const uint64_t Lo = ballot(vq && u[q] <= cv2);
-                        const uint64_t Hi = ballot(vq && u[q] > cv2);
+                        if (qx[q] < 0) continue;   // an unused slot of the last group
+                        const uint32_t bits = mw[q] >> (((uint32_t)u[q] & 15u) << 1);
                         const uint64_t B0 = ballot(bits & 1u), B1 = ballot(bits & 2u);
+                        const uint64_t Hi = ballot(u[q] > qv[q]);
                         const uint64_t B01 = B0 & B1;
-                        const bool me = lane() == qx[q];
-                        k[0] += me ? (uint32_t)popc64(B0 & Lo) : 0u;
-                        k[1] += me ? (uint32_t)popc64(B0 & Hi) : 0u;
-                        k[2] += me ? (uint32_t)popc64(B1 & Lo) : 0u;
-                        k[3] += me ? (uint32_t)popc64(B1 & Hi) : 0u;
-                        k[4] += me ? (uint32_t)popc64(B01 & Lo) : 0u;
-                        k[5] += me ? (uint32_t)popc64(B01 & Hi) : 0u;
-                        k[6] += me ? (uint32_t)popc64(Lo) : 0u;
-                        k[7] += me ? (uint32_t)popc64(Hi) : 0u;
+                        if (lane() == qx[q]) {
+                            k[0] += (uint32_t)popc64(B0 & ~Hi);
+                            k[1] += (uint32_t)popc64(B0 & Hi);
+                            k[2] += (uint32_t)popc64(B1 & ~Hi);
+                            k[3] += (uint32_t)popc64(B1 & Hi);
+                            k[4] += (uint32_t)popc64(B01 & ~Hi);
+                            k[5] += (uint32_t)popc64(B01 & Hi);
+                            k[7] += (uint32_t)popc64(Hi);
+                        }
                     }
                 }
+                if (valid) k[6] = (uint32_t)len - k[7];
                 if (valid) {
                     streamed += (uint64_t)len;
                     n_in += 1;
