@@ -632,6 +632,8 @@ constexpr int MM_CHILDREN = 4096;              // children per item, taken by th
 constexpr int64_t MM_HEAVY = 256;              // entries with at least this many children use the map
 constexpr int MM_G = 8;                        // 64-candidate chunks loaded at once by a wave
 constexpr int32_t MM_LONG = 1024;              // children with this many candidates are streamed by the whole wave
+constexpr int MM_E = 16;                       // candidates a lane counts per round (a multiple of 4)
+constexpr int MM_FLUSH = 252 / MM_E;           // rounds between moves of the byte counts
 
 __device__ __forceinline__ uint32_t map_bits(const uint32_t* map, int32_t u) {
     return (map[(uint32_t)u >> 4] >> (((uint32_t)u & 15u) << 1)) & 3u;
@@ -815,43 +817,45 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                 const int32_t len = (int32_t)(s1 - lo2);
                 uint32_t k[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 // children with fewer than MM_LONG candidates: the lane streams
-                // its own list, four candidates (one 16-byte load) at a time.  The
+                // its own list, MM_E candidates (16-byte loads) at a time.  The
                 // children of an entry come in the order of their names, which is
                 // the order of decreasing degree, so the lists of a group of 64
                 // are of similar lengths.  A candidate u falls in one of eight
                 // classes (u above v2 or not, times its two map bits); the lane
                 // counts them in the eight bytes of a 64-bit word, one class bit
-                // per candidate, and moves the bytes to 32-bit counts every 63
-                // rounds (at most 252 per byte).  Lanes past the list take vertex
-                // 0 (no bits, not above v2): its class is never read.
+                // per candidate, and moves the bytes to 32-bit counts every
+                // MM_FLUSH rounds (at most 252 per byte).  Lanes past the list
+                // take vertex 0 (no bits, not above v2): its class is never read.
                 {
                     const int32_t te = (valid && len < MM_LONG) ? len : 0;
-                    const int32_t nit = (te + 3) >> 2;
+                    const int32_t nit = (te + MM_E - 1) / MM_E;
                     const int32_t* cp = col + lo2;
                     uint32_t n8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                     int32_t i = 0;
                     // the next block is loaded before the current one is counted
-                    // (a block at most four past the list's last one: within the
-                    // zeroed tail)
-                    int32_t nu[4];
-                    __builtin_memcpy(nu, cp, 16);
+                    // (it ends at most 2 * MM_E - 1 entries past the list: within
+                    // the zeroed tail)
+                    int32_t nu[MM_E];
+                    __builtin_memcpy(nu, cp, 4 * MM_E);
                     while (ballot(i < nit)) {
                         uint64_t acc = 0;
-                        const int32_t stop = i + 63;
+                        const int32_t stop = i + MM_FLUSH;
                         do {
                             if (i < nit) {
-                                int32_t u[4] = {nu[0], nu[1], nu[2], nu[3]};
-                                __builtin_memcpy(nu, cp + 4 * (i + 1), 16);
-                                const int32_t r = te - 4 * i;
-                                u[1] = r > 1 ? u[1] : 0;
-                                u[2] = r > 2 ? u[2] : 0;
-                                u[3] = r > 3 ? u[3] : 0;
-                                uint32_t mw[4];
+                                int32_t u[MM_E];
 #pragma unroll
-                                for (int q = 0; q < 4; ++q) mw[q] = map[(uint32_t)u[q] >> 4];
+                                for (int q = 0; q < MM_E; ++q) u[q] = nu[q];
+                                __builtin_memcpy(nu, cp + MM_E * (i + 1), 4 * MM_E);
+                                const int32_t r = te - MM_E * i;
 #pragma unroll
-                                for (int q = 0; q < 4; ++q) {
-                                    const uint32_t bits = (mw[q] >> (((uint32_t)u[q] & 15u) << 1)) & 3u;
+                                for (int q = 1; q < MM_E; ++q) u[q] = r > q ? u[q] : 0;
+                                uint32_t mw[MM_E];
+#pragma unroll
+                                for (int q = 0; q < MM_E; ++q) mw[q] = map[(uint32_t)u[q] >> 4];
+#pragma unroll
+                                for (int q = 0; q < MM_E; ++q) {
+                                    // v_bfe takes the low five bits of its offset: 2 * (u mod 16)
+                                    const uint32_t bits = __builtin_amdgcn_ubfe(mw[q], (uint32_t)u[q] << 1, 2u);
                                     const uint32_t sh = (bits << 3) | (u[q] > v2 ? 32u : 0u);
                                     acc += 1ull << sh;
                                 }
