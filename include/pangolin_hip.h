@@ -106,9 +106,18 @@ int pg_set_memory_budget(pg_graph* g, uint64_t bytes);
  *                        bitmask over its root's out-list; k = 3 is their
  *                        number, and deeper levels count with popcounts;
  *                        0: the general level kernels for every k.
+ *   PG_OPT_FSM_BIT_KEYS  1 (default): FSM sets the domain bits of patterns
+ *                        of three edges (section 5.3) by writing one key
+ *                        (bitmap word, bit) per embedding vertex, sorting
+ *                        the keys by 64 KB bitmap block and OR-ing each
+ *                        block in LDS, when the keys fit the memory budget
+ *                        (32 B per embedding, twice); 0: an atomic OR per
+ *                        embedding vertex into the bitmaps.  Supports are
+ *                        the same either way.
  * Unknown options return PG_EINVAL.
  */
 #define PG_OPT_CLIQUE_MASKS 1
+#define PG_OPT_FSM_BIT_KEYS 2
 int pg_graph_set_option(pg_graph* g, int option, int64_t value);
 
 /*

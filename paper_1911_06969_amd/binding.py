@@ -212,6 +212,7 @@ def pg_set_memory_budget(g, nbytes: int) -> None:
 
 
 PG_OPT_CLIQUE_MASKS = 1
+PG_OPT_FSM_BIT_KEYS = 2
 
 
 def pg_graph_set_option(g, option: int, value: int) -> None:

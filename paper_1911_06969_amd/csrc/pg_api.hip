@@ -46,12 +46,15 @@ static void run_with_arena(pg_graph* g, F&& body) {
         } catch (const Error& e) {
             (void)hipStreamSynchronize(g->stream);
             prof_flush();
-            if (e.code == PG_ENOMEM && e.msg == "arena" && attempt < 12) {
+            if (e.code == PG_ENOMEM && e.msg == "arena" && attempt < 32) {
                 const size_t cap = g->budget + (size_t(64) << 20);
                 if (g->arena.need > cap)
                     throw Error{PG_ENOMEM, "memory budget too small for the embedding levels (need " +
                                                std::to_string(g->arena.need) + " bytes)"};
-                g->arena.want = std::min(g->arena.want, std::max(g->arena.need, cap));
+                // at least twice the last size: a call finds its needs one push
+                // at a time, and each retry runs it from the start
+                g->arena.want = std::min(std::max(g->arena.want, 2 * g->arena.buf.bytes),
+                                         std::max(g->arena.need, cap));
                 g->arena.buf.release();
                 continue;
             }
@@ -141,6 +144,7 @@ int pg_graph_set_option(pg_graph* g, int option, int64_t value) {
         PG_REQUIRE(g != nullptr, PG_EINVAL, "graph is NULL");
         switch (option) {
             case PG_OPT_CLIQUE_MASKS: g->force_generic = (value == 0); break;
+            case PG_OPT_FSM_BIT_KEYS: g->fsm_bit_keys = (value != 0); break;
             default: throw Error{PG_EINVAL, "unknown option " + std::to_string(option)};
         }
     });

@@ -700,6 +700,62 @@ __device__ __forceinline__ void set_bits(const Bits& Bt, const Emb& E) {
     }
 }
 
+// The domain bits of one embedding of at most four vertices as sort keys:
+// (bitmap word << 5 | bit) per vertex, all ones where there is none (fewer
+// vertices, or a pattern without a slot in this group), four keys per
+// embedding at a 32-byte aligned place.
+__device__ __forceinline__ void bit_keys(const Bits& Bt, const Emb& E, uint64_t* __restrict__ out) {
+    const int32_t sl = Bt.slot[E.pid];
+    const bool in = sl >= Bt.s_lo && sl < Bt.s_hi;
+    const uint64_t base = in ? (uint64_t)(sl - Bt.s_lo) * Bt.norb : 0;
+    uint64_t k[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        k[i] = ~0ull;
+        if (in && i < E.nv) {
+            const uint32_t v = (uint32_t)Bt.lrank[E.v[i]];
+            k[i] = (((base + (uint64_t)E.orb[i]) * (uint64_t)Bt.words + (v >> 5)) << 5) | (v & 31u);
+        }
+    }
+    __builtin_memcpy(__builtin_assume_aligned(out, 32), k, 32);
+}
+
+// Bitmap blocks of FB_WORDS words (64 KB): the keys are sorted by block
+// (key >> FB_SHIFT), then one workgroup per block ORs its keys into LDS
+// and stores the block's words.  The all-ones keys sort after every block
+// (the sort covers enough bits to tell the last block from them).
+constexpr int FB_WORDS = 16384;
+constexpr int FB_SHIFT = 5 + 14;
+constexpr int FB_THREADS = 1024;
+
+__device__ __forceinline__ int64_t first_key_at_least(const uint64_t* __restrict__ keys, int64_t m, uint64_t t) {
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(FB_THREADS) void k_bits_apply(const uint64_t* __restrict__ keys, int64_t m,
+                                                           int64_t total_words, uint32_t* __restrict__ bm) {
+    __shared__ uint32_t w[FB_WORDS];
+    __shared__ int64_t rng[2];
+    const int64_t b = blockIdx.x;
+    for (int i = threadIdx.x; i < FB_WORDS; i += FB_THREADS) w[i] = 0;
+    if (threadIdx.x < 2) rng[threadIdx.x] = first_key_at_least(keys, m, (uint64_t)(b + threadIdx.x) << FB_SHIFT);
+    __syncthreads();
+    for (int64_t i = rng[0] + threadIdx.x; i < rng[1]; i += FB_THREADS) {
+        const uint64_t k = keys[i];
+        atomicOr(&w[(uint32_t)(k >> 5) & (FB_WORDS - 1)], 1u << (uint32_t)(k & 31u));
+    }
+    __syncthreads();
+    const int64_t w0 = b * FB_WORDS;
+    const int nw = (int)min64(FB_WORDS, total_words - w0);
+    for (int i = threadIdx.x; i < nw; i += FB_THREADS) bm[w0 + i] = w[i];
+}
+
 // level 1: patterns of every edge, or domain bits
 template <bool BITS>
 __global__ void k_fsm_l1(FsmCtx C, int64_t E, int32_t* __restrict__ pid, Bits Bt) {
@@ -758,16 +814,18 @@ __global__ void k_fsm_l2(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, u
 }
 
 // Level 3 from frequent wedges.  L3_HIST / L3_BITS: fused with Reduce (a
-// histogram of patterns, or domain bits); L3_COUNT / L3_WRITE: the
-// materialised level of four-edge mining (children per parent, then
-// (e1, e2, e3, pattern) at the parent's offset).
-enum { L3_HIST = 0, L3_BITS = 1, L3_COUNT = 2, L3_WRITE = 3 };
+// histogram of patterns, with the children per parent when nch is given,
+// or domain bits); L3_KEYS: the domain bits as sort keys at the parent's
+// offset; L3_COUNT / L3_WRITE: the materialised level of four-edge mining
+// (children per parent, then (e1, e2, e3, pattern) at the parent's offset).
+enum { L3_HIST = 0, L3_BITS = 1, L3_COUNT = 2, L3_WRITE = 3, L3_KEYS = 4 };
 
 template <int MODE>
 __global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, const int32_t* __restrict__ e2s,
                          uint32_t* __restrict__ counts, Bits Bt, unsigned long long* __restrict__ n_emb,
                          const uint64_t* __restrict__ start, int32_t* __restrict__ o1, int32_t* __restrict__ o2,
-                         int32_t* __restrict__ o3, int32_t* __restrict__ opid) {
+                         int32_t* __restrict__ o3, int32_t* __restrict__ opid, uint32_t* __restrict__ nch,
+                         uint64_t* __restrict__ keys) {
     uint64_t local = 0, scanned = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t e1 = e1s[i], e2 = e2s[i];
@@ -777,12 +835,16 @@ __global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, c
         const int32_t o = (s == a) ? b : a;
         const int32_t t = (s == c) ? d : c;
         if (MODE == L3_HIST) scanned += (uint64_t)(C.rp[s + 1] - C.rp[s] + C.rp[o + 1] - C.rp[o] + C.rp[t + 1] - C.rp[t]);
-        uint64_t pos = MODE == L3_WRITE ? start[i] : 0;
+        uint64_t pos = (MODE == L3_WRITE || MODE == L3_KEYS) ? start[i] : 0;
         uint32_t nchild = 0;
         auto emit = [&](int32_t e3, const Emb& Em) {
             ++local;
             if (MODE == L3_HIST) atomicAdd(&counts[Em.pid], 1u);
             if (MODE == L3_BITS) set_bits(Bt, Em);
+            if (MODE == L3_KEYS) {
+                bit_keys(Bt, Em, keys + (pos << 2));
+                ++pos;
+            }
             if (MODE == L3_WRITE) {
                 o1[pos] = e1;
                 o2[pos] = e2;
@@ -817,6 +879,7 @@ __global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, c
             emit(C.eid[j], classify_path(C, o, s, t, w));
         }
         if (MODE == L3_COUNT) counts[i] = nchild;
+        if (MODE == L3_HIST && nch) nch[i] = nchild;
     }
     if (MODE == L3_HIST) {
         local = wave_sum_u64(local);
@@ -935,6 +998,16 @@ __global__ void k_frequent(int64_t np, const int32_t* __restrict__ slot, const u
 }
 
 // ------------------------------------------------------------------ host
+
+// Throws as a full arena push does unless `bytes` more fit, so that the
+// call is retried once with room for several large pushes that follow.
+static void arena_ensure(Arena& a, size_t bytes) {
+    if (a.top + bytes > a.buf.bytes) {
+        a.need = std::max(a.need, a.top + bytes);
+        a.want = std::max(a.want, a.need + a.need / 4);
+        throw Error{PG_ENOMEM, "arena"};
+    }
+}
 
 static unsigned grid1(int64_t items) {
     int64_t b = (items + 255) / 256;
@@ -1107,7 +1180,8 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
     unsigned long long* n_emb = reinterpret_cast<unsigned long long*>(push<uint64_t>(ar, 4));
     fill_u64(reinterpret_cast<uint64_t*>(n_emb), 4, 0, s);
 
-    int64_t n2_total = 0, m2_total = 0, l3_passes = 0, n3_stored = 0;
+    int64_t n2_total = 0, m2_total = 0, l3_passes = 0, l3_key_passes = 0, n3_stored = 0;
+    double apply_keys = 0.0, apply_words = 0.0;
     // ---------------- level 1: every edge; Reduce; Filter
     int32_t* pid1 = push<int32_t>(ar, std::max<int64_t>(E, 1));
     {
@@ -1175,20 +1249,61 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
             PG_HIP(hipGetLastError());
             if (max_edges == 3) {
                 // ---------------- level 3, fused with Reduce (never stored)
+                uint32_t* nch = push<uint32_t>(ar, std::max<int64_t>(m2, 1));
+                uint64_t* st3 = push<uint64_t>(ar, m2 + 1);
                 if (m2 > 0) {
                     ProfScope ps("fsm_l3_hist", s, (double)m2);
                     k_fsm_l3<L3_HIST><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, counts, Bits{}, n_emb, nullptr,
-                                                                nullptr, nullptr, nullptr, nullptr);
+                                                                nullptr, nullptr, nullptr, nullptr, nch, nullptr);
                     PG_HIP(hipGetLastError());
                 }
+                // every embedding's place among the level's, for the bit keys
+                scan_u32(nch, m2, st3, ar, s);
+                const int64_t n3 = (int64_t)read_u64(st3 + m2, s);
                 reduce_level(g, C, lrank, label_max, C.B.tri, C.B.total, counts, min_support, freq, sup_pat,
                              [&](const Bits& Bt) {
-                    if (m2 > 0) {
+                    if (m2 == 0) return;
+                    // sorted keys need 2 x 32 B per embedding and the sort's tile
+                    // histograms (12 B per digit per 2,048 keys)
+                    const int64_t nk = 4 * n3;
+                    const uint64_t need = 64ull * (uint64_t)n3 + 12ull * 256 * (uint64_t)(nk / 2048 + 2) +
+                                          (uint64_t(64) << 20);
+                    const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
+                    if (g->fsm_bit_keys && n3 > 0 && need <= room) {
+                        arena_ensure(ar, need);
+                        const size_t mk = ar.mark();
+                        const int64_t total_words = (int64_t)(Bt.s_hi - Bt.s_lo) * Bt.norb * Bt.words;
+                        const int64_t nblk = (total_words + FB_WORDS - 1) / FB_WORDS;
+                        // sort digits enough for 2^bits > nblk: the all-ones keys
+                        // then sort after the last block
+                        int bits = 1;
+                        while ((int64_t(1) << bits) <= nblk) ++bits;
+                        uint64_t* keys = push<uint64_t>(ar, nk);
+                        uint64_t* tmp = push<uint64_t>(ar, nk);
+                        {
+                            ProfScope ps("fsm_l3_keys", s, (double)m2);
+                            k_fsm_l3<L3_KEYS><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bt, nullptr, st3,
+                                                                        nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                                        keys);
+                            PG_HIP(hipGetLastError());
+                        }
+                        radix_sort_u64(keys, tmp, nk, FB_SHIFT, FB_SHIFT + bits, ar, s);
+                        {
+                            ProfScope ps("fsm_bits_apply", s, (double)nk);
+                            k_bits_apply<<<(unsigned)nblk, FB_THREADS, 0, s>>>(keys, nk, total_words, Bt.bm);
+                            PG_HIP(hipGetLastError());
+                        }
+                        ar.reset(mk);
+                        ++l3_key_passes;   // one per group of candidate patterns
+                        apply_keys += (double)nk;
+                        apply_words += (double)total_words;
+                    } else {
+                        ++l3_passes;
                         ProfScope ps("fsm_l3_bits", s, (double)m2);
                         k_fsm_l3<L3_BITS><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bt, nullptr, nullptr,
-                                                                    nullptr, nullptr, nullptr, nullptr);
+                                                                    nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                                    nullptr);
                         PG_HIP(hipGetLastError());
-                        ++l3_passes;   // one per group of candidate patterns
                     }
                 });
             } else {
@@ -1198,7 +1313,8 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
                 if (m2 > 0) {
                     ProfScope ps("fsm_l3_count", s, (double)m2);
                     k_fsm_l3<L3_COUNT><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, c3, Bits{}, nullptr, nullptr,
-                                                                 nullptr, nullptr, nullptr, nullptr);
+                                                                 nullptr, nullptr, nullptr, nullptr, nullptr,
+                                                                 nullptr);
                     PG_HIP(hipGetLastError());
                 }
                 scan_u32(c3, m2, st3, ar, s);
@@ -1212,7 +1328,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
                 if (m2 > 0) {
                     ProfScope ps("fsm_l3_write", s, (double)n3);
                     k_fsm_l3<L3_WRITE><<<grid1(m2), 256, 0, s>>>(C, m2, fa, fb, nullptr, Bits{}, nullptr, st3, x3,
-                                                                 y3, z3, p3);
+                                                                 y3, z3, p3, nullptr, nullptr);
                     PG_HIP(hipGetLastError());
                     k_hist<<<hist_blocks(n3), 256, 0, s>>>(n3, p3, counts, (int32_t)C.B.tri,
                                                            (int32_t)(C.B.p5 - C.B.tri));
@@ -1271,9 +1387,22 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
         // row-pointer pairs (72 B); per scanned list element its vertex and
         // edge id (8 B); per embedding the new vertex's label (4 B) and a
         // read-modify-write of one domain word per vertex (4 x 8 B)
-        if (l3_passes > 0)
-            ProfScope pw("fsm_l3_bits_work", s,
-                         (double)l3_passes * (72.0 * (double)m2_total + 8.0 * (double)n3s[1] + 36.0 * (double)n3));
+        const double walk = 72.0 * (double)m2_total + 8.0 * (double)n3s[1];
+        if (l3_passes > 0) ProfScope pw("fsm_l3_bits_work", s, (double)l3_passes * (walk + 36.0 * (double)n3));
+        if (max_edges == 3 && m2_total > 0) {
+            // the histogram pass: the same walk, per embedding the new
+            // vertex's label and a histogram update (4 + 8 B), per parent its
+            // child count (4 B)
+            ProfScope ph("fsm_l3_hist_work", s, walk + 12.0 * (double)n3 + 4.0 * (double)m2_total);
+        }
+        // the key pass: the walk, per parent its offset (8 B), per embedding
+        // the new vertex's label and four 8-byte keys; the block pass: each
+        // key read once and every bitmap word written once
+        if (l3_key_passes > 0) {
+            ProfScope pk("fsm_l3_keys_work", s,
+                         (double)l3_key_passes * (walk + 8.0 * (double)m2_total + 36.0 * (double)n3));
+            ProfScope pa("fsm_bits_apply_work", s, 8.0 * apply_keys + 4.0 * apply_words);
+        }
     }
     size_t nf = 0;
     for (int64_t p = 0; p < np; ++p) {

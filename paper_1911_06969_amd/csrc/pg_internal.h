@@ -190,6 +190,7 @@ struct pg_graph {
     pg::MotifGraph mg;
     uint64_t budget = 0;     // bytes for materialised levels
     bool force_generic = false;   // cliques: skip the sibling-mask path
+    bool fsm_bit_keys = true;     // FSM: sorted bit keys for three-edge domains
     pg::Arena arena;
 };
 

@@ -537,6 +537,8 @@ void radix_sort_u64(uint64_t* keys, uint64_t* tmp, int64_t m, int lo_bit, int hi
     uint64_t* dst = tmp;
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         ProfScope ps("radix_sort", s, (double)m);
+        // per pass every key is read twice (histogram, scatter) and written once
+        ProfScope pw("radix_sort_work", s, 24.0 * (double)m);
         k_radix_hist<<<(unsigned)n_tiles, RS_THREADS, 0, s>>>(src, m, shift, n_tiles, hist);
         PG_HIP(hipGetLastError());
         scan_u32(hist, 256 * n_tiles, offs, a, s);

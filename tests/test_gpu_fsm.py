@@ -79,6 +79,20 @@ def test_bitmap_groups_under_small_budget(torch):
     assert np.array_equal(gpu_fsm(g, 3, 5, budget=8 << 20), want)
 
 
+@pytest.mark.parametrize("n,L,sigma", [(30000, 6, 20), (5000, 3, 2)])
+def test_bit_keys_and_atomic_bits_agree(torch, n, L, sigma):
+    """Domain bits of three-edge patterns through sorted keys (the default)
+    and through atomic ORs give the oracle's supports."""
+    g = synth.erdos_renyi(n, 8 / (n - 1), seed=46, n_labels=L)
+    want = oracle.fsm(g, 3, sigma)
+    for keys in (1, 0):
+        with binding.Graph.from_csr(g) as G:
+            G.set_option(binding.PG_OPT_FSM_BIT_KEYS, keys)
+            sup, nf = binding.pg_fsm(G.h, 3, sigma, g.n_labels)
+        say("fsm bit keys", keys, n, L, sigma, nf)
+        assert np.array_equal(sup, want)
+
+
 def test_thresholds_and_antimonotone(torch):
     g = synth.erdos_renyi(3000, 0.003, seed=46, n_labels=3)
     allsup = gpu_fsm(g, 3, 0)
