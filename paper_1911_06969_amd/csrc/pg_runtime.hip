@@ -459,18 +459,20 @@ void scan_u64(const uint64_t* in, int64_t m, uint64_t* out, Arena& a, hipStream_
 // tile (laid out digit-major), an exclusive scan of the histograms, then a
 // stable scatter.  Inside a tile every wave owns a contiguous run of keys
 // and ranks them in order; the ranks of equal digits within one 64-key
-// step come from eight ballots (one per digit bit).
+// step come from eight ballots (one per digit bit).  The ranked keys are
+// first placed in LDS in digit order, then written out in that order, so
+// that each digit's keys of a tile (32 on average) leave as one run.
 
-constexpr int RS_THREADS = 256;
+constexpr int RS_THREADS = 512;    // at least 256: one thread per digit
 constexpr int RS_WAVES = RS_THREADS / WAVE;
-constexpr int RS_PER_WAVE = 512;   // keys per wave per tile
+constexpr int RS_PER_WAVE = 1024;   // keys per wave per tile
 constexpr int64_t RS_TILE = (int64_t)RS_WAVES * RS_PER_WAVE;
 
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t m,
                                                            int shift, int64_t n_tiles,
                                                            uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    if (threadIdx.x < 256) h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t0 = blockIdx.x * RS_TILE;
     for (int64_t i = threadIdx.x; i < RS_TILE; i += RS_THREADS) {
@@ -478,30 +480,54 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint64_t* __res
         if (j < m) atomicAdd(&h[(keys[j] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t* __restrict__ keys, int64_t m,
                                                               int shift, int64_t n_tiles,
                                                               const uint64_t* __restrict__ offs,
                                                               uint64_t* __restrict__ out) {
-    __shared__ uint32_t wcount[RS_WAVES][256];
+    // per wave and digit: its count, then (in place) its next place
     __shared__ uint32_t run[RS_WAVES][256];
+    __shared__ uint32_t dstart[256];
+    __shared__ uint64_t sk[RS_TILE];
     const int w = threadIdx.x / WAVE;
-    for (int d = lane(); d < 256; d += WAVE) wcount[w][d] = 0;
+    for (int d = lane(); d < 256; d += WAVE) run[w][d] = 0;
     __syncthreads();
-    const int64_t wbase = blockIdx.x * RS_TILE + (int64_t)w * RS_PER_WAVE;
+    const int64_t tbase = blockIdx.x * RS_TILE;
+    const int64_t wbase = tbase + (int64_t)w * RS_PER_WAVE;
     for (int it = 0; it < RS_PER_WAVE; it += WAVE) {
         int64_t j = wbase + it + lane();
-        if (j < m) atomicAdd(&wcount[w][(keys[j] >> shift) & 255u], 1u);
+        if (j < m) atomicAdd(&run[w][(keys[j] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    // run[w][d] = tile offset of digit d + keys of digit d in earlier waves
-    for (int d = threadIdx.x; d < 256; d += RS_THREADS) {
-        uint32_t acc = 0;
+    // dstart[d]: first place of digit d in the tile's digit order (one
+    // thread per digit, the 256 totals scanned by the first wave's lanes)
+    if (threadIdx.x < 256) {
+        const int d = threadIdx.x;
+        uint32_t tot = 0;
+        for (int ww = 0; ww < RS_WAVES; ++ww) tot += run[ww][d];
+        dstart[d] = tot;
+    }
+    __syncthreads();
+    if (w == 0) {
+        uint32_t carry = 0;
+        for (int c = 0; c < 256; c += WAVE) {
+            const uint32_t v = dstart[c + lane()];
+            const uint32_t inc = wave_incl_scan(v);
+            dstart[c + lane()] = carry + inc - v;
+            carry += bcast(inc, WAVE - 1);
+        }
+    }
+    __syncthreads();
+    // run[w][d] = place of wave w's first key of digit d
+    if (threadIdx.x < 256) {
+        const int d = threadIdx.x;
+        uint32_t acc = dstart[d];
         for (int ww = 0; ww < RS_WAVES; ++ww) {
+            const uint32_t c = run[ww][d];
             run[ww][d] = acc;
-            acc += wcount[ww][d];
+            acc += c;
         }
     }
     __syncthreads();
@@ -518,11 +544,19 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t* __
         }
         uint32_t before = (uint32_t)popc64(peers & lanemask_lt());
         uint32_t base = valid ? run[w][d] : 0;
-        if (valid) out[offs[(int64_t)d * n_tiles + blockIdx.x] + base + before] = k;
+        if (valid) sk[base + before] = k;
         // the highest lane of each digit group advances the running count
         bool last = valid && ((peers >> lane()) == 1ull);
         if (last) run[w][d] = base + before + 1;
         __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // out in digit order: a digit's keys go to consecutive places
+    const int n = (int)min64(RS_TILE, m - tbase);
+    for (int p = threadIdx.x; p < n; p += RS_THREADS) {
+        const uint64_t k = sk[p];
+        const uint32_t d = (uint32_t)((k >> shift) & 255u);
+        out[offs[(int64_t)d * n_tiles + blockIdx.x] + (uint32_t)(p - (int)dstart[d])] = k;
     }
 }
 
