@@ -373,6 +373,17 @@ __global__ __launch_bounds__(256) void k_upper_write(int64_t n, const int64_t* _
     }
 }
 
+// for every L1 entry (u, v): the first place in v's row past u
+__global__ __launch_bounds__(256) void k_upper_rev(int64_t m, const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, const int32_t* __restrict__ src,
+                                                   const int32_t* __restrict__ dst, int32_t* __restrict__ rev) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = dst[p];
+        const int64_t q0 = rp[v];
+        rev[p] = (int32_t)(upper_bound(col, q0, rp[v + 1], src[p]) - q0);
+    }
+}
+
 void build_motif_l1(pg_graph* g, const MotifView& V) {
     MotifL1& L = *V.ml1;
     if (L.built) return;
@@ -381,6 +392,7 @@ void build_motif_l1(pg_graph* g, const MotifView& V) {
     L.seg.reserve(sizeof(int64_t) * (n + 1));
     L.src.reserve(sizeof(int32_t) * std::max<int64_t>(m, 1));
     L.dst.reserve(sizeof(int32_t) * std::max<int64_t>(m, 1));
+    L.rev.reserve(sizeof(int32_t) * std::max<int64_t>(m, 1));
     DevBuf cnt;
     cnt.reserve(sizeof(uint32_t) * std::max<int64_t>(n, 1));
     Arena tmp;
@@ -392,6 +404,11 @@ void build_motif_l1(pg_graph* g, const MotifView& V) {
         k_upper_write<<<grid_for(n, 4), 256, 0, s>>>(n, V.rp, V.col, L.seg.as<uint64_t>(), L.src.as<int32_t>(),
                                                      L.dst.as<int32_t>());
         PG_HIP(hipGetLastError());
+        if (m > 0) {
+            k_upper_rev<<<grid_for(m, 256), 256, 0, s>>>(m, V.rp, V.col, L.src.as<int32_t>(), L.dst.as<int32_t>(),
+                                                        L.rev.as<int32_t>());
+            PG_HIP(hipGetLastError());
+        }
     } else {
         fill_u64(L.seg.as<uint64_t>(), 1, 0, s);
     }

@@ -149,6 +149,7 @@ struct MotifL1 {
     DevBuf seg;              // int64[n+1]: edges of vertex u are seg[u]..seg[u+1]-1
     DevBuf src;              // int32[n_edges] = u
     DevBuf dst;              // int32[n_edges] = v (> u), ascending within u
+    DevBuf rev;              // int32[n_edges]: place after u in v's row, from the row's start
     // dense adjacency rows of high-degree vertices (membership in O(1))
     bool hubs_built = false;
     int64_t n_hubs = 0, hub_words = 0;

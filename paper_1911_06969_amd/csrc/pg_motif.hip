@@ -95,6 +95,7 @@ struct MotifArgs {
     const int64_t* l1_seg;
     const int32_t* l1_src;
     const int32_t* l1_dst;
+    const int32_t* l1_rev;      // first place in l1_dst's row past l1_src (row-relative)
     int64_t x_lo, x_hi;         // L1 entries extended (count / write / last3)
     uint32_t* count;            // ML1_COUNT: L2 children per L1 entry (indexed by entry)
     const uint64_t* start;      // ML1_WRITE: children of entry x at start[x] - start_base
@@ -721,10 +722,14 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
             __syncthreads();   // every wave is done with the previous item's children
             if (threadIdx.x == 0) s_grab = 0;
             if (v0 != mv0 || v1 != mv1) {
-                const int64_t r0 = uniform64(A.rp[v0]), r1 = uniform64(A.rp[v0 + 1]);
+                // L1 entries are the rows' upper halves in order: A0 above v0
+                // starts where v0's entries begin to count, and v1 sits at the
+                // entry's rank among them; v0's place in v1's row is stored
+                const int64_t s0 = uniform64(A.l1_seg[v0]), s0e = uniform64(A.l1_seg[v0 + 1]);
+                const int64_t r1 = uniform64(A.rp[v0 + 1]);
                 const int64_t q0 = uniform64(A.rp[v1]), q1 = uniform64(A.rp[v1 + 1]);
-                const int64_t a0b = uniform64(upper_bound(col, r0, r1, v0));
-                const int64_t a1b = uniform64(upper_bound(col, q0, q1, v0));
+                const int64_t a0b = r1 - (s0e - s0);
+                const int64_t a1b = q0 + uniform(A.l1_rev[p]);
                 if (v0 != mv0) {
                     for (int64_t t = m0b + threadIdx.x; t < m0e; t += MM_THREADS) map[(uint32_t)col[t] >> 4] = 0u;
                     for (int64_t t = m1b + threadIdx.x; t < m1e; t += MM_THREADS) map[(uint32_t)col[t] >> 4] = 0u;
@@ -781,7 +786,7 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                 m1b = a1b;
                 m1e = q1;
                 nc = (int32_t)total;
-                mna = (int32_t)(r1 - uniform64(upper_bound(col, a0b, r1, v1)));
+                mna = (int32_t)(s0e - p - 1);   // A0's elements above v1
             }
             __syncthreads();   // the counter is reset (and the marks are in place)
             const int32_t xend = min(xa + MM_CHILDREN, s);
@@ -1212,6 +1217,7 @@ static MotifArgs base_args(const MotifView& V) {
     A.l1_seg = V.ml1->seg.as<int64_t>();
     A.l1_src = V.ml1->src.as<int32_t>();
     A.l1_dst = V.ml1->dst.as<int32_t>();
+    A.l1_rev = V.ml1->rev.as<int32_t>();
     A.hub_id = V.ml1->hub_id.as<int32_t>();
     A.hub_bits = V.ml1->hub_bits.as<uint32_t>();
     A.hub_words = V.ml1->hub_words;
