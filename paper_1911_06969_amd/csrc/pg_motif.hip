@@ -100,6 +100,10 @@ struct MotifArgs {
     uint32_t* count;            // ML1_COUNT: L2 children per L1 entry (indexed by entry)
     const uint64_t* start;      // ML1_WRITE: children of entry x at start[x] - start_base
     uint64_t start_base;
+    // ML1_WRITE: entries with at least this many children go to the map
+    // kernel, which tells from its map whether a child of A0 is adjacent to
+    // v1, so their codes are not computed here
+    uint64_t heavy_min;
     int32_t* out_vid;
     uint8_t* out_code;
     // last level of k = 4: segment p (an L1 entry) owns L2 entries
@@ -161,7 +165,7 @@ struct L1Lds {
     int32_t d1[MO_WAVES][WAVE];     // |A1 above v0|
     int32_t v1[MO_WAVES][WAVE];
     int32_t na[MO_WAVES][WAVE];     // |A0 above v1|
-    int32_t opt[MO_WAVES][WAVE];    // COUNT/LAST3: 0 iterate A0', 1 iterate A1'
+    int32_t opt[MO_WAVES][WAVE];    // COUNT/LAST3: 0 iterate A0', 1 iterate A1'; WRITE: 1 no codes (map kernel)
     int32_t hb1[MO_WAVES][WAVE];    // dense row of v1, or -1
     uint32_t c_all[MO_WAVES][WAVE];
     uint32_t c_hi[MO_WAVES][WAVE];
@@ -188,6 +192,7 @@ __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, i
             int opt = 0;
             if (MODE == ML1_WRITE) {
                 work = (uint32_t)(na + d1p);
+                opt = (A.start[b + x + 1] - A.start[b + x] >= A.heavy_min) ? 1 : 0;
             } else {
                 // iterate A0' probing A1, or A1' probing A0: the cheaper total
                 const int64_t c0 = (int64_t)d0p * probe_cost(hb1 >= 0, (int32_t)(q1 - q0));
@@ -258,8 +263,10 @@ __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, i
                     const int32_t hb1 = L.hb1[w][xi];
                     if ((int32_t)j < na) {
                         u = A0[d0 - na + (int32_t)j];
-                        bool a12;
-                        if (hb1 >= 0) {
+                        bool a12 = false;
+                        if (L.opt[w][xi]) {
+                            // the map kernel finds u ~ v1 in its map
+                        } else if (hb1 >= 0) {
                             a12 = bit_has(A.hub_bits + (int64_t)hb1 * A.hub_words, u);
                         } else {
                             const int64_t q0 = A.rp[v1], q1 = A.rp[v1 + 1];
@@ -804,7 +811,9 @@ __global__ __launch_bounds__(MM_THREADS) void k_motif_last4_map(MotifArgs A, int
                 int32_t I0[2] = {0, 0}, I1[2] = {0, 0}, I01[2] = {0, 0};
                 if (valid) {
                     v2 = A.vid2[b + x];
-                    code = A.code2[b + x];
+                    // the first mna children are A0's (code bit 0), and v2 ~ v1
+                    // is bit 1 of v2's pair in the map; the others are A1's only
+                    code = x < mna ? (1 | (int32_t)(map_bits(map, v2) & 2u)) : 2;
                     const int64_t s0 = A.rp[v2];
                     s1 = A.rp[v2 + 1];
                     lo2 = upper_bound(col, s0, s1, v0);
@@ -1218,6 +1227,7 @@ static MotifArgs base_args(const MotifView& V) {
     A.l1_src = V.ml1->src.as<int32_t>();
     A.l1_dst = V.ml1->dst.as<int32_t>();
     A.l1_rev = V.ml1->rev.as<int32_t>();
+    A.heavy_min = UINT64_MAX;
     A.hub_id = V.ml1->hub_id.as<int32_t>();
     A.hub_bits = V.ml1->hub_bits.as<uint32_t>();
     A.hub_words = V.ml1->hub_words;
@@ -1481,6 +1491,7 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
             W.start_base = hs[j];
             W.out_vid = vid2;
             W.out_code = code2;
+            if (k == 4 && map.logv > 0) W.heavy_min = (uint64_t)MM_HEAVY;
             const int64_t v_lo = hv[j];
             const int64_t v_hi = (j + 1 == nb) ? g->n : std::min<int64_t>(g->n, hv[j + 1] + 1);
             launch_l1<ML1_WRITE>(R, W, v_lo, v_hi, "motif_write", (double)(hs[j + 1] - hs[j]));
@@ -1527,10 +1538,11 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
         // algorithmic bytes of the fused last level.  Per-wave kernel: per
         // input embedding the SoA entry (5 B), the three row-pointer pairs
         // (48 B) and one 4-byte probe per intersection item.  Map kernel: per
-        // input embedding the SoA entry and v2's row-pointer pair (21 B) and
-        // 4 B per candidate of its list; 4 B per list element marked.
+        // input embedding its vertex and v2's row-pointer pair (20 B: the code
+        // comes from the map) and 4 B per candidate of its list; 4 B per list
+        // element marked.
         ProfScope ps("motif_last_work", s, 53.0 * (double)h[7] + 4.0 * (double)h[6]);
-        ProfScope pm("motif_last_map_work", s, 21.0 * (double)h[10] + 4.0 * (double)(h[9] + h[11]));
+        ProfScope pm("motif_last_map_work", s, 20.0 * (double)h[10] + 4.0 * (double)(h[9] + h[11]));
     }
     if (prof_on() && k == 5) {
         // k = 5: per level-2 entry its SoA entry and a row-pointer pair
