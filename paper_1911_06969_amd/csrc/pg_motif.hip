@@ -43,6 +43,7 @@ constexpr int MO_THREADS = 128;
 constexpr int MO_WAVES = MO_THREADS / WAVE;
 constexpr int MO_STAGE = 512;     // adjacency lists up to this long are staged in LDS
 constexpr int MO_CMAX = 512;      // common-neighbour lists up to this long live in LDS
+constexpr int MO_FLAT = 1024;     // children streaming fewer candidates share wave steps
 constexpr int MO5_WAVES_PER_CU = 32;   // k = 5 last level: at most this many waves per CU (latency-bound lanes)
 
 enum { ML1_COUNT = 0, ML1_WRITE = 1, ML1_LAST3 = 2 };
@@ -420,7 +421,82 @@ __device__ __forceinline__ void motif_last4_segment(const MotifArgs& A, L4Lds& L
         }
         uint32_t cnt[6] = {0, 0, 0, 0, 0, 0};   // lane x: its child's counters
         const int nx = min(WAVE, s - xc);
+        // Children that stream their own list and have fewer than MO_FLAT
+        // candidates: their lists are laid end to end and the wave takes 64
+        // candidates a step, so several short children share a step.  A
+        // lane finds its child in the prefix of the lengths; a child's lanes
+        // are contiguous, and the last of them adds the child's counts
+        // (ballot popcounts over its lanes, below v2 | above v2 << 16).  The
+        // per-wave child staging area holds the prefix, list starts, v2 and
+        // counts until they are read back.
+        const bool flat = x < s && opt == 0 && (s1 - lo2) < MO_FLAT;
+        {
+            uint32_t* fpre = reinterpret_cast<uint32_t*>(S2);
+            int64_t* flo = reinterpret_cast<int64_t*>(fpre + WAVE);
+            int32_t* fv2 = reinterpret_cast<int32_t*>(flo + WAVE);
+            uint32_t* fcc = reinterpret_cast<uint32_t*>(fv2 + WAVE);   // [3][WAVE]
+            const uint32_t my = flat ? (uint32_t)(s1 - lo2) : 0u;
+            const uint32_t inc = wave_incl_scan(my);
+            const uint32_t total = bcast(inc, WAVE - 1);
+            wave_sync();   // the previous item's use of the staging area is over
+            fpre[lane()] = inc - my;
+            flo[lane()] = lo2;
+            fv2[lane()] = v2;
+            fcc[lane()] = 0;
+            fcc[WAVE + lane()] = 0;
+            fcc[2 * WAVE + lane()] = 0;
+            wave_sync();
+            for (uint32_t t0 = 0; t0 < total; t0 += WAVE) {
+                const uint32_t t = t0 + lane();
+                const bool valid = t < total;
+                // the child of candidate t: the last lane whose prefix is <= t
+                int xi = 0;
+                {
+                    int n_i = nx;
+                    while (n_i > 1) {
+                        const int half = n_i >> 1;
+                        if (fpre[xi + half] <= t) xi += half;
+                        n_i -= half;
+                    }
+                }
+                int32_t u = 0, cv = 0;
+                if (valid) {
+                    u = A.col[flo[xi] + (int64_t)(t - fpre[xi])];
+                    cv = fv2[xi];
+                }
+                const bool in0 = valid && adj_has_u(h0, A0, d0, u);
+                const bool in1 = valid && adj_has_u(h1, A1, d1, u);
+                const bool hi = u > cv;
+                const int key = valid ? xi : WAVE;
+                const int prev = __shfl_up(key, 1, WAVE);
+                const bool head = lane() == 0 || prev != key;
+                const uint64_t H = ballot(head);
+                const uint64_t le = lanemask_lt() | (1ull << lane());
+                const int hd = 63 - __clzll(H & le);
+                const uint64_t grp = le & ~((1ull << hd) - 1ull);
+                const bool last = lane() == WAVE - 1 || ((H >> (lane() + 1)) & 1ull);
+                const uint64_t B0l = ballot(in0 && !hi), B0h = ballot(in0 && hi);
+                const uint64_t B1l = ballot(in1 && !hi), B1h = ballot(in1 && hi);
+                const uint64_t B2l = ballot(in0 && in1 && !hi), B2h = ballot(in0 && in1 && hi);
+                if (valid && last) {
+                    fcc[xi] += (uint32_t)popc64(B0l & grp) | ((uint32_t)popc64(B0h & grp) << 16);
+                    fcc[WAVE + xi] += (uint32_t)popc64(B1l & grp) | ((uint32_t)popc64(B1h & grp) << 16);
+                    fcc[2 * WAVE + xi] += (uint32_t)popc64(B2l & grp) | ((uint32_t)popc64(B2h & grp) << 16);
+                }
+                wave_sync();
+            }
+            if (flat) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const uint32_t v = fcc[c * WAVE + lane()];
+                    cnt[2 * c] = v & 0xffffu;
+                    cnt[2 * c + 1] = v >> 16;
+                }
+            }
+            wave_sync();   // read back before the staging area is reused
+        }
         for (int xi = 0; xi < nx; ++xi) {
+            if (ballot(flat) >> xi & 1ull) continue;   // counted above
             const int32_t cv2 = readlane(v2, xi);
             uint32_t c6[6] = {0, 0, 0, 0, 0, 0};
             if (readlane(opt, xi) == 0) {
