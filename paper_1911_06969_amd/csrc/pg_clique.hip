@@ -997,11 +997,19 @@ struct MaskArgs {
     int32_t* out_idx;
     uint16_t* out_pos;
     unsigned long long* stats;
+    // COUNT, when the children's level is the last: tally the last level's
+    // work (its parents are these children) into stats[8..11]
+    int last_work;
 };
 
 template <int MODE>
 __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
     uint64_t acc = 0;
+    // COUNT with last_work: last-level parents, words of their sets, entries,
+    // row words the last level reads (each of a parent's entries reads the
+    // words of the pairs where the parent's set is non-empty)
+    uint32_t lw_par = 0, lw_set = 0, lw_ent = 0;
+    uint64_t lw_row = 0;
     QueueCursor cur = queue_start();
     int64_t it_end = 0;
     for (int64_t it = queue_next(A.Q, cur, it_end); it >= 0; it = queue_next(A.Q, cur, it_end)) {
@@ -1062,7 +1070,7 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
                 // only the words where the parent's set is non-empty (a
                 // wave-uniform test) are read, in 16-byte pairs
                 uint64_t words[MODE == MODE_WRITE ? BM_W : 1];
-                uint32_t cnt = 0;
+                uint32_t cnt = 0, nzw = 0;
 #pragma unroll
                 for (int q = 0; q < BM_W; q += 2) {
                     const uint64_t s0 = q < W ? s[q] : 0ull, s1 = q + 1 < W ? s[q + 1] : 0ull;
@@ -1077,12 +1085,21 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
                         }
                     }
                     cnt += (uint32_t)(__popcll(w0) + __popcll(w1));
+                    if constexpr (MODE == MODE_COUNT) nzw += ((w0 | w1) != 0ull) ? ((q + 1 < W) ? 2u : 1u) : 0u;
                     if constexpr (MODE == MODE_WRITE) {
                         words[q] = w0;
                         words[q + 1] = w1;
                     }
                 }
-                if (MODE == MODE_COUNT && valid) A.count[x] = cnt;
+                if (MODE == MODE_COUNT && valid) {
+                    A.count[x] = cnt;
+                    if (A.last_work && cnt) {
+                        lw_par += 1;
+                        lw_set += (uint32_t)W * (uint32_t)A.lev;   // the child's row and its ancestors'
+                        lw_ent += cnt;
+                        lw_row += (uint64_t)cnt * nzw;
+                    }
+                }
                 if (MODE == MODE_LAST) acc += cnt;
                 if (MODE == MODE_WRITE) {
                     // children of the wave's entries, entry by entry, each
@@ -1114,6 +1131,16 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
     if (MODE == MODE_LAST) {
         acc = wave_sum_u64(acc);
         if (lane() == 0 && acc) atomicAdd(&A.stats[0], (unsigned long long)acc);
+    }
+    if (MODE == MODE_COUNT && A.last_work) {
+        const uint64_t t_par = wave_sum_u64(lw_par), t_set = wave_sum_u64(lw_set);
+        const uint64_t t_ent = wave_sum_u64(lw_ent), t_row = wave_sum_u64(lw_row);
+        if (lane() == 0 && t_par) {
+            atomicAdd(&A.stats[8], (unsigned long long)t_par);
+            atomicAdd(&A.stats[9], (unsigned long long)t_set);
+            atomicAdd(&A.stats[10], (unsigned long long)t_ent);
+            atomicAdd(&A.stats[11], (unsigned long long)t_row);
+        }
     }
 }
 
@@ -1358,7 +1385,9 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
     uint32_t* cnt = push<uint32_t>(ar, m);
     uint64_t* start = push<uint64_t>(ar, m + 1);
     A.count = cnt;
+    A.last_work = (lev + 1 == R.k - 2) ? 1 : 0;
     launch_mask<MODE_COUNT>(R, A, p_lo, p_hi - p_lo, "clique_count_l", (double)m);
+    A.last_work = 0;
     scan_u32(cnt, m, start, ar, R.s);
     const uint64_t total = read_u64(start + m, R.s);
     if (total == 0) {
@@ -1675,10 +1704,10 @@ uint64_t count_cliques(pg_graph* g, int k) {
     R.waves = grid_waves(32);
     R.blocks = (int)(R.waves / CQ_WAVES);
     R.long_segments = g->dag.max_out > CQ_ROUND;
-    uint64_t* small = push<uint64_t>(ar, 8 + Q_WORDS);
+    uint64_t* small = push<uint64_t>(ar, 12 + Q_WORDS);
     R.stats = reinterpret_cast<unsigned long long*>(small);
-    R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
-    fill_u64(small, 8, 0, s);
+    R.qctr = reinterpret_cast<unsigned long long*>(small + 12);
+    fill_u64(small, 12, 0, s);
     const bool masks = k >= 3 && !g->force_generic;
     uint64_t n2 = 0;
     if (masks) {
@@ -1705,7 +1734,7 @@ uint64_t count_cliques(pg_graph* g, int k) {
         // level L1: entries = DAG edges, parents = vertices (segment = out-list)
         extend_level(R, 1, g->dag.rp.as<int64_t>(), 0, 0, g->n, g->dag.col.as<int32_t>(), 0, g->dag.n_edges);
     }
-    uint64_t st[5] = {0, 0, 0, 0, 0};
+    uint64_t st[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     PG_HIP(hipMemcpyAsync(st, small, sizeof(st), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
     if (masks) st[1] = n2;
@@ -1726,6 +1755,16 @@ uint64_t count_cliques(pg_graph* g, int k) {
             if (k >= 4) ProfScope pw("clique_write_work", s, 16.0 * E + (double)st[4] + 6.0 * (double)st[1]);
             if (k == 4)   // last level: 6 B SoA + 8 B info per entry, 16 B per pair of row words
                 ProfScope pl("clique_last_work", s, 14.0 * (double)st[1] + 16.0 * (double)st[2]);
+            if (k >= 5) {
+                // last mask level: per parent its level-1 info (8 B), its
+                // ancestry (idx and pos, 6 B per level) and the words of its
+                // set (8 B each); per entry its pos (2 B) and the row words
+                // read (8 B each)
+                const double na = (double)(k - 4);
+                ProfScope pl("clique_last_work", s,
+                             (8.0 + 6.0 * na) * (double)st[8] + 8.0 * (double)st[9] + 2.0 * (double)st[10] +
+                                 8.0 * (double)st[11]);
+            }
         }
     }
     // k = 3 on the mask path: the light roots' triangles are the level-2
@@ -1769,10 +1808,10 @@ uint64_t list_cliques(pg_graph* g, int k, int32_t* out, uint64_t capacity) {
     R.waves = grid_waves(32);
     R.blocks = (int)(R.waves / CQ_WAVES);
     R.long_segments = g->dag.max_out > CQ_ROUND;
-    uint64_t* small = push<uint64_t>(ar, 8 + Q_WORDS);
+    uint64_t* small = push<uint64_t>(ar, 12 + Q_WORDS);
     R.stats = reinterpret_cast<unsigned long long*>(small);
-    R.qctr = reinterpret_cast<unsigned long long*>(small + 8);
-    fill_u64(small, 8, 0, s);
+    R.qctr = reinterpret_cast<unsigned long long*>(small + 12);
+    fill_u64(small, 12, 0, s);
     ListOut O;
     O.host = out;
     O.capacity = out ? capacity : 0;
