@@ -487,19 +487,27 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t* __
                                                               int shift, int64_t n_tiles,
                                                               const uint64_t* __restrict__ offs,
                                                               uint64_t* __restrict__ out) {
+    constexpr int KPL = RS_PER_WAVE / WAVE;   // keys per lane, held in registers
     // per wave and digit: its count, then (in place) its next place
     __shared__ uint32_t run[RS_WAVES][256];
     __shared__ uint32_t dstart[256];
+    __shared__ uint64_t doff[256];   // the digit's first place in the output, for this tile
     __shared__ uint64_t sk[RS_TILE];
     const int w = threadIdx.x / WAVE;
     for (int d = lane(); d < 256; d += WAVE) run[w][d] = 0;
-    __syncthreads();
+    if (threadIdx.x < 256) doff[threadIdx.x] = offs[(int64_t)threadIdx.x * n_tiles + blockIdx.x];
     const int64_t tbase = blockIdx.x * RS_TILE;
     const int64_t wbase = tbase + (int64_t)w * RS_PER_WAVE;
-    for (int it = 0; it < RS_PER_WAVE; it += WAVE) {
-        int64_t j = wbase + it + lane();
-        if (j < m) atomicAdd(&run[w][(keys[j] >> shift) & 255u], 1u);
+    uint64_t kk[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const int64_t j = wbase + i * WAVE + lane();
+        kk[i] = j < m ? keys[j] : 0ull;
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KPL; ++i)
+        if (wbase + i * WAVE + lane() < m) atomicAdd(&run[w][(kk[i] >> shift) & 255u], 1u);
     __syncthreads();
     // dstart[d]: first place of digit d in the tile's digit order (one
     // thread per digit, the 256 totals scanned by the first wave's lanes)
@@ -531,22 +539,22 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t* __
         }
     }
     __syncthreads();
-    for (int it = 0; it < RS_PER_WAVE; it += WAVE) {
-        int64_t j = wbase + it + lane();
-        bool valid = j < m;
-        uint64_t k = valid ? keys[j] : 0;
-        uint32_t d = (uint32_t)((k >> shift) & 255u);
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+        const bool valid = wbase + i * WAVE + lane() < m;
+        const uint64_t k = kk[i];
+        const uint32_t d = (uint32_t)((k >> shift) & 255u);
         uint64_t peers = ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            uint64_t mb = ballot(((d >> b) & 1u) != 0);
+            const uint64_t mb = ballot(((d >> b) & 1u) != 0);
             peers &= ((d >> b) & 1u) ? mb : ~mb;
         }
-        uint32_t before = (uint32_t)popc64(peers & lanemask_lt());
-        uint32_t base = valid ? run[w][d] : 0;
+        const uint32_t before = (uint32_t)popc64(peers & lanemask_lt());
+        const uint32_t base = valid ? run[w][d] : 0;
         if (valid) sk[base + before] = k;
         // the highest lane of each digit group advances the running count
-        bool last = valid && ((peers >> lane()) == 1ull);
+        const bool last = valid && ((peers >> lane()) == 1ull);
         if (last) run[w][d] = base + before + 1;
         __builtin_amdgcn_wave_barrier();
     }
@@ -556,7 +564,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t* __
     for (int p = threadIdx.x; p < n; p += RS_THREADS) {
         const uint64_t k = sk[p];
         const uint32_t d = (uint32_t)((k >> shift) & 255u);
-        out[offs[(int64_t)d * n_tiles + blockIdx.x] + (uint32_t)(p - (int)dstart[d])] = k;
+        out[doff[d] + (uint32_t)(p - (int)dstart[d])] = k;
     }
 }
 
