@@ -820,66 +820,157 @@ __global__ void k_fsm_l2(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, u
 // (children per parent, then (e1, e2, e3, pattern) at the parent's offset).
 enum { L3_HIST = 0, L3_BITS = 1, L3_COUNT = 2, L3_WRITE = 3, L3_KEYS = 4 };
 
+// A wave takes 64 parents (frequent wedges e1, e2 with shared vertex s,
+// other ends o of e1 and t of e2) a round and lays their candidate edges
+// end to end: the lists of s, o and t.  Each step the 64 lanes take 64
+// consecutive candidates, so a list is read by neighbouring lanes, and a
+// lane finds its parent in the prefix of the parents' list lengths.  A
+// candidate edge (x, w) extends the wedge when the canonical order admits
+// it: at s a new leaf (a star) and at o (a triangle or a path) only edges
+// after e2, at t (a path) edges after e1.  A child's place among its
+// parent's children is the children the parent had before this step plus
+// those of its lanes below it in the step (a parent's lanes are
+// contiguous), so the children of a parent are written side by side.
+constexpr int F3_THREADS = 256;
+constexpr int F3_WAVES = F3_THREADS / WAVE;
+
+struct F3Lds {
+    uint32_t pre[F3_WAVES][WAVE];   // first candidate of each parent
+    uint32_t ns[F3_WAVES][WAVE], no[F3_WAVES][WAVE];
+    uint32_t cnt[F3_WAVES][WAVE];   // children found so far
+    int32_t s[F3_WAVES][WAVE], o[F3_WAVES][WAVE], t[F3_WAVES][WAVE];
+    int32_t e1[F3_WAVES][WAVE], e2[F3_WAVES][WAVE];
+    int64_t bs[F3_WAVES][WAVE], bo[F3_WAVES][WAVE], bt[F3_WAVES][WAVE];
+};
+
 template <int MODE>
-__global__ void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s, const int32_t* __restrict__ e2s,
-                         uint32_t* __restrict__ counts, Bits Bt, unsigned long long* __restrict__ n_emb,
-                         const uint64_t* __restrict__ start, int32_t* __restrict__ o1, int32_t* __restrict__ o2,
-                         int32_t* __restrict__ o3, int32_t* __restrict__ opid, uint32_t* __restrict__ nch,
-                         uint64_t* __restrict__ keys) {
+__global__ __launch_bounds__(F3_THREADS) void k_fsm_l3(FsmCtx C, int64_t m, const int32_t* __restrict__ e1s,
+                                                      const int32_t* __restrict__ e2s, uint32_t* __restrict__ counts,
+                                                      Bits Bt, unsigned long long* __restrict__ n_emb,
+                                                      const uint64_t* __restrict__ start, int32_t* __restrict__ o1,
+                                                      int32_t* __restrict__ o2, int32_t* __restrict__ o3,
+                                                      int32_t* __restrict__ opid, uint32_t* __restrict__ nch,
+                                                      uint64_t* __restrict__ keys) {
+    __shared__ F3Lds L;
+    const int w = threadIdx.x / WAVE;
     uint64_t local = 0, scanned = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t e1 = e1s[i], e2 = e2s[i];
-        const int32_t a = C.esrc[e1], b = C.edst[e1], c = C.esrc[e2], d = C.edst[e2];
-        // shared vertex s; o = other end of e1; t = other end of e2
-        const int32_t s = (a == c || a == d) ? a : b;
-        const int32_t o = (s == a) ? b : a;
-        const int32_t t = (s == c) ? d : c;
-        if (MODE == L3_HIST) scanned += (uint64_t)(C.rp[s + 1] - C.rp[s] + C.rp[o + 1] - C.rp[o] + C.rp[t + 1] - C.rp[t]);
-        uint64_t pos = (MODE == L3_WRITE || MODE == L3_KEYS) ? start[i] : 0;
-        uint32_t nchild = 0;
-        auto emit = [&](int32_t e3, const Emb& Em) {
-            ++local;
-            if (MODE == L3_HIST) atomicAdd(&counts[Em.pid], 1u);
-            if (MODE == L3_BITS) set_bits(Bt, Em);
-            if (MODE == L3_KEYS) {
-                bit_keys(Bt, Em, keys + (pos << 2));
-                ++pos;
+    const int64_t stride = (int64_t)gridDim.x * F3_WAVES * WAVE;
+    for (int64_t r0 = ((int64_t)blockIdx.x * F3_WAVES + w) * WAVE; r0 < m; r0 += stride) {
+        const int64_t i = r0 + lane();
+        uint32_t tot = 0;
+        {
+            int32_t e1 = 0, e2 = 0, sv = 0, ov = 0, tv = 0;
+            int64_t bs = 0, bo = 0, bt = 0;
+            uint32_t ns = 0, no = 0, nt = 0;
+            if (i < m) {
+                e1 = e1s[i];
+                e2 = e2s[i];
+                const int32_t a = C.esrc[e1], b = C.edst[e1], c = C.esrc[e2], d = C.edst[e2];
+                sv = (a == c || a == d) ? a : b;
+                ov = (sv == a) ? b : a;
+                tv = (sv == c) ? d : c;
+                bs = C.rp[sv];
+                ns = (uint32_t)(C.rp[sv + 1] - bs);
+                bo = C.rp[ov];
+                no = (uint32_t)(C.rp[ov + 1] - bo);
+                bt = C.rp[tv];
+                nt = (uint32_t)(C.rp[tv + 1] - bt);
             }
-            if (MODE == L3_WRITE) {
-                o1[pos] = e1;
-                o2[pos] = e2;
-                o3[pos] = e3;
-                opid[pos] = Em.pid;
-                ++pos;
+            tot = ns + no + nt;
+            const uint32_t inc = wave_incl_scan(tot);
+            L.pre[w][lane()] = inc - tot;
+            L.ns[w][lane()] = ns;
+            L.no[w][lane()] = no;
+            L.cnt[w][lane()] = 0;
+            L.s[w][lane()] = sv;
+            L.o[w][lane()] = ov;
+            L.t[w][lane()] = tv;
+            L.e1[w][lane()] = e1;
+            L.e2[w][lane()] = e2;
+            L.bs[w][lane()] = bs;
+            L.bo[w][lane()] = bo;
+            L.bt[w][lane()] = bt;
+        }
+        if (MODE == L3_HIST) scanned += tot;
+        const uint32_t total = bcast(wave_incl_scan(tot), WAVE - 1);
+        const int np = (int)min64(WAVE, m - r0);
+        wave_sync();
+        for (uint32_t c0 = 0; c0 < total; c0 += WAVE) {
+            const uint32_t cidx = c0 + lane();
+            const bool valid = cidx < total;
+            // the parent of candidate cidx: the last lane whose prefix is <= cidx
+            int xi = 0;
+            {
+                int n_i = np;
+                while (n_i > 1) {
+                    const int half = n_i >> 1;
+                    if (L.pre[w][xi + half] <= cidx) xi += half;
+                    n_i -= half;
+                }
             }
-            ++nchild;
-        };
-        // edges at s: new leaf w (adjacent to e1 -> e > e2): star
-        for (int64_t j = C.rp[s]; j < C.rp[s + 1]; ++j) {
-            const int32_t w = C.col[j];
-            if (w == o || w == t) continue;
-            if (C.eid[j] <= e2) continue;
-            if (MODE == L3_COUNT) { ++nchild; continue; }
-            emit(C.eid[j], classify_star(C, s, o, t, w));
+            bool child = false;
+            Emb Em;
+            Em.pid = 0;
+            Em.nv = 0;
+            int32_t e3 = 0;
+            if (valid) {
+                const uint32_t off = cidx - L.pre[w][xi];
+                const uint32_t ns = L.ns[w][xi], no = L.no[w][xi];
+                const int32_t sv = L.s[w][xi], ov = L.o[w][xi], tv = L.t[w][xi];
+                if (off < ns) {
+                    const int64_t j = L.bs[w][xi] + off;
+                    const int32_t x = C.col[j];
+                    e3 = C.eid[j];
+                    child = x != ov && x != tv && e3 > L.e2[w][xi];
+                    if (child && MODE != L3_COUNT) Em = classify_star(C, sv, ov, tv, x);
+                } else if (off < ns + no) {
+                    const int64_t j = L.bo[w][xi] + (off - ns);
+                    const int32_t x = C.col[j];
+                    e3 = C.eid[j];
+                    child = x != sv && e3 > L.e2[w][xi];
+                    if (child && MODE != L3_COUNT)
+                        Em = (x == tv) ? classify_triangle(C, sv, ov, tv) : classify_path(C, x, ov, sv, tv);
+                } else {
+                    const int64_t j = L.bt[w][xi] + (off - ns - no);
+                    const int32_t x = C.col[j];
+                    e3 = C.eid[j];
+                    child = x != sv && x != ov && e3 > L.e1[w][xi];
+                    if (child && MODE != L3_COUNT) Em = classify_path(C, ov, sv, tv, x);
+                }
+            }
+            // the child's place among its parent's children
+            const uint64_t V = ballot(child);
+            const int key = valid ? xi : WAVE;
+            const int prev = __shfl_up(key, 1, WAVE);
+            const bool head = lane() == 0 || prev != key;
+            const uint64_t H = ballot(head);
+            const uint64_t lt = lanemask_lt();
+            const int hd = 63 - __clzll(H & (lt | (1ull << lane())));
+            const uint64_t seg_lt = lt & ~((1ull << hd) - 1ull);
+            const uint32_t before = L.cnt[w][xi] + (uint32_t)popc64(V & seg_lt);
+            const bool last = lane() == WAVE - 1 || ((H >> (lane() + 1)) & 1ull);
+            if (child) {
+                ++local;
+                if (MODE == L3_HIST) atomicAdd(&counts[Em.pid], 1u);
+                if (MODE == L3_BITS) set_bits(Bt, Em);
+                if (MODE == L3_KEYS) bit_keys(Bt, Em, keys + ((start[r0 + xi] + before) << 2));
+                if (MODE == L3_WRITE) {
+                    const uint64_t pos = start[r0 + xi] + before;
+                    o1[pos] = L.e1[w][xi];
+                    o2[pos] = L.e2[w][xi];
+                    o3[pos] = e3;
+                    opid[pos] = Em.pid;
+                }
+            }
+            wave_sync();   // every lane has read the counts before they move on
+            if (valid && last) L.cnt[w][xi] = before + (uint32_t)(child ? 1 : 0);
+            wave_sync();
         }
-        // edges at o (adjacent to e1 -> e > e2): closing edge (triangle) or path w-o-s-t
-        for (int64_t j = C.rp[o]; j < C.rp[o + 1]; ++j) {
-            const int32_t w = C.col[j];
-            if (w == s) continue;
-            if (C.eid[j] <= e2) continue;
-            if (MODE == L3_COUNT) { ++nchild; continue; }
-            emit(C.eid[j], (w == t) ? classify_triangle(C, s, o, t) : classify_path(C, w, o, s, t));
+        if (i < m) {
+            if (MODE == L3_COUNT) counts[i] = L.cnt[w][lane()];
+            if (MODE == L3_HIST && nch) nch[i] = L.cnt[w][lane()];
         }
-        // edges at t not touching e1 (only e > e1 needed): path o-s-t-w
-        for (int64_t j = C.rp[t]; j < C.rp[t + 1]; ++j) {
-            const int32_t w = C.col[j];
-            if (w == s || w == o) continue;
-            if (C.eid[j] <= e1) continue;
-            if (MODE == L3_COUNT) { ++nchild; continue; }
-            emit(C.eid[j], classify_path(C, o, s, t, w));
-        }
-        if (MODE == L3_COUNT) counts[i] = nchild;
-        if (MODE == L3_HIST && nch) nch[i] = nchild;
+        wave_sync();   // the round's LDS is read before the next round writes it
     }
     if (MODE == L3_HIST) {
         local = wave_sum_u64(local);
