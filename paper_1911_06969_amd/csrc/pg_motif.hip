@@ -210,6 +210,10 @@ __device__ __forceinline__ void motif_l1_segment(const MotifArgs& A, L1Lds& L, i
         }
         const uint32_t inc = wave_incl_scan(work);
         const uint32_t W = bcast(inc, WAVE - 1);
+        if (MODE == ML1_LAST3 && lane() == 0) {
+            acc[2] += W;                     // list elements iterated
+            acc[3] += (uint64_t)(x1 - xc);   // level-1 entries
+        }
         L.pre[w][lane()] = inc - work;
         L.c_all[w][lane()] = 0;
         L.c_hi[w][lane()] = 0;
@@ -337,6 +341,7 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_l1(MotifArgs A) {
             if (xa >= xb) continue;
             const int64_t r0 = A.rp[v0], r1 = A.rp[v0 + 1];
             const int32_t d0 = (int32_t)(r1 - r0);
+            if (MODE == ML1_LAST3 && lane() == 0) acc[4] += (uint64_t)d0 + 4;   // v0's row pointers and list
             if (d0 <= MO_STAGE) {
                 for (int i = lane(); i < d0; i += WAVE) L.A0[w][i] = A.col[r0 + i];
                 wave_sync();
@@ -353,6 +358,10 @@ __global__ __launch_bounds__(MO_THREADS) void k_motif_l1(MotifArgs A) {
         if (lane() == 0) {
             if (wd) atomicAdd(&A.out[0], (unsigned long long)wd);
             if (tr) atomicAdd(&A.out[1], (unsigned long long)tr);
+            // work (lane 0 holds it): elements iterated, entries, 4-byte words of staging
+            if (acc[2]) atomicAdd(&A.out[12], (unsigned long long)acc[2]);
+            if (acc[3]) atomicAdd(&A.out[13], (unsigned long long)acc[3]);
+            if (acc[4]) atomicAdd(&A.out[14], (unsigned long long)acc[4]);
         }
     }
 }
@@ -1619,6 +1628,12 @@ void count_motifs(pg_graph* g, int k, uint64_t* counts) {
         // element marked.
         ProfScope ps("motif_last_work", s, 53.0 * (double)h[7] + 4.0 * (double)h[6]);
         ProfScope pm("motif_last_map_work", s, 20.0 * (double)h[10] + 4.0 * (double)(h[9] + h[11]));
+    }
+    if (prof_on() && k == 3) {
+        // fused level 2: per level-1 entry v1 and its row-pointer pair
+        // (20 B), 4 B per list element iterated (A0' probing A1 or A1'
+        // probing A0, the cheaper), and per item v0's row pointers and list
+        ProfScope ps("motif_last_work", s, 20.0 * (double)h[13] + 4.0 * (double)h[12] + 4.0 * (double)h[14]);
     }
     if (prof_on() && k == 5) {
         // k = 5: per level-2 entry its SoA entry and a row-pointer pair
