@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -18,6 +20,15 @@ std::string prof_list();
 int fsm_pattern_key(uint64_t index, int max_edges, int n_labels, int* shape, int32_t* labels5);
 
 static int g_live_objects = 0;
+
+// PG_TRACE_ARENA=1: report on stderr each time a call is rerun with a larger arena
+static bool trace_arena() {
+    static const bool on = [] {
+        const char* e = std::getenv("PG_TRACE_ARENA");
+        return e != nullptr && e[0] == '1';
+    }();
+    return on;
+}
 
 static void require_device() {
     static int have = -1;
@@ -51,10 +62,15 @@ static void run_with_arena(pg_graph* g, F&& body) {
                 if (g->arena.need > cap)
                     throw Error{PG_ENOMEM, "memory budget too small for the embedding levels (need " +
                                                std::to_string(g->arena.need) + " bytes)"};
-                // at least twice the last size: a call finds its needs one push
-                // at a time, and each retry runs it from the start
-                g->arena.want = std::min(std::max(g->arena.want, 2 * g->arena.buf.bytes),
+                // at least four times the last size and at least 64 MiB (within
+                // the budget): a call finds its needs one push at a time, and
+                // each retry runs it from the start
+                const size_t floor_bytes = std::min<size_t>(cap, size_t(64) << 20);
+                g->arena.want = std::min(std::max({g->arena.want, 4 * g->arena.buf.bytes, floor_bytes}),
                                          std::max(g->arena.need, cap));
+                if (trace_arena())
+                    std::fprintf(stderr, "[pangolin] call retried with an arena of %zu bytes (attempt %d)\n",
+                                 g->arena.want, attempt + 1);
                 g->arena.buf.release();
                 continue;
             }

@@ -1717,6 +1717,12 @@ uint64_t count_cliques(pg_graph* g, int k) {
         build_mask_plan(g);
         const MaskPlan& P = g->dag.plan;
         if (P.heavy_edges > 0) {
+            // the count pass below needs the mask rows and per-entry counts,
+            // infos and offsets: if the arena cannot hold them, rerun the call
+            // now rather than after the heavy roots' levels
+            const uint64_t E1 = (uint64_t)g->dag.n_edges;
+            const size_t light = 8 * std::max<uint64_t>((uint64_t)P.words, 1) + 20 * E1 + 8 + 4 * 256;
+            ar.ensure(light);
             const size_t mk = ar.mark();
             // k = 3, 4: wide rows in device memory when every heavy root
             // fits them and they fit the budget; otherwise the general kernels

@@ -1090,16 +1090,6 @@ __global__ void k_frequent(int64_t np, const int32_t* __restrict__ slot, const u
 
 // ------------------------------------------------------------------ host
 
-// Throws as a full arena push does unless `bytes` more fit, so that the
-// call is retried once with room for several large pushes that follow.
-static void arena_ensure(Arena& a, size_t bytes) {
-    if (a.top + bytes > a.buf.bytes) {
-        a.need = std::max(a.need, a.top + bytes);
-        a.want = std::max(a.want, a.need + a.need / 4);
-        throw Error{PG_ENOMEM, "arena"};
-    }
-}
-
 static unsigned grid1(int64_t items) {
     int64_t b = (items + 255) / 256;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)device_info().n_cu * 16));
@@ -1361,7 +1351,7 @@ void run_fsm(pg_graph* g, int max_edges, uint64_t min_support, uint64_t* support
                                           (uint64_t(64) << 20);
                     const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
                     if (g->fsm_bit_keys && n3 > 0 && need <= room) {
-                        arena_ensure(ar, need);
+                        ar.ensure(need);
                         const size_t mk = ar.mark();
                         const int64_t total_words = (int64_t)(Bt.s_hi - Bt.s_lo) * Bt.norb * Bt.words;
                         const int64_t nblk = (total_words + FB_WORDS - 1) / FB_WORDS;

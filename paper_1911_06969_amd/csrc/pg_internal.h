@@ -75,6 +75,9 @@ struct Arena {
     size_t need = 0;   // largest size a push of this call required
     void begin_call();
     void* push(size_t bytes);   // 256-byte aligned; throws PG_ENOMEM when full
+    // throws as push would if `bytes` more could not be pushed: a call checks
+    // up front for room it needs later, so a short arena reruns it early
+    void ensure(size_t bytes);
     size_t mark() const { return top; }
     void reset(size_t m) { top = m; }
     size_t avail() const { return buf.bytes > top ? buf.bytes - top : 0; }

@@ -78,14 +78,18 @@ void Arena::begin_call() {
     if (want > buf.bytes) buf.reserve(want);
 }
 
-void* Arena::push(size_t bytes) {
-    size_t b = (bytes + 255) & ~size_t(255);
-    if (top + b > buf.bytes) {
+void Arena::ensure(size_t bytes) {
+    if (top + bytes > buf.bytes) {
         // Remember the size this call needed; the caller retries after growth.
-        need = std::max(need, top + b);
+        need = std::max(need, top + bytes);
         want = std::max(want, need + need / 4);
         throw Error{PG_ENOMEM, "arena"};
     }
+}
+
+void* Arena::push(size_t bytes) {
+    size_t b = (bytes + 255) & ~size_t(255);
+    ensure(b);
     void* p = static_cast<char*>(buf.p) + top;
     top += b;
     high = std::max(high, top);

@@ -26,3 +26,5 @@ def golden(name):
 def say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+    # also past pytest's capture, so that a long test shows its progress
+    print(*a, file=sys.__stderr__, flush=True)
