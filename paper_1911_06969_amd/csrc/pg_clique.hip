@@ -984,7 +984,7 @@ struct MaskChain {
 struct MaskArgs {
     XcdQueue Q;                  // over parents: a parent has at most BM_MAXD children
     int64_t p_lo;                // parents (level lev-1 entries)
-    const uint64_t* seg;         // children of parent p: seg[p] - seg_base .. seg[p+1] - seg_base
+    const uint64_t* seg;         // COUNT, WRITE: children of parent p: seg[p] - seg_base .. seg[p+1] - seg_base
     uint64_t seg_base;
     int lev;                     // level of the children
     MaskChain ch;
@@ -997,17 +997,24 @@ struct MaskArgs {
     int32_t* out_idx;
     uint16_t* out_pos;
     unsigned long long* stats;
-    // COUNT, when the children's level is the last: tally the last level's
-    // work (its parents are these children) into stats[8..11]
-    int last_work;
 };
 
+__device__ __forceinline__ int32_t lanes_below(uint64_t m) {
+    return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// COUNT and WRITE take a parent's children from the stored level `lev`.
+// LAST never stores that level: a parent's children are the positions set
+// in its set (every position in it extends the parent to a clique of the
+// level), packed into LDS with ballots, and each adds the popcount of its
+// row AND the set, which counts its own children (the k-cliques).
 template <int MODE>
-__global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
+__global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_clique_mask_level(MaskArgs A) {
+    __shared__ uint16_t kids[MODE == MODE_LAST ? CQ_WAVES : 1][MODE == MODE_LAST ? BM_MAXD : 1];
     uint64_t acc = 0;
-    // COUNT with last_work: last-level parents, words of their sets, entries,
-    // row words the last level reads (each of a parent's entries reads the
-    // words of the pairs where the parent's set is non-empty)
+    // LAST: parents with children, words of their sets, children, and row
+    // words read (each child reads the words of the pairs where its
+    // parent's set is non-empty)
     uint32_t lw_par = 0, lw_set = 0, lw_ent = 0;
     uint64_t lw_row = 0;
     QueueCursor cur = queue_start();
@@ -1024,11 +1031,15 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
 #pragma unroll
         for (int q = 0; q < BM_W; ++q) sp[q] = 0ull;
         if (it + lane() < it_end) {
-            const int64_t b = (int64_t)(A.seg[p] - A.seg_base);
-            const int64_t e2 = (int64_t)(A.seg[p + 1] - A.seg_base);
-            // the parent's children within the launch's window [x_lo, x_hi)
-            px0 = max64(b, A.x_lo);
-            px1 = min64(e2, A.x_hi);
+            if constexpr (MODE == MODE_LAST) {
+                px1 = 1;   // decided by the set below
+            } else {
+                const int64_t b = (int64_t)(A.seg[p] - A.seg_base);
+                const int64_t e2 = (int64_t)(A.seg[p + 1] - A.seg_base);
+                // the parent's children within the launch's window [x_lo, x_hi)
+                px0 = max64(b, A.x_lo);
+                px1 = min64(e2, A.x_hi);
+            }
             if (px0 < px1) {
                 int32_t apos[PG_KMAX];
                 int na = 0;
@@ -1049,6 +1060,22 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
                         sp[q] = v;
                     }
                 }
+                if constexpr (MODE == MODE_LAST) {
+                    uint32_t nch = 0, nzw = 0;
+#pragma unroll
+                    for (int q = 0; q < BM_W; q += 2) {
+                        const uint64_t s0 = q < Wl ? sp[q] : 0ull, s1 = q + 1 < Wl ? sp[q + 1] : 0ull;
+                        nch += (uint32_t)(__popcll(s0) + __popcll(s1));
+                        nzw += ((s0 | s1) != 0ull) ? ((q + 1 < Wl) ? 2u : 1u) : 0u;
+                    }
+                    if (nch == 0) px1 = 0;
+                    else {
+                        lw_par += 1;
+                        lw_set += (uint32_t)Wl * (uint32_t)(A.lev - 1);   // the parent's rows
+                        lw_ent += nch;
+                        lw_row += (uint64_t)nch * nzw;
+                    }
+                }
             }
         }
         uint64_t todo_p = ballot(px0 < px1);
@@ -1060,17 +1087,35 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
             uint64_t s[BM_W];
 #pragma unroll
             for (int q = 0; q < BM_W; ++q) s[q] = q < W ? readlane64(sp[q], pi) : 0ull;
-            const int64_t x0 = (int64_t)readlane64((uint64_t)px0, pi);
-            const int64_t x1 = (int64_t)readlane64((uint64_t)px1, pi);
+            int64_t x0 = 0, x1 = 0;
+            uint16_t* kl = kids[MODE == MODE_LAST ? threadIdx.x / WAVE : 0];
+            if constexpr (MODE == MODE_LAST) {
+                // the set's positions, in order
+                int32_t n = 0;
+#pragma unroll
+                for (int q = 0; q < BM_W; ++q) {
+                    if (q < W && s[q] != 0ull) {
+                        if ((s[q] >> lane()) & 1ull) kl[n + lanes_below(s[q])] = (uint16_t)(q * 64 + lane());
+                        n += popc64(s[q]);
+                    }
+                }
+                wave_sync();
+                x1 = n;
+            } else {
+                x0 = (int64_t)readlane64((uint64_t)px0, pi);
+                x1 = (int64_t)readlane64((uint64_t)px1, pi);
+            }
             for (int64_t xb = x0; xb < x1; xb += WAVE) {
                 const int64_t x = xb + lane();
                 const bool valid = x < x1;
-                const int32_t px = valid ? A.ch.pos[A.lev][x] : 0;
+                int32_t px = 0;
+                if constexpr (MODE == MODE_LAST) px = valid ? (int32_t)kl[x] : 0;
+                else px = valid ? A.ch.pos[A.lev][x] : 0;
                 const uint64_t* row = blk + (uint64_t)px * W;
                 // only the words where the parent's set is non-empty (a
                 // wave-uniform test) are read, in 16-byte pairs
                 uint64_t words[MODE == MODE_WRITE ? BM_W : 1];
-                uint32_t cnt = 0, nzw = 0;
+                uint32_t cnt = 0;
 #pragma unroll
                 for (int q = 0; q < BM_W; q += 2) {
                     const uint64_t s0 = q < W ? s[q] : 0ull, s1 = q + 1 < W ? s[q + 1] : 0ull;
@@ -1085,21 +1130,12 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
                         }
                     }
                     cnt += (uint32_t)(__popcll(w0) + __popcll(w1));
-                    if constexpr (MODE == MODE_COUNT) nzw += ((w0 | w1) != 0ull) ? ((q + 1 < W) ? 2u : 1u) : 0u;
                     if constexpr (MODE == MODE_WRITE) {
                         words[q] = w0;
                         words[q + 1] = w1;
                     }
                 }
-                if (MODE == MODE_COUNT && valid) {
-                    A.count[x] = cnt;
-                    if (A.last_work && cnt) {
-                        lw_par += 1;
-                        lw_set += (uint32_t)W * (uint32_t)A.lev;   // the child's row and its ancestors'
-                        lw_ent += cnt;
-                        lw_row += (uint64_t)cnt * nzw;
-                    }
-                }
+                if (MODE == MODE_COUNT && valid) A.count[x] = cnt;
                 if (MODE == MODE_LAST) acc += cnt;
                 if (MODE == MODE_WRITE) {
                     // children of the wave's entries, entry by entry, each
@@ -1126,13 +1162,12 @@ __global__ __launch_bounds__(CQ_THREADS) void k_clique_mask_level(MaskArgs A) {
                     }
                 }
             }
+            if constexpr (MODE == MODE_LAST) wave_sync();   // the list is read before the next parent's
         }
     }
     if (MODE == MODE_LAST) {
         acc = wave_sum_u64(acc);
         if (lane() == 0 && acc) atomicAdd(&A.stats[0], (unsigned long long)acc);
-    }
-    if (MODE == MODE_COUNT && A.last_work) {
         const uint64_t t_par = wave_sum_u64(lw_par), t_set = wave_sum_u64(lw_set);
         const uint64_t t_ent = wave_sum_u64(lw_ent), t_row = wave_sum_u64(lw_row);
         if (lane() == 0 && t_par) {
@@ -1376,28 +1411,30 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
     A.x_hi = m;
     A.info = X.info;
     A.M = X.M;
-    if (lev == R.k - 2) {
-        launch_mask<MODE_LAST>(R, A, p_lo, p_hi - p_lo, "clique_last", 0.0);
+    if (m <= 0) return;
+    if (lev + 1 == R.k - 2) {
+        // the next level's entries are the last level's inputs: they are never
+        // stored, the last level finds them in the sets of this level's entries
+        A.lev = lev + 1;
+        launch_mask<MODE_LAST>(R, A, 0, m, "clique_last", 0.0);
         return;
     }
-    if (m <= 0) return;
     const size_t mk = ar.mark();
     uint32_t* cnt = push<uint32_t>(ar, m);
     uint64_t* start = push<uint64_t>(ar, m + 1);
     A.count = cnt;
-    A.last_work = (lev + 1 == R.k - 2) ? 1 : 0;
     launch_mask<MODE_COUNT>(R, A, p_lo, p_hi - p_lo, "clique_count_l", (double)m);
-    A.last_work = 0;
     scan_u32(cnt, m, start, ar, R.s);
     const uint64_t total = read_u64(start + m, R.s);
     if (total == 0) {
         ar.reset(mk);
         return;
     }
-    const bool next_last = (lev + 1 == R.k - 2);
-    const uint64_t per = next_last ? 6 : 6 + 4 + 8;
+    // a stored level is extended in turn: its entries (6 B), counts (4 B)
+    // and starts (8 B), twice over for its own children
+    const uint64_t per = 6 + 4 + 8;
     const uint64_t room = g->budget > ar.mark() ? g->budget - ar.mark() : 0;
-    const uint64_t cap = std::max<uint64_t>(room / (per * (next_last ? 1 : 2)), (uint64_t)g->dag.max_out + 1);
+    const uint64_t cap = std::max<uint64_t>(room / (per * 2), (uint64_t)g->dag.max_out + 1);
     const int64_t nb = (int64_t)((total + cap - 1) / cap);
     std::vector<int64_t> hc(nb + 1), hp(nb + 1);
     std::vector<uint64_t> hs(nb + 1);
@@ -1764,12 +1801,10 @@ uint64_t count_cliques(pg_graph* g, int k) {
             if (k >= 5) {
                 // last mask level: per parent its level-1 info (8 B), its
                 // ancestry (idx and pos, 6 B per level) and the words of its
-                // set (8 B each); per entry its pos (2 B) and the row words
-                // read (8 B each)
+                // set (8 B each); per child the row words read (8 B each)
                 const double na = (double)(k - 4);
                 ProfScope pl("clique_last_work", s,
-                             (8.0 + 6.0 * na) * (double)st[8] + 8.0 * (double)st[9] + 2.0 * (double)st[10] +
-                                 8.0 * (double)st[11]);
+                             (8.0 + 6.0 * na) * (double)st[8] + 8.0 * (double)st[9] + 8.0 * (double)st[11]);
             }
         }
     }
