@@ -470,6 +470,8 @@ __device__ __forceinline__ int info_i(uint64_t info) { return (int)((info >> 4) 
 __device__ __forceinline__ uint64_t info_base(uint64_t info) { return info >> 14; }
 
 constexpr int BM_CHUNK = 8;              // most count-pass items a wave takes at once
+constexpr int64_t BM_SMALL_E = int64_t(1) << 20;   // DAG edges below which count-pass items are short
+constexpr int BM_SMALL_ROUND = 16;                 // their level-1 entries per item
 
 struct BmLds {
     int32_t S[CQ_WAVES][BM_MAXD];
@@ -520,7 +522,7 @@ __device__ __forceinline__ uint32_t search_keys(const int32_t* S, int32_t x, int
 }
 
 struct BmArgs {
-    XcdQueue Q;                 // over items[]: (root, round of 64 level-1 entries), highest ranks first
+    XcdQueue Q;                 // over items[]: (root, round of `round` level-1 entries), highest ranks first
     const uint64_t* items;
     const int64_t* rp;          // DAG
     const int32_t* col;
@@ -529,10 +531,12 @@ struct BmArgs {
     uint32_t* count;            // children of each level-1 entry
     uint64_t* info;             // row_info of each level-1 entry
     unsigned long long* stats;  // [3] += out-list entries streamed
+    int round;                  // level-1 entries per item (64 or 16)
 };
 
 // count pass: a work item is one round of 64 level-1 entries of a root r
-// (so no wave holds a heavy root for long), with out(r) staged in LDS.  The
+// (16 on graphs of fewer than 2^20 DAG edges), so no wave holds a heavy
+// root for long, with out(r) staged in LDS.  The
 // wave walks the round's entries in order; for entry i (vertex v = S[i]) all 64 lanes
 // stream out(v) together, BM_UNROLL coalesced loads per lane in flight,
 // and look each candidate up in S[i+1, d) with a branch-free binary search
@@ -639,13 +643,14 @@ __global__ __launch_bounds__(CQ_THREADS, 7) void k_clique_count_masks(BmArgs A) 
             const int32_t d = dr & 0xffff;
             if (d < 2) continue;   // counts are pre-zeroed; rows and infos are never read
             const int W = (d + 63) >> 6;
-            const int32_t xc = (dr >> 16) * WAVE;
+            const int32_t xc = (dr >> 16) * A.round;
+            const int nx = min(A.round, d - xc);
             // out-list bounds of the round's entries, one per lane; the
             // entry's vertex comes from HBM, so these loads fly with the staging
             const int32_t xl = xc + lane();
             int64_t lo = 0;
             int32_t nl = 0;   // out-degree (the DAG has fewer than 2^31 edges)
-            if (xl < d - 1) {
+            if (lane() < nx && xl < d - 1) {
                 const int32_t v = A.col[b + xl];
                 lo = A.rp[v];
                 nl = (int32_t)(A.rp[v + 1] - lo);
@@ -657,7 +662,6 @@ __global__ __launch_bounds__(CQ_THREADS, 7) void k_clique_count_masks(BmArgs A) 
             const uint64_t base = ((uint64_t)(uint32_t)uniform((int32_t)desc.w) << 32) | (uint32_t)uniform((int32_t)desc.z);
             uint64_t* Mr = A.M + base;
             uint32_t mine = 0;
-            const int nx = min(WAVE, d - xc);
             for (int xi = 0; xi < nx; ++xi) {
                 const int32_t x = xc + xi;
                 const int64_t l = (int64_t)readlane64((uint64_t)lo, xi);
@@ -691,7 +695,7 @@ __global__ __launch_bounds__(CQ_THREADS, 7) void k_clique_count_masks(BmArgs A) 
                 if (lane() == xi) mine = c;
                 wave_sync();      // cleared before the next entry's hits
             }
-            if (xl < d) {
+            if (lane() < nx) {
                 A.count[b + xl] = mine;
                 A.info[b + xl] = row_info(base, xl, W);
             }
@@ -1486,7 +1490,7 @@ static void mask_levels(CliqueRun& R, const MaskCtx& X, int lev, MaskChain ch, c
 // The mask path's layout and schedule, built once per graph beside the DAG
 // (they depend on its out-degrees only): each light root's first mask
 // word, the windows of roots for the fused last level, the count pass's
-// work items (rounds of 64 level-1 entries of light roots), and the heavy
+// work items (rounds of 64 or 16 level-1 entries of light roots), and the heavy
 // roots' out-lists as a CSR of their own for the general kernels.
 static void build_mask_plan(pg_graph* g) {
     MaskPlan& P = g->dag.plan;
@@ -1499,7 +1503,10 @@ static void build_mask_plan(pg_graph* g) {
     // none released before the end: four uint32[n] arrays and three
     // uint64[n+1] offset arrays (40 B per root), the items at their bound
     // (round_items' bound), and the scans' tile sums
-    const int64_t cap = E / WAVE + n + 1;
+    // small graphs take rounds of 16 entries, so that the few waves holding
+    // a hub's entries do not serialise the whole pass
+    P.round = (E < BM_SMALL_E) ? BM_SMALL_ROUND : WAVE;
+    const int64_t cap = E / P.round + n + 1;
     Arena ar;
     ar.buf.reserve(sizeof(uint64_t) * (size_t)(9 * (n + 1) + cap + 16 * ((n + 2047) / 2048)) + (size_t(1) << 20));
     P.moff.reserve(sizeof(uint64_t) * (n + 1));
@@ -1538,7 +1545,7 @@ static void build_mask_plan(pg_graph* g) {
         PG_HIP(hipGetLastError());
     }
     uint64_t* items = nullptr;
-    const int64_t m = round_items(lseg, 0, n, WAVE, ar, s, &items, E - e_heavy);
+    const int64_t m = round_items(lseg, 0, n, P.round, ar, s, &items, E - e_heavy);
     P.item.reserve(sizeof(uint64_t) * std::max<int64_t>(m, 1));
     if (m > 0)
         PG_HIP(hipMemcpyAsync(P.item.as<uint64_t>(), items, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
@@ -1650,6 +1657,7 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
         A.count = cnt;
         A.info = info;
         A.stats = R.stats;
+        A.round = P.round;
         if (n_items > 0) {
             ProfScope ps("clique_count", s, (double)E);
             k_clique_count_masks<<<R.blocks, CQ_THREADS, 0, s>>>(A);

@@ -119,10 +119,11 @@ struct MaskPlan {
     bool built = false;
     int64_t words = 0;       // mask words of all light roots
     int64_t items = 0;       // count-pass work items
+    int round = 64;          // level-1 entries per count-pass item (16 on small graphs)
     int64_t windows = 0;     // windows of roots for the fused last level
     int64_t heavy_edges = 0; // DAG edges of heavy roots
     DevBuf moff;             // uint64[n+1]: first mask word of each root (heavy roots: none)
-    DevBuf item;             // uint64[items]: (light root, round of 64 level-1 entries)
+    DevBuf item;             // uint64[items]: (light root, round of `round` level-1 entries)
     DevBuf wfirst;           // int64[windows+1]: first root of each window; wfirst[windows] = n
     DevBuf hrp;              // uint64[n+1]: heavy roots' out-lists in hcol (empty for light roots)
     DevBuf hcol;             // int32[heavy_edges]
