@@ -1056,13 +1056,16 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
                 Wl = info_w(f);
                 bl = info_base(f);
                 const uint64_t* blk = A.M + bl;
+                // a row at a time, its words loaded together
+                const uint64_t* ri = blk + (uint64_t)info_i(f) * Wl;
 #pragma unroll
-                for (int q = 0; q < BM_W; ++q) {
-                    if (q < Wl) {
-                        uint64_t v = blk[(uint64_t)info_i(f) * Wl + q];
-                        for (int a2 = 0; a2 < na; ++a2) v &= blk[(uint64_t)apos[a2] * Wl + q];
-                        sp[q] = v;
-                    }
+                for (int q = 0; q < BM_W; ++q)
+                    if (q < Wl) sp[q] = ri[q];
+                for (int a2 = 0; a2 < na; ++a2) {
+                    const uint64_t* ra = blk + (uint64_t)apos[a2] * Wl;
+#pragma unroll
+                    for (int q = 0; q < BM_W; ++q)
+                        if (q < Wl) sp[q] &= ra[q];
                 }
                 if constexpr (MODE == MODE_LAST) {
                     uint32_t nch = 0, nzw = 0;
@@ -1112,33 +1115,35 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
             for (int64_t xb = x0; xb < x1; xb += WAVE) {
                 const int64_t x = xb + lane();
                 const bool valid = x < x1;
+                // idle lanes take the last entry's row and drop the result,
+                // so the loads below need no per-lane branches
+                const int64_t xs = valid ? x : x1 - 1;
                 int32_t px = 0;
-                if constexpr (MODE == MODE_LAST) px = valid ? (int32_t)kl[x] : 0;
-                else px = valid ? A.ch.pos[A.lev][x] : 0;
+                if constexpr (MODE == MODE_LAST) px = (int32_t)kl[xs];
+                else px = A.ch.pos[A.lev][xs];
                 const uint64_t* row = blk + (uint64_t)px * W;
-                // only the words where the parent's set is non-empty (a
-                // wave-uniform test) are read, in 16-byte pairs
+                // only the pairs of words where the parent's set is non-empty
+                // (a wave-uniform test) are read, 16 bytes each and all in
+                // flight together (the word after an odd-width row's last is
+                // M's next word or its padding, and its set word is zero)
+                ulonglong2 pr[BM_W / 2];
+#pragma unroll
+                for (int q = 0; q < BM_W; q += 2) {
+                    pr[q / 2] = make_ulonglong2(0ull, 0ull);
+                    if ((s[q] | s[q + 1]) != 0ull) pr[q / 2] = *reinterpret_cast<const ulonglong2*>(row + q);
+                }
                 uint64_t words[MODE == MODE_WRITE ? BM_W : 1];
                 uint32_t cnt = 0;
 #pragma unroll
                 for (int q = 0; q < BM_W; q += 2) {
-                    const uint64_t s0 = q < W ? s[q] : 0ull, s1 = q + 1 < W ? s[q + 1] : 0ull;
-                    uint64_t w0 = 0ull, w1 = 0ull;
-                    if ((s0 | s1) != 0ull && valid) {
-                        if (q + 1 < W) {
-                            const ulonglong2 pr = *reinterpret_cast<const ulonglong2*>(row + q);
-                            w0 = s0 & pr.x;
-                            w1 = s1 & pr.y;
-                        } else {
-                            w0 = s0 & row[q];
-                        }
-                    }
+                    const uint64_t w0 = s[q] & pr[q / 2].x, w1 = s[q + 1] & pr[q / 2].y;
                     cnt += (uint32_t)(__popcll(w0) + __popcll(w1));
                     if constexpr (MODE == MODE_WRITE) {
                         words[q] = w0;
                         words[q + 1] = w1;
                     }
                 }
+                if (!valid) cnt = 0;
                 if (MODE == MODE_COUNT && valid) A.count[x] = cnt;
                 if (MODE == MODE_LAST) acc += cnt;
                 if (MODE == MODE_WRITE) {
@@ -1632,7 +1637,8 @@ static uint64_t count_cliques4_masks(pg_graph* g, CliqueRun& R) {
     const MaskPlan& P = g->dag.plan;
     const uint64_t* moff = P.moff.as<uint64_t>();
     const uint64_t mwords = (uint64_t)P.words;
-    uint64_t* M = push<uint64_t>(ar, std::max<uint64_t>(mwords, 1));
+    // two words of padding: the deeper levels read rows in 16-byte pairs
+    uint64_t* M = push<uint64_t>(ar, mwords + 2);
     uint32_t* cnt = push<uint32_t>(ar, E);
     uint64_t* info = push<uint64_t>(ar, E);
     uint64_t* start = push<uint64_t>(ar, E + 1);
