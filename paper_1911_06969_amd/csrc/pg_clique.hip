@@ -1093,7 +1093,7 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
             const uint64_t* blk = A.M + readlane64(bl, pi);
             uint64_t s[BM_W];
 #pragma unroll
-            for (int q = 0; q < BM_W; ++q) s[q] = q < W ? readlane64(sp[q], pi) : 0ull;
+            for (int q = 0; q < BM_W; ++q) s[q] = readlane64(sp[q], pi);   // zero from W on
             int64_t x0 = 0, x1 = 0;
             uint16_t* kl = kids[MODE == MODE_LAST ? threadIdx.x / WAVE : 0];
             if constexpr (MODE == MODE_LAST) {
@@ -1101,7 +1101,7 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
                 int32_t n = 0;
 #pragma unroll
                 for (int q = 0; q < BM_W; ++q) {
-                    if (q < W && s[q] != 0ull) {
+                    if (s[q] != 0ull) {
                         if ((s[q] >> lane()) & 1ull) kl[n + lanes_below(s[q])] = (uint16_t)(q * 64 + lane());
                         n += popc64(s[q]);
                     }
