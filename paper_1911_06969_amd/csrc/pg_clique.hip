@@ -1095,6 +1095,11 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
 #pragma unroll
             for (int q = 0; q < BM_W; ++q) s[q] = readlane64(sp[q], pi);   // zero from W on
             int64_t x0 = 0, x1 = 0;
+            uint32_t acc_p = 0;   // LAST: this parent's count in this lane (at most 12 rounds of 768)
+            // pairs of words where the parent's set is non-empty, one bit each
+            uint32_t nzp = 0;
+#pragma unroll
+            for (int q = 0; q < BM_W; q += 2) nzp |= ((s[q] | s[q + 1]) != 0ull) ? (1u << (q / 2)) : 0u;
             uint16_t* kl = kids[MODE == MODE_LAST ? threadIdx.x / WAVE : 0];
             if constexpr (MODE == MODE_LAST) {
                 // the set's positions, in order
@@ -1130,14 +1135,18 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
 #pragma unroll
                 for (int q = 0; q < BM_W; q += 2) {
                     pr[q / 2] = make_ulonglong2(0ull, 0ull);
-                    if ((s[q] | s[q + 1]) != 0ull) pr[q / 2] = *reinterpret_cast<const ulonglong2*>(row + q);
+                    if ((nzp >> (q / 2)) & 1u) pr[q / 2] = *reinterpret_cast<const ulonglong2*>(row + q);
                 }
                 uint64_t words[MODE == MODE_WRITE ? BM_W : 1];
                 uint32_t cnt = 0;
 #pragma unroll
                 for (int q = 0; q < BM_W; q += 2) {
-                    const uint64_t w0 = s[q] & pr[q / 2].x, w1 = s[q + 1] & pr[q / 2].y;
-                    cnt += (uint32_t)(__popcll(w0) + __popcll(w1));
+                    uint64_t w0 = 0ull, w1 = 0ull;
+                    if ((nzp >> (q / 2)) & 1u) {   // the same uniform test as the loads
+                        w0 = s[q] & pr[q / 2].x;
+                        w1 = s[q + 1] & pr[q / 2].y;
+                        cnt += (uint32_t)(__popcll(w0) + __popcll(w1));
+                    }
                     if constexpr (MODE == MODE_WRITE) {
                         words[q] = w0;
                         words[q + 1] = w1;
@@ -1145,7 +1154,7 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
                 }
                 if (!valid) cnt = 0;
                 if (MODE == MODE_COUNT && valid) A.count[x] = cnt;
-                if (MODE == MODE_LAST) acc += cnt;
+                if (MODE == MODE_LAST) acc_p += cnt;
                 if (MODE == MODE_WRITE) {
                     // children of the wave's entries, entry by entry, each
                     // word compacted by a ballot (coalesced stores)
@@ -1171,7 +1180,10 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
                     }
                 }
             }
-            if constexpr (MODE == MODE_LAST) wave_sync();   // the list is read before the next parent's
+            if constexpr (MODE == MODE_LAST) {
+                acc += acc_p;
+                wave_sync();   // the list is read before the next parent's
+            }
         }
     }
     if (MODE == MODE_LAST) {
