@@ -1092,8 +1092,15 @@ __global__ __launch_bounds__(CQ_THREADS, MODE == MODE_LAST ? 6 : 1) void k_cliqu
             const int W = readlane(Wl, pi);
             const uint64_t* blk = A.M + readlane64(bl, pi);
             uint64_t s[BM_W];
+            // the words below W, a pair at a time (the others are zero)
 #pragma unroll
-            for (int q = 0; q < BM_W; ++q) s[q] = readlane64(sp[q], pi);   // zero from W on
+            for (int q = 0; q < BM_W; q += 2) {
+                s[q] = s[q + 1] = 0ull;
+                if (q < W) {
+                    s[q] = readlane64(sp[q], pi);
+                    s[q + 1] = readlane64(sp[q + 1], pi);
+                }
+            }
             int64_t x0 = 0, x1 = 0;
             uint32_t acc_p = 0;   // LAST: this parent's count in this lane (at most 12 rounds of 768)
             // pairs of words where the parent's set is non-empty, one bit each
