@@ -159,6 +159,28 @@ def test_edge_blocking_same_counts(torch):
     assert gpu_cliques(g, ks, budget=1 << 20) == want
 
 
+def test_deeper_levels_under_a_small_budget(torch):
+    """k = 6 and 7 store the levels up to k - 3 in chunks under a 4 MiB
+    budget; the last mask level then takes each chunk's entries as parents
+    and finds their children in the parents' sets."""
+    g = synth.rmat(12, 16, seed=4)
+    ks = (5, 6, 7)
+    want = [oracle.clique_count(g, k) for k in ks]
+    say("rmat 12 16, k = 5..7 at 4 MiB", want)
+    assert gpu_cliques(g, ks, budget=4 << 20) == want
+
+
+def test_last_mask_level_on_wide_rows(torch):
+    """5-cliques of K_705 and K_769 through the sibling masks: rows of 11
+    and 12 words (the odd width reads the word after a row's last), every
+    pair of words non-empty; against C(n, 5)."""
+    for n in (705, 769):
+        say("K", n, "k = 5")
+        with binding.Graph.from_csr(synth.complete(n)) as G:
+            G.set_option(binding.PG_OPT_CLIQUE_MASKS, 1)
+            assert G.cliques(5) == comb(n, 5)
+
+
 def test_relabel_invariance(torch):
     g = synth.rmat(11, 8, seed=5)
     h = synth.relabel(g, np.random.default_rng(1).permutation(g.n))
