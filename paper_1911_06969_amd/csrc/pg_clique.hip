@@ -458,7 +458,7 @@ static void extend_level(CliqueRun& R, int lev, const int64_t* seg, int64_t seg_
 
 constexpr int BM_MAXD = 768;             // roots with out-degree up to this use masks
 constexpr int BM_W = BM_MAXD / 64;       // 64-bit words per mask row
-constexpr int BM_UNROLL = 3;             // out-list elements per lane per step (double-buffered)
+constexpr int BM_UNROLL = 4;             // out-list elements per lane per step (double-buffered)
 
 // Level-1 entry e = (r, S[i]) is described by one word: the first mask word
 // of r's block, i, and the row width W (words):  base << 14 | i << 4 | W.
@@ -574,10 +574,11 @@ __device__ __forceinline__ uint32_t stream_entry(const int32_t* cp, int64_t left
     };
     // A step is sorted: once the first key of a row of 64 exceeds s_last
     // (or the row is past the list), no key of it or of a later row hits.
-    static_assert(BM_UNROLL == 3, "the row cases below are written out for three rows");
+    static_assert(BM_UNROLL == 4, "the row cases below are written out for four rows");
     auto search = [&](const int32_t (&u)[BM_UNROLL], int32_t lim) {
         auto live = [&](int q) { return q * WAVE < lim && readlane(u[q], 0) <= s_last; };
-        if (live(2)) c += search_keys<LG, 3>(S, x, d, u, row);
+        if (live(3)) c += search_keys<LG, 4>(S, x, d, u, row);
+        else if (live(2)) c += search_keys<LG, 3>(S, x, d, u, row);
         else if (live(1)) c += search_keys<LG, 2>(S, x, d, u, row);
         else if (live(0)) c += search_keys<LG, 1>(S, x, d, u, row);
     };
